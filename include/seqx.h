@@ -1,0 +1,194 @@
+/*
+ * seqx.h -- semiempirical (NDDO) CIS / TDHF excited states on one MI355X (gfx950).
+ *
+ * C ABI of libseqx.  The calls follow the paper's problem statement (PySEQM 2.0,
+ * "Theory and implementation"): atomic numbers, coordinates and method
+ * parameters in; the closed-shell RHF ground state (Eq. 1, F C = C eps with
+ * S = I) built from the NDDO integrals; then the lowest roots of CIS (Eq. 7)
+ * or TDHF/RPA (Eq. 2) by a Davidson iteration whose only large operation is
+ * the matrix-free product of Eqs. 8-9; excitation energies, amplitudes and
+ * oscillator strengths out.
+ *
+ * Conventions shared by every call
+ *  - Status codes only; nothing throws or aborts across the ABI.  On error the
+ *    outputs are untouched and seqx_last_error() describes the failure.
+ *  - Units: Angstrom and eV at the boundary; bohr and hartree inside
+ *    (CODATA 2018: 1 Eh = 27.211386245988 eV, a0 = 0.529177210903 A).
+ *  - Host pointers are owned by the caller and never retained after a call
+ *    returns.  Device pointers (the *_device calls) must be device memory of
+ *    the context's GPU, ordered on the context's stream.
+ *  - AOs: H carries s; C and O carry s, px, py, pz, in input atom order.
+ *  - MOs ascend in eps.  Amplitudes are row-major [root][i][a], i over the
+ *    nocc occupied MOs, a over the nvirt virtual MOs.  Roots ascend in omega;
+ *    each root is signed so its largest |X| element is positive (ties: lowest
+ *    flat index).
+ *  - Results are bitwise reproducible for one device and build (no
+ *    floating-point atomics).
+ *  - A context is not thread-safe; several contexts may coexist.
+ */
+#ifndef SEQX_H
+#define SEQX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SEQX_ABI_VERSION 1
+#define SEQX_NPARAM 11 /* per-element parameters, order below */
+
+typedef struct seqx_ctx seqx_ctx; /* one device + one stream */
+typedef struct seqx_job seqx_job; /* molecules after integrals + SCF; owns their device state */
+
+typedef enum {
+  SEQX_OK = 0,
+  SEQX_E_ARG = 1,         /* bad argument (null pointer, size, enum value)               */
+  SEQX_E_ELEMENT = 2,     /* atomic number without parameters (supported: 1, 6, 8)      */
+  SEQX_E_OPEN_SHELL = 3,  /* odd electron count                                          */
+  SEQX_E_GEOMETRY = 4,    /* non-finite coordinate or two atoms closer than 0.1 Angstrom */
+  SEQX_E_NOMEM = 5,       /* device allocation failed                                    */
+  SEQX_E_DEVICE = 6,      /* HIP / rocSOLVER error, or no usable device                  */
+  SEQX_E_SCF_NOCONV = 7,  /* SCF reached max_iter above tol                              */
+  SEQX_E_DAV_NOCONV = 8,  /* Davidson reached max_iter above tol                         */
+  SEQX_E_UNSTABLE = 9,    /* A-B (or A+B) not positive definite: imaginary TDHF root     */
+  SEQX_E_BUFSIZE = 10,    /* caller buffer too small (see *needed)                       */
+  SEQX_E_STATE = 11       /* call out of order (e.g. results before solve)               */
+} seqx_status;
+
+typedef enum { SEQX_CIS = 0, SEQX_TDHF = 1 } seqx_theory;
+
+/* Arithmetic of the dense MO<->AO transforms inside the sigma build.  Subspace
+ * projection, Gram-Schmidt, the small eigensolves and the SCF stay FP64. */
+typedef enum { SEQX_FP64 = 0, SEQX_FP32 = 1, SEQX_BF16 = 2, SEQX_BF16X3 = 3 } seqx_precision;
+
+typedef enum { SEQX_GUESS_GAP = 0, SEQX_GUESS_LEARNED = 1, SEQX_GUESS_USER = 2 } seqx_guess;
+
+/* Parameter order of one row of seqx_set_params (eV, exponents in 1/bohr):
+ *   zeta_s, zeta_p, U_ss, U_pp, beta_s, beta_p, g_ss, g_sp, g_pp, g_p2, h_sp
+ * Entries that do not apply (p terms of H) are ignored. */
+
+typedef struct {
+  double tol;       /* max |F P - P F| in hartree; <= 0 selects 1e-10 */
+  int32_t max_iter; /* <= 0 selects 300 */
+  int32_t ndiis;    /* DIIS history length; <= 0 selects 8, 1 disables DIIS */
+  int32_t integrals_only; /* nonzero: build ERIs and core Hamiltonian only, no SCF
+                             (seqx_scf_results, seqx_sigma and seqx_solve then return SEQX_E_STATE) */
+} seqx_scf_opts;
+
+typedef struct {
+  int32_t theory;       /* seqx_theory */
+  int32_t nroots;       /* K >= 1, at most nocc*nvirt of the smallest molecule */
+  double tol;           /* residual norm in hartree; <= 0 selects 1e-6 */
+  int32_t max_iter;     /* <= 0 selects 100 */
+  int32_t max_subspace; /* <= 0: derived from mem_budget_bytes, capped at 20 * nroots + 40 */
+  size_t mem_budget_bytes; /* 0: 40 % of free device memory (subspace + sigma scratch) */
+  int32_t precision;    /* seqx_precision of the transforms */
+  int32_t guess;        /* seqx_guess */
+  int32_t n_user_guess; /* SEQX_GUESS_USER: number of host vectors in user_guess */
+  const double* user_guess; /* host [n_user_guess][nocc][nvirt], molecule 0 only */
+} seqx_solve_opts;
+
+typedef struct {
+  int32_t scf_iterations;   /* summed over molecules */
+  int32_t dav_iterations;   /* iterations of the last solve (max over molecules) */
+  int64_t n_sigma;          /* sigma vectors formed in the last solve */
+  double commutator;        /* max |FP-PF| at SCF exit, over molecules */
+  double t_integrals_s;     /* device time of ERI + core Hamiltonian build */
+  double t_scf_s;           /* device time of the SCF */
+  double t_davidson_s;      /* wall time of the last solve, sigma included */
+  double t_sigma_s;         /* device time spent in sigma builds during the last solve */
+  double time_to_roots_s[64]; /* wall time (s) at which each Davidson iteration ended */
+  int32_t n_history;
+  /* Sigma-build phases since the last seqx_solve started (device time from HIP
+   * events on the context stream): 0 C_occ V, 1 (C_occ V) C_virt^T,
+   * 2 NDDO contraction G(R), 3 G C_virt, 4 C_occ^T (G C_virt) + de V.
+   * Flops and bytes are algorithmic (what the operation must do), not counters. */
+  double phase_ms[5];
+  int64_t phase_launches[5];
+  double phase_flops[5];
+  double phase_bytes[5];
+} seqx_stats;
+
+/* Version of this header the library was built with (SEQX_ABI_VERSION). */
+int seqx_abi_version(void);
+
+/* Host-only input check (the same one seqx_prepare runs): Z in {1, 6, 8},
+ * even electron count per molecule, finite coordinates, no two atoms of a
+ * molecule closer than 0.1 Angstrom.  msg (optional, msglen bytes) receives
+ * the reason.  Needs no GPU. */
+seqx_status seqx_validate(int32_t nmol, const int32_t* natoms, const int32_t* Z,
+                          const double* xyz_angstrom, char* msg, size_t msglen);
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to order
+ * all work on (e.g. torch's current stream) or NULL for the null stream.
+ * Returns SEQX_E_DEVICE when no GPU is usable. */
+seqx_status seqx_create(int device, void* hip_stream, seqx_ctx** out);
+void seqx_destroy(seqx_ctx* ctx);
+/* Text of the last error on this context (owned by ctx, valid until the next call). */
+const char* seqx_last_error(const seqx_ctx* ctx);
+
+/* Element parameters: nelem rows of SEQX_NPARAM values for atomic numbers Z[nelem].
+ * The paper runs AM1 for every result; any NDDO parameter set of this form may
+ * be given.  Derived multipole lengths and additive terms are computed here. */
+seqx_status seqx_set_params(seqx_ctx* ctx, int32_t nelem, const int32_t* Z, const double* values);
+
+/* Integrals + RHF SCF for nmol molecules given as concatenated arrays:
+ * natoms[nmol], Z[sum natoms], xyz_angstrom[sum natoms][3].  opts may be NULL.
+ * The job keeps C, eps, the ERI tables and the core Hamiltonian on the device. */
+seqx_status seqx_prepare(seqx_ctx* ctx, int32_t nmol, const int32_t* natoms, const int32_t* Z,
+                         const double* xyz_angstrom, const seqx_scf_opts* opts, seqx_job** out);
+void seqx_job_free(seqx_job* job);
+
+seqx_status seqx_dims(const seqx_job* job, int32_t mol, int32_t* nao, int32_t* nocc, int32_t* nvirt);
+
+/* Ground state of molecule `mol`: eps_eV[nao], C[nao][nao] (row mu = AO, column p = MO),
+ * P[nao][nao] = 2 C_occ C_occ^T.  Any output may be NULL. */
+seqx_status seqx_scf_results(const seqx_job* job, int32_t mol, double* eps_eV, double* C, double* P);
+
+/* Core Hamiltonian H[nao][nao] in hartree (U on the diagonal, core attraction
+ * on atom-diagonal blocks, resonance (beta_mu+beta_nu)/2 S_mu,nu between atoms). */
+seqx_status seqx_core_hamiltonian(const seqx_job* job, int32_t mol, double* H);
+
+/* Packed ERI matrix W[np][np] (hartree), np = sum over atoms of 10 (C, O) or 1 (H):
+ * W[P][Q] = (mu nu | lam sig) with P = (mu <= nu) on one atom and Q = (lam <= sig)
+ * on one atom; pairs of an atom ordered ss, s px, s py, s pz, px px, px py,
+ * px pz, py py, py pz, pz pz; atoms in input order.  Diagonal atom blocks hold
+ * the one-centre integrals.  cap: capacity of out in doubles; *needed = np*np. */
+seqx_status seqx_integrals(const seqx_job* job, int32_t mol, double* out, size_t cap, size_t* needed);
+
+/* Matrix-free products (Eqs. 8-9) for k host vectors V[k][nocc][nvirt]:
+ *   theory CIS : out1 = A V            (out2 unused, may be NULL)
+ *   theory TDHF: out1 = (A+B) V, out2 = (A-B) V
+ * in hartree, with the transforms in `precision`.  Blocking host copy. */
+seqx_status seqx_sigma(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* V,
+                       double* out1, double* out2, int32_t precision);
+/* Same on device buffers (ordered on the context stream, no host sync). */
+seqx_status seqx_sigma_device(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* dV,
+                              double* dout1, double* dout2, int32_t precision);
+
+/* Davidson for every molecule of the job (seqx_solve_opts above). */
+seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts);
+
+/* Results of molecule `mol` after seqx_solve: omega_eV[K], X[K][nocc][nvirt],
+ * Y[K][nocc][nvirt] (zero for CIS), f[K] oscillator strengths,
+ * mu[K][3] transition dipoles (atomic units).  Any output may be NULL. */
+seqx_status seqx_results(const seqx_job* job, int32_t mol, double* omega_eV, double* X, double* Y,
+                         double* f, double* mu);
+
+seqx_status seqx_get_stats(const seqx_job* job, seqx_stats* out);
+
+/* Convergence history of molecule `mol` in the last seqx_solve: per Davidson
+ * iteration, the wall time since the solve started (t_s[it], seconds) and the
+ * K Ritz values (omega_eV[it][K]).  cap: capacity in iterations; *n_iter
+ * receives the iteration count (SEQX_E_BUFSIZE if it exceeds cap; t_s and
+ * omega_eV may be NULL to query it). */
+seqx_status seqx_history(const seqx_job* job, int32_t mol, int32_t cap, int32_t* n_iter, double* t_s,
+                         double* omega_eV);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEQX_H */

@@ -1,0 +1,505 @@
+// C ABI of libseqx (declared in include/seqx.h): context and job lifecycle,
+// host validation, argument marshalling and the error model.  No exception
+// crosses the boundary; every entry point returns a status code.
+#include <chrono>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/seqx.h"
+#include "davidson.hpp"
+#include "integrals.hpp"
+#include "linalg.hpp"
+#include "model.hpp"
+#include "molecule.hpp"
+#include "scf.hpp"
+#include "sigma.hpp"
+
+using namespace seqx;
+
+struct seqx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  Elem elems[kNumSlots];
+  bool have[kNumSlots] = {false, false, false};
+  DBuf<Elem> d_elems;
+  std::unique_ptr<DenseSolver> ds;
+};
+
+struct seqx_job {
+  seqx_ctx* ctx = nullptr;
+  std::vector<std::unique_ptr<DeviceMolecule>> mols;
+  GWork gw;
+  ScfWork sw;
+  DavWork dw;
+  seqx_stats stats{};
+  bool solved = false;
+};
+
+namespace {
+
+thread_local std::string g_noctx_err;
+
+template <class F>
+seqx_status guarded(seqx_ctx* ctx, F&& f) {
+  try {
+    if (ctx) SEQX_HIP(hipSetDevice(ctx->device));
+    f();
+    if (ctx) ctx->err.clear();
+    return SEQX_OK;
+  } catch (const Error& e) {
+    (ctx ? ctx->err : g_noctx_err) = e.what();
+    return static_cast<seqx_status>(e.status);
+  } catch (const std::bad_alloc&) {
+    (ctx ? ctx->err : g_noctx_err) = "host allocation failed";
+    return SEQX_E_NOMEM;
+  } catch (const std::exception& e) {
+    (ctx ? ctx->err : g_noctx_err) = e.what();
+    return SEQX_E_DEVICE;
+  }
+}
+
+template <class T>
+void h2d(DBuf<T>& d, const std::vector<T>& h, hipStream_t st) {
+  d.alloc(h.size());
+  if (!h.empty()) SEQX_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+template <class T>
+void d2h(T* dst, const T* src, size_t n, hipStream_t st) {
+  if (n) SEQX_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, st));
+}
+
+DeviceMolecule& mol_of(const seqx_job* job, int32_t mol) {
+  if (!job) throw Error(kEArg, "job is NULL");
+  if (mol < 0 || mol >= static_cast<int>(job->mols.size())) throw Error(kEArg, "molecule index out of range");
+  return *job->mols[mol];
+}
+
+DeviceMolecule& scf_mol_of(const seqx_job* job, int32_t mol) {
+  DeviceMolecule& m = mol_of(job, mol);
+  if (!m.scf_done) throw Error(kEState, "job was prepared with integrals_only: no ground state");
+  return m;
+}
+
+void setup_molecule(seqx_ctx* ctx, DeviceMolecule& m, int natoms, const int32_t* Z, const double* xyz) {
+  hipStream_t st = ctx->stream;
+  m.L = make_layout(natoms, Z, xyz, ctx->elems);
+  const Layout& L = m.L;
+  m.natoms = L.natoms;
+  m.nheavy = L.nheavy;
+  m.nao = L.nao;
+  m.nocc = L.nocc;
+  m.nvirt = L.nvirt;
+  m.np = L.np;
+  m.elems = ctx->d_elems.p;
+  h2d(m.slot, L.slot, st);
+  h2d(m.ao_off, L.ao_off, st);
+  h2d(m.pi_off, L.pi_off, st);
+  h2d(m.xyz, L.xyz, st);
+  std::vector<int2> pr[3];
+  for (int A = 0; A < natoms; ++A)
+    for (int B = A + 1; B < natoms; ++B) {
+      const int g = (B < L.nheavy) ? 0 : (A < L.nheavy ? 1 : 2);
+      pr[g].push_back(make_int2(A, B));
+    }
+  for (int g = 0; g < 3; ++g) {
+    m.npairs[g] = static_cast<int>(pr[g].size());
+    h2d(m.pairs[g], pr[g], st);
+  }
+  std::vector<int> pmu(L.np), pnu(L.np), aoa(L.nao);
+  for (int A = 0; A < natoms; ++A) {
+    const int o = L.ao_off[A], na = L.ao_off[A + 1] - o, po = L.pi_off[A];
+    for (int i = 0; i < na; ++i) aoa[o + i] = A;
+    if (na == 1) {
+      pmu[po] = o;
+      pnu[po] = o;
+    } else {
+      for (int P = 0; P < 10; ++P) {
+        pmu[po + P] = o + pair_first(P);
+        pnu[po + P] = o + pair_second(P);
+      }
+    }
+  }
+  h2d(m.pi_mu, pmu, st);
+  h2d(m.pi_nu, pnu, st);
+  h2d(m.atom_of_ao, aoa, st);
+  m.W.alloc(static_cast<size_t>(L.np) * L.np);
+  m.H.alloc(static_cast<size_t>(L.nao) * L.nao);
+}
+
+// permute a square internal-order matrix into input order
+void unpermute_square(const std::vector<double>& in, int n, const std::vector<int>& map, double* out) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[static_cast<size_t>(map[i]) * n + map[j]] = in[static_cast<size_t>(i) * n + j];
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  SEQX_HIP(hipEventElapsedTime(&ms, a, b));
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+int seqx_abi_version(void) { return SEQX_ABI_VERSION; }
+
+seqx_status seqx_validate(int32_t nmol, const int32_t* natoms, const int32_t* Z, const double* xyz, char* msg,
+                          size_t msglen) {
+  try {
+    validate_molecules(nmol, natoms, Z, xyz);
+    if (msg && msglen) msg[0] = 0;
+    return SEQX_OK;
+  } catch (const Error& e) {
+    if (msg && msglen) {
+      std::strncpy(msg, e.what(), msglen - 1);
+      msg[msglen - 1] = 0;
+    }
+    return static_cast<seqx_status>(e.status);
+  }
+}
+
+seqx_status seqx_create(int device, void* hip_stream, seqx_ctx** out) {
+  if (!out) return SEQX_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    g_noctx_err = "no HIP device available";
+    return SEQX_E_DEVICE;
+  }
+  if (device < 0 || device >= count) {
+    g_noctx_err = "device index out of range";
+    return SEQX_E_ARG;
+  }
+  std::unique_ptr<seqx_ctx> ctx(new seqx_ctx());
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  const seqx_status s = guarded(ctx.get(), [&] {
+    ctx->d_elems.alloc(kNumSlots);
+    ctx->ds.reset(new DenseSolver(ctx->stream));
+  });
+  if (s != SEQX_OK) {
+    g_noctx_err = ctx->err;
+    return s;
+  }
+  *out = ctx.release();
+  return SEQX_OK;
+}
+
+void seqx_destroy(seqx_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+const char* seqx_last_error(const seqx_ctx* ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
+
+seqx_status seqx_set_params(seqx_ctx* ctx, int32_t nelem, const int32_t* Z, const double* values) {
+  if (!ctx) return SEQX_E_ARG;
+  return guarded(ctx, [&] {
+    if (nelem <= 0 || !Z || !values) throw Error(kEArg, "nelem must be > 0 and arrays non-null");
+    for (int i = 0; i < nelem; ++i) {
+      const int s = element_slot(Z[i]);
+      if (s < 0) throw Error(kEElement, "unsupported element Z=" + std::to_string(Z[i]));
+      const double* v = values + static_cast<size_t>(i) * SEQX_NPARAM;
+      const int need = Z[i] == 1 ? 1 : SEQX_NPARAM;
+      for (int k = 0; k < need; ++k)
+        if (!std::isfinite(v[k])) throw Error(kEArg, "non-finite parameter");
+      if (v[0] <= 0 || (Z[i] != 1 && v[1] <= 0)) throw Error(kEArg, "orbital exponents must be positive");
+      if (v[6] <= 0 || (Z[i] != 1 && (v[10] <= 0 || v[8] <= v[9])))
+        throw Error(kEArg, "one-centre parameters need g_ss > 0, h_sp > 0 and g_pp > g_p2");
+      ctx->elems[s] = make_elem(Z[i], v);
+      ctx->have[s] = true;
+    }
+    SEQX_HIP(hipMemcpyAsync(ctx->d_elems.p, ctx->elems, sizeof(ctx->elems), hipMemcpyHostToDevice, ctx->stream));
+    SEQX_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+seqx_status seqx_prepare(seqx_ctx* ctx, int32_t nmol, const int32_t* natoms, const int32_t* Z, const double* xyz,
+                         const seqx_scf_opts* opts, seqx_job** out) {
+  if (!ctx || !out) return SEQX_E_ARG;
+  *out = nullptr;
+  std::unique_ptr<seqx_job> job(new seqx_job());
+  job->ctx = ctx;
+  const seqx_status s = guarded(ctx, [&] {
+    validate_molecules(nmol, natoms, Z, xyz);
+    size_t off = 0;
+    for (int m = 0; m < nmol; ++m) {
+      for (int a = 0; a < natoms[m]; ++a)
+        if (!ctx->have[element_slot(Z[off + a])])
+          throw Error(kEElement, "no parameters loaded for Z=" + std::to_string(Z[off + a]));
+      off += natoms[m];
+    }
+    ScfOptions so;
+    bool integrals_only = false;
+    if (opts) {
+      if (opts->tol > 0) so.tol = opts->tol;
+      if (opts->max_iter > 0) so.max_iter = opts->max_iter;
+      if (opts->ndiis > 0) so.ndiis = opts->ndiis;
+      integrals_only = opts->integrals_only != 0;
+    }
+    hipStream_t st = ctx->stream;
+    hipEvent_t e[3];
+    for (auto& ev : e) SEQX_HIP(hipEventCreate(&ev));
+    off = 0;
+    double t_int = 0, t_scf = 0;
+    try {
+      for (int m = 0; m < nmol; ++m) {
+        std::unique_ptr<DeviceMolecule> dm(new DeviceMolecule());
+        setup_molecule(ctx, *dm, natoms[m], Z + off, xyz + 3 * off);
+        SEQX_HIP(hipEventRecord(e[0], st));
+        build_integrals(*dm, st);
+        SEQX_HIP(hipEventRecord(e[1], st));
+        if (!integrals_only) run_scf(*dm, so, *ctx->ds, job->gw, job->sw, st);
+        dm->scf_done = !integrals_only;
+        SEQX_HIP(hipEventRecord(e[2], st));
+        SEQX_HIP(hipStreamSynchronize(st));
+        t_int += elapsed_ms(e[0], e[1]);
+        t_scf += elapsed_ms(e[1], e[2]);
+        job->stats.scf_iterations += dm->scf_iterations;
+        job->stats.commutator = std::max(job->stats.commutator, dm->commutator);
+        job->mols.push_back(std::move(dm));
+        off += natoms[m];
+      }
+    } catch (...) {
+      for (auto& ev : e) (void)hipEventDestroy(ev);
+      throw;
+    }
+    for (auto& ev : e) (void)hipEventDestroy(ev);
+    job->stats.t_integrals_s = t_int * 1e-3;
+    job->stats.t_scf_s = t_scf * 1e-3;
+  });
+  if (s != SEQX_OK) return s;
+  *out = job.release();
+  return SEQX_OK;
+}
+
+void seqx_job_free(seqx_job* job) {
+  if (!job) return;
+  (void)hipSetDevice(job->ctx->device);
+  (void)hipStreamSynchronize(job->ctx->stream);
+  delete job;
+}
+
+seqx_status seqx_dims(const seqx_job* job, int32_t mol, int32_t* nao, int32_t* nocc, int32_t* nvirt) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = mol_of(job, mol);
+    if (nao) *nao = m.nao;
+    if (nocc) *nocc = m.nocc;
+    if (nvirt) *nvirt = m.nvirt;
+  });
+}
+
+seqx_status seqx_scf_results(const seqx_job* job, int32_t mol, double* eps_eV, double* C, double* P) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = scf_mol_of(job, mol);
+    hipStream_t st = job->ctx->stream;
+    const int n = m.nao;
+    std::vector<double> e(n), c, p;
+    d2h(e.data(), m.eps.p, n, st);
+    if (C) {
+      c.resize(static_cast<size_t>(n) * n);
+      d2h(c.data(), m.C.p, c.size(), st);
+    }
+    if (P) {
+      p.resize(static_cast<size_t>(n) * n);
+      d2h(p.data(), m.P.p, p.size(), st);
+    }
+    SEQX_HIP(hipStreamSynchronize(st));
+    if (eps_eV)
+      for (int i = 0; i < n; ++i) eps_eV[i] = e[i] * kHartreeEV;
+    if (C)  // rows are AOs (permute), columns are MOs (unchanged)
+      for (int mu = 0; mu < n; ++mu)
+        for (int q = 0; q < n; ++q) C[static_cast<size_t>(m.L.ao_user[mu]) * n + q] = c[static_cast<size_t>(mu) * n + q];
+    if (P) unpermute_square(p, n, m.L.ao_user, P);
+  });
+}
+
+seqx_status seqx_core_hamiltonian(const seqx_job* job, int32_t mol, double* H) {
+  if (!job || !H) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = mol_of(job, mol);
+    const int n = m.nao;
+    std::vector<double> h(static_cast<size_t>(n) * n);
+    d2h(h.data(), m.H.p, h.size(), job->ctx->stream);
+    SEQX_HIP(hipStreamSynchronize(job->ctx->stream));
+    unpermute_square(h, n, m.L.ao_user, H);
+  });
+}
+
+seqx_status seqx_integrals(const seqx_job* job, int32_t mol, double* out, size_t cap, size_t* needed) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = mol_of(job, mol);
+    const size_t need = static_cast<size_t>(m.np) * m.np;
+    if (needed) *needed = need;
+    if (!out) return;
+    if (cap < need) throw Error(kEBufSize, "integral buffer too small");
+    std::vector<double> w(need);
+    d2h(w.data(), m.W.p, need, job->ctx->stream);
+    SEQX_HIP(hipStreamSynchronize(job->ctx->stream));
+    unpermute_square(w, m.np, m.L.pi_user, out);
+  });
+}
+
+seqx_status seqx_sigma_device(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* dV, double* dout1,
+                              double* dout2, int32_t precision) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    DeviceMolecule& m = scf_mol_of(job, mol);
+    if (theory != SEQX_CIS && theory != SEQX_TDHF) throw Error(kEArg, "theory must be CIS or TDHF");
+    if (k <= 0 || !dV || !dout1 || (theory == SEQX_TDHF && !dout2)) throw Error(kEArg, "bad sigma arguments");
+    if (precision != SEQX_FP64) throw Error(kEArg, "only SEQX_FP64 transforms are available in this build");
+    sigma_build(m, theory, k, dV, dout1, dout2, job->dw.sig, job->ctx->stream);
+  });
+}
+
+seqx_status seqx_sigma(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* V, double* out1,
+                       double* out2, int32_t precision) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    DeviceMolecule& m = scf_mol_of(job, mol);
+    if (theory != SEQX_CIS && theory != SEQX_TDHF) throw Error(kEArg, "theory must be CIS or TDHF");
+    if (k <= 0 || !V || !out1 || (theory == SEQX_TDHF && !out2)) throw Error(kEArg, "bad sigma arguments");
+    if (precision != SEQX_FP64) throw Error(kEArg, "only SEQX_FP64 transforms are available in this build");
+    hipStream_t st = job->ctx->stream;
+    const size_t n = static_cast<size_t>(k) * m.nocc * m.nvirt;
+    DBuf<double> dV(n), d1(n), d2(theory == SEQX_TDHF ? n : 0);
+    SEQX_HIP(hipMemcpyAsync(dV.p, V, n * sizeof(double), hipMemcpyHostToDevice, st));
+    sigma_build(m, theory, k, dV.p, d1.p, d2.p, job->dw.sig, st);
+    d2h(out1, d1.p, n, st);
+    if (theory == SEQX_TDHF) d2h(out2, d2.p, n, st);
+    SEQX_HIP(hipStreamSynchronize(st));
+  });
+}
+
+seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
+  if (!job || !opts) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    if (opts->theory != SEQX_CIS && opts->theory != SEQX_TDHF) throw Error(kEArg, "theory must be CIS or TDHF");
+    if (opts->precision != SEQX_FP64) throw Error(kEArg, "only SEQX_FP64 transforms are available in this build");
+    if (opts->guess == SEQX_GUESS_LEARNED) throw Error(kEArg, "learned guess needs a loaded network");
+    hipStream_t st = job->ctx->stream;
+    DavOptions d;
+    d.theory = opts->theory;
+    d.nroots = opts->nroots;
+    d.tol = opts->tol > 0 ? opts->tol : 1e-6;
+    d.max_iter = opts->max_iter > 0 ? opts->max_iter : 100;
+    d.max_sub = opts->max_subspace;
+    DBuf<double> guess;
+    job->solved = false;
+    job->stats.n_sigma = 0;
+    job->dw.sig.timer.reset();
+    job->stats.dav_iterations = 0;
+    job->stats.t_sigma_s = 0;
+    job->stats.n_history = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (size_t mi = 0; mi < job->mols.size(); ++mi) {
+      DeviceMolecule& m = scf_mol_of(job, static_cast<int32_t>(mi));
+      const long nov = static_cast<long>(m.nocc) * m.nvirt;
+      if (opts->nroots < 1 || opts->nroots > nov) throw Error(kEArg, "nroots must be in [1, nocc*nvirt]");
+      if (opts->guess == SEQX_GUESS_USER && mi == 0) {
+        if (!opts->user_guess || opts->n_user_guess < 1) throw Error(kEArg, "user guess missing");
+        guess.alloc(static_cast<size_t>(opts->n_user_guess) * nov);
+        SEQX_HIP(hipMemcpyAsync(guess.p, opts->user_guess, guess.n * sizeof(double), hipMemcpyHostToDevice, st));
+        d.guess = guess.p;
+        d.nguess = opts->n_user_guess;
+      } else {
+        d.guess = nullptr;
+        d.nguess = 0;
+      }
+      // subspace cap from the memory budget: V, (A+B)V, (A-B)V rows of nov doubles
+      if (d.max_sub <= 0) {
+        size_t budget = opts->mem_budget_bytes;
+        if (budget == 0) {
+          size_t fr = 0, tot = 0;
+          SEQX_HIP(hipMemGetInfo(&fr, &tot));
+          budget = fr * 2 / 5;
+        }
+        const size_t per = static_cast<size_t>(opts->theory == SEQX_TDHF ? 3 : 2) * nov * sizeof(double);
+        const long cap_mem = static_cast<long>(budget / std::max<size_t>(per, 1));
+        d.max_sub = static_cast<int>(std::max<long>(std::min<long>(cap_mem, 20L * opts->nroots + 40), 1));
+      }
+      DavResult r = davidson(m, d, *job->ctx->ds, job->dw, st);
+      m.hist_t = r.t_iter;
+      m.hist_omega.clear();
+      for (const auto& w : r.omega_iter) m.hist_omega.insert(m.hist_omega.end(), w.begin(), w.end());
+      job->stats.n_sigma += r.n_sigma;
+      job->stats.dav_iterations = std::max(job->stats.dav_iterations, r.iterations);
+      job->stats.t_sigma_s += r.t_sigma_ms * 1e-3;
+      if (mi == 0) {
+        const int nh = std::min<int>(static_cast<int>(r.t_iter.size()), 64);
+        job->stats.n_history = nh;
+        for (int i = 0; i < nh; ++i) job->stats.time_to_roots_s[i] = r.t_iter[i];
+      }
+    }
+    job->stats.t_davidson_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    job->solved = true;
+  });
+}
+
+seqx_status seqx_results(const seqx_job* job, int32_t mol, double* omega_eV, double* X, double* Y, double* f,
+                         double* mu) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = mol_of(job, mol);
+    if (!job->solved || m.nroots == 0) throw Error(kEState, "no results: call seqx_solve first");
+    hipStream_t st = job->ctx->stream;
+    const int K = m.nroots;
+    const size_t nx = static_cast<size_t>(K) * m.nocc * m.nvirt;
+    std::vector<double> om(K);
+    d2h(om.data(), m.omega.p, K, st);
+    if (X) d2h(X, m.X.p, nx, st);
+    if (Y) d2h(Y, m.Y.p, nx, st);
+    if (f) d2h(f, m.f.p, K, st);
+    if (mu) d2h(mu, m.mu.p, 3 * static_cast<size_t>(K), st);
+    SEQX_HIP(hipStreamSynchronize(st));
+    if (omega_eV)
+      for (int j = 0; j < K; ++j) omega_eV[j] = om[j] * kHartreeEV;
+  });
+}
+
+seqx_status seqx_history(const seqx_job* job, int32_t mol, int32_t cap, int32_t* n_iter, double* t_s,
+                         double* omega_eV) {
+  if (!job || !n_iter) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = mol_of(job, mol);
+    if (!job->solved || m.nroots == 0) throw Error(kEState, "no history: call seqx_solve first");
+    const int n = static_cast<int>(m.hist_t.size());
+    *n_iter = n;
+    if (!t_s && !omega_eV) return;
+    if (n > cap) throw Error(kEBufSize, "history longer than cap");
+    for (int i = 0; i < n; ++i) {
+      if (t_s) t_s[i] = m.hist_t[i];
+      if (omega_eV)
+        for (int j = 0; j < m.nroots; ++j)
+          omega_eV[static_cast<size_t>(i) * m.nroots + j] = m.hist_omega[static_cast<size_t>(i) * m.nroots + j] * kHartreeEV;
+    }
+  });
+}
+
+seqx_status seqx_get_stats(const seqx_job* job, seqx_stats* out) {
+  if (!job || !out) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    // fold in sigma builds still pending on the stream (waits for them)
+    PhaseTimer& t = const_cast<seqx_job*>(job)->dw.sig.timer;
+    t.resolve();
+    *out = job->stats;
+    for (int p = 0; p < kNumPhases; ++p) {
+      out->phase_ms[p] = t.ms[p];
+      out->phase_launches[p] = t.launches[p];
+      out->phase_flops[p] = t.flops[p];
+      out->phase_bytes[p] = t.bytes[p];
+    }
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,550 @@
+// Davidson iteration for CIS (Eq. 7) and TDHF (Eq. 2) on one GPU.
+//
+// The paper's outline (GPU-implementation subsection): start from orthonormal
+// trial vectors; form the matrix-vector products; project and diagonalise;
+// Ritz vectors and residuals; precondition only the unconverged residuals with
+// the diagonal; orthonormalise against the basis and append.  The subspace is
+// capped (the paper derives the cap from free memory) and collapses onto the
+// current best Ritz vectors when full.
+//
+// TDHF uses one orthonormal basis V for X+Y and X-Y: M+ = V^T (A+B) V and
+// M- = V^T (A-B) V; with M- = L L^T, (L^T M+ L) z = w^2 z, t = L z / sqrt(w),
+// u = M+ t / w, so that t^T u = 1 (X^T X - Y^T Y = 1).  Residuals:
+// r_T = (A+B) T - w U, r_U = (A-B) U - w T.  New directions per unconverged
+// root: (r_T + r_U)/(w - d) and (r_T - r_U)/(-w - d), d = eps_a - eps_i.
+// Orthonormalisation: unit rows, classical Gram-Schmidt twice against V,
+// then symmetric (Loewdin) orthonormalisation inside the new block with
+// near-dependent directions dropped.  All subspace arithmetic is FP64.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+#include "davidson.hpp"
+#include "gemm.hpp"
+#include "sigma.hpp"
+
+namespace seqx {
+
+namespace {
+
+__global__ void gap_kernel(int o, int v, const double* __restrict__ eps, double* __restrict__ d) {
+  const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (x >= static_cast<long>(o) * v) return;
+  const int i = static_cast<int>(x / v), a = static_cast<int>(x % v);
+  d[x] = eps[o + a] - eps[i];
+}
+
+// smallest ng gaps (ties: lowest flat index i*v + a).  Any of them has i among
+// the ng highest occupied and a among the ng lowest virtual orbitals.
+__global__ void gap_guess_kernel(int o, int v, int ng, const double* __restrict__ eps, int* __restrict__ idx) {
+  const int i0 = max(0, o - ng), ni = o - i0, na = min(v, ng);
+  const int N = ni * na;
+  for (int q = threadIdx.x; q < N; q += blockDim.x) {
+    const int i = i0 + q / na, a = q % na;
+    const double g = eps[o + a] - eps[i];
+    const int f = i * v + a;
+    int rank = 0;
+    for (int q2 = 0; q2 < N; ++q2) {
+      const int i2 = i0 + q2 / na, a2 = q2 % na;
+      const double g2 = eps[o + a2] - eps[i2];
+      const int f2 = i2 * v + a2;
+      if (g2 < g || (g2 == g && f2 < f)) ++rank;
+    }
+    if (rank < ng) idx[rank] = f;
+  }
+}
+
+__global__ void unit_vectors_kernel(int ng, long nov, const int* __restrict__ idx, double* __restrict__ V) {
+  const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  const int r = blockIdx.y;
+  if (x >= nov) return;
+  V[r * nov + x] = (x == idx[r]) ? 1.0 : 0.0;
+}
+
+// column-major M: new columns t in [S0, S1) are filled for rows [0, S1);
+// mirror them into rows and symmetrise the new-new block
+__global__ void sym_fill_kernel(double* M, int ld, int S0, int S1) {
+  const int t = S0 + blockIdx.y;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S1; s += gridDim.x * blockDim.x) {
+    if (s < S0) {
+      M[static_cast<long>(s) * ld + t] = M[static_cast<long>(t) * ld + s];
+    } else if (s < t) {
+      const double a = 0.5 * (M[static_cast<long>(t) * ld + s] + M[static_cast<long>(s) * ld + t]);
+      M[static_cast<long>(t) * ld + s] = a;
+      M[static_cast<long>(s) * ld + t] = a;
+    }
+  }
+}
+
+__global__ void omega_kernel(int K, const double* __restrict__ w2, double* __restrict__ om, int tdhf) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < K) om[j] = tdhf ? sqrt(fmax(w2[j], 0.0)) : w2[j];
+}
+
+// C[:, j] *= om[j]^(-p) for j < K (column-major, nrows rows)
+__global__ void scale_cols_kernel(double* C, int ld, int nrows, int K, const double* __restrict__ om, double p) {
+  const int j = blockIdx.x;
+  const double s = pow(om[j], -p);
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) C[static_cast<long>(j) * ld + r] *= s;
+}
+
+// residual norms^2, partial sums per block: TDHF r_T = PT - w U, r_U = MU - w T;
+// CIS r = PT - w T
+__global__ void residual_norm_kernel(long nov, int tdhf, const double* __restrict__ om, const double* __restrict__ Tv,
+                                     const double* __restrict__ Uv, const double* __restrict__ PT,
+                                     const double* __restrict__ MU, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int j = blockIdx.y;
+  const double w = om[j];
+  const long base = static_cast<long>(j) * nov;
+  double s = 0.0;
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < nov; x += 256L * gridDim.x) {
+    if (tdhf) {
+      const double rT = PT[base + x] - w * Uv[base + x];
+      const double rU = MU[base + x] - w * Tv[base + x];
+      s += rT * rT + rU * rU;
+    } else {
+      const double r = PT[base + x] - w * Tv[base + x];
+      s += r * r;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[static_cast<long>(j) * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void reduce_rows_kernel(int K, int nb, const double* __restrict__ part, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= K) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[static_cast<long>(j) * nb + b];
+  out[j] = sqrt(s);
+}
+
+__device__ inline double guard(double x) {
+  return fabs(x) < 1e-8 ? (x < 0 ? -1e-8 : 1e-8) : x;
+}
+
+__global__ void precond_kernel(long nov, int tdhf, const int* __restrict__ sel, const double* __restrict__ om,
+                               const double* __restrict__ d, const double* __restrict__ Tv,
+                               const double* __restrict__ Uv, const double* __restrict__ PT,
+                               const double* __restrict__ MU, double* __restrict__ W) {
+  const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (x >= nov) return;
+  const int q = blockIdx.y;
+  const int j = sel[q];
+  const double w = om[j];
+  const long b = static_cast<long>(j) * nov + x;
+  if (tdhf) {
+    const double rT = PT[b] - w * Uv[b];
+    const double rU = MU[b] - w * Tv[b];
+    W[(2L * q) * nov + x] = (rT + rU) / guard(w - d[x]);
+    W[(2L * q + 1) * nov + x] = (rT - rU) / guard(-w - d[x]);
+  } else {
+    const double r = PT[b] - w * Tv[b];
+    W[static_cast<long>(q) * nov + x] = r / guard(w - d[x]);
+  }
+}
+
+__global__ void scale_rows_kernel(long nov, double* __restrict__ W, const double* __restrict__ G, int ldg) {
+  const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  const int r = blockIdx.y;
+  if (x >= nov) return;
+  const double g = G[static_cast<long>(r) * ldg + r];
+  W[r * nov + x] *= (g > 0.0) ? 1.0 / sqrt(g) : 0.0;
+}
+
+__global__ void invsqrt_cols_kernel(double* Q, int ld, int nrows, int j0, const double* __restrict__ lam) {
+  const int j = j0 + blockIdx.x;
+  const double s = 1.0 / sqrt(lam[j]);
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) Q[static_cast<long>(j) * ld + r] *= s;
+}
+
+__global__ void finalize_kernel(long nov, int tdhf, const double* __restrict__ Tv, const double* __restrict__ Uv,
+                                double* __restrict__ X, double* __restrict__ Y) {
+  const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= nov) return;
+  const long b = static_cast<long>(j) * nov + x;
+  if (tdhf) {
+    X[b] = 0.5 * (Tv[b] + Uv[b]);
+    Y[b] = 0.5 * (Tv[b] - Uv[b]);
+  } else {
+    X[b] = Tv[b];
+    Y[b] = 0.0;
+  }
+}
+
+// flip root j so that its largest |X| element (lowest index on ties) is positive
+__global__ void sign_fix_kernel(long nov, double* __restrict__ X, double* __restrict__ Y) {
+  __shared__ double bv[256];
+  __shared__ long bi[256];
+  const int j = blockIdx.x;
+  double* x = X + static_cast<long>(j) * nov;
+  double best = -1.0;
+  long bidx = 0;
+  for (long t = threadIdx.x; t < nov; t += 256) {
+    const double a = fabs(x[t]);
+    if (a > best) {  // strided scan visits indices in increasing order
+      best = a;
+      bidx = t;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const double a = bv[threadIdx.x + h];
+      const long ia = bi[threadIdx.x + h];
+      if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ia < bi[threadIdx.x])) {
+        bv[threadIdx.x] = a;
+        bi[threadIdx.x] = ia;
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = x[bi[0]] < 0.0;
+  __syncthreads();
+  if (flip) {
+    double* y = Y + static_cast<long>(j) * nov;
+    for (long t = threadIdx.x; t < nov; t += 256) {
+      x[t] = -x[t];
+      y[t] = -y[t];
+    }
+  }
+}
+
+// transition dipoles mu_j = sqrt(2) sum_mn T_mn <m|r|n> with the ZDO dipole
+// (R_A on the diagonal, D1_A between s and p_k of one atom) and
+// f_j = 2/3 w_j |mu_j|^2
+__global__ void dipole_kernel(int natoms, int n, const double* __restrict__ T, const int* __restrict__ slot,
+                              const int* __restrict__ ao_off, const double* __restrict__ xyz,
+                              const Elem* __restrict__ elems, const double* __restrict__ om, double* __restrict__ mu,
+                              double* __restrict__ f) {
+  __shared__ double red[3][256];
+  const int j = blockIdx.x;
+  const double* Tj = T + static_cast<long>(j) * n * n;
+  double s[3] = {0, 0, 0};
+  for (int A = threadIdx.x; A < natoms; A += 256) {
+    const Elem e = elems[slot[A]];
+    const int o = ao_off[A];
+    double tr = 0.0;
+    for (int i = 0; i < e.nao; ++i) tr += Tj[static_cast<long>(o + i) * n + o + i];
+    for (int c = 0; c < 3; ++c) {
+      s[c] += tr * xyz[3 * A + c];
+      if (e.nao == 4)
+        s[c] += e.D1 * (Tj[static_cast<long>(o) * n + o + 1 + c] + Tj[static_cast<long>(o + 1 + c) * n + o]);
+    }
+  }
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double m2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double v = sqrt(2.0) * red[c][0];
+      mu[3 * j + c] = v;
+      m2 += v * v;
+    }
+    f[j] = 2.0 / 3.0 * om[j] * m2;
+  }
+}
+
+template <class T>
+void d2h(T* dst, const T* src, size_t n, hipStream_t st) {
+  SEQX_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, st));
+}
+
+// per-iteration JSON lines on stderr when SEQX_LOG is set to a non-empty value other than 0
+bool log_enabled() {
+  static const bool on = [] {
+    const char* s = std::getenv("SEQX_LOG");
+    return s && *s && std::strcmp(s, "0") != 0;
+  }();
+  return on;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Orthonormalise the nc rows of Wc against V[0:S] and among themselves, append
+// the kept directions at V[S:]; returns how many were kept.
+int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov, int nc, double* Wc, int S,
+                          double* V, int max_keep) {
+  double* G = w.G.p;
+  double* Cc = w.Q.p;  // nc x S coefficients, reused below for the Loewdin vectors
+  dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(ceil_div(nov, 256), nc), dim3(256), 0, st, nov, Wc, G, nc);
+  SEQX_LAUNCH_CHECK();
+  if (S > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      dots(st, nc, Wc, nov, S, V, nov, nov, Cc, S, w.ws.p);
+      dgemm(st, false, false, nc, static_cast<int>(nov), S, -1.0, Cc, S, 0, V, nov, 0, 1.0, Wc, nov, 0, 1, nullptr);
+    }
+  }
+  dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
+  ds.eigh(nc, G, nc, w.w2.p);
+  std::vector<double> lam(nc);
+  d2h(lam.data(), w.w2.p, nc, st);
+  SEQX_HIP(hipStreamSynchronize(st));
+  int j0 = 0;
+  while (j0 < nc && !(lam[j0] > 1e-12)) ++j0;
+  int kept = nc - j0;
+  if (kept > max_keep) {
+    j0 = nc - max_keep;
+    kept = max_keep;
+  }
+  if (kept <= 0) return 0;
+  hipLaunchKernelGGL(invsqrt_cols_kernel, dim3(kept), dim3(64), 0, st, G, nc, nc, j0, w.w2.p);
+  SEQX_LAUNCH_CHECK();
+  // V[S + r] = sum_c Q(c, j0 + r) W_c
+  dgemm(st, false, false, kept, static_cast<int>(nov), nc, 1.0, G + static_cast<long>(j0) * nc, nc, 0, Wc, nov, 0,
+        0.0, V + static_cast<long>(S) * nov, nov, 0, 1, nullptr);
+  return kept;
+}
+
+}  // namespace
+
+DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, DavWork& w, hipStream_t st) {
+  const int o = m.nocc, v = m.nvirt, K = opt.nroots;
+  const long nov = static_cast<long>(o) * v;
+  const bool tdhf = opt.theory == 1;
+  if (K < 1 || K > nov) throw Error(kEArg, "nroots must be in [1, nocc*nvirt]");
+  int Smax = opt.max_sub > 0 ? opt.max_sub : 20 * K + 40;
+  Smax = static_cast<int>(std::min<long>(Smax, nov));
+  const int ncand_max = tdhf ? 2 * K : K;
+  Smax = std::max(Smax, std::min<int>(static_cast<int>(nov), 2 * K + ncand_max));
+  const int ng = opt.guess ? opt.nguess : static_cast<int>(std::min<long>(nov, 2L * K));
+  if (ng < 1 || ng > Smax) throw Error(kEArg, "guess size out of range");
+  DavResult res;
+  const double t0 = now_s();
+
+  w.V.ensure(static_cast<size_t>(Smax) * nov);
+  w.SP.ensure(static_cast<size_t>(Smax) * nov);
+  if (tdhf) w.SM.ensure(static_cast<size_t>(Smax) * nov);
+  w.Mp.ensure(static_cast<size_t>(Smax) * Smax);
+  w.Mm.ensure(static_cast<size_t>(Smax) * Smax);
+  w.Lm.ensure(static_cast<size_t>(Smax) * Smax);
+  w.Tmp.ensure(static_cast<size_t>(Smax) * Smax);
+  w.Hs.ensure(static_cast<size_t>(Smax) * Smax);
+  w.w2.ensure(Smax);
+  w.coef.ensure(static_cast<size_t>(Smax) * 2 * K);
+  for (DBuf<double>* b : {&w.Tv, &w.Uv, &w.PT, &w.MU}) b->ensure(static_cast<size_t>(K) * nov);
+  w.W.ensure(static_cast<size_t>(std::max(ncand_max, opt.guess ? opt.nguess : 0)) * nov);
+  w.scratch.ensure(static_cast<size_t>(2 * K) * nov);
+  w.G.ensure(static_cast<size_t>(Smax) * Smax);
+  w.Q.ensure(static_cast<size_t>(std::max(ncand_max, 2 * K)) * Smax);
+  w.ws.ensure(std::max<size_t>(dots_workspace(Smax, Smax, nov), 4096));
+  w.d.ensure(nov);
+  w.rn.ensure(2 * K);
+  const int nbres = static_cast<int>(std::min<long>(256, ceil_div(nov, 256)));
+  w.part.ensure(static_cast<size_t>(K) * nbres);
+  w.idx.ensure(std::max(ng, 1));
+  w.sel.ensure(K);
+  m.omega.ensure(K);
+  m.X.ensure(static_cast<size_t>(K) * nov);
+  m.Y.ensure(static_cast<size_t>(K) * nov);
+  m.f.ensure(K);
+  m.mu.ensure(3 * K);
+  double* om = w.rn.p + K;  // omega of the current iteration (hartree)
+
+  hipLaunchKernelGGL(gap_kernel, dim3(ceil_div(nov, 256)), dim3(256), 0, st, o, v, m.eps.p, w.d.p);
+  int S = 0, knew = 0;
+  if (opt.guess) {
+    copy(st, w.W.p, opt.guess, static_cast<long>(opt.nguess) * nov);
+    knew = orthonormalize_append(st, ds, w, nov, opt.nguess, w.W.p, 0, w.V.p, Smax);
+    if (knew == 0) throw Error(kEArg, "user guess vectors are linearly dependent or zero");
+  } else {
+    hipLaunchKernelGGL(gap_guess_kernel, dim3(1), dim3(1024), 0, st, o, v, ng, m.eps.p, w.idx.p);
+    hipLaunchKernelGGL(unit_vectors_kernel, dim3(ceil_div(nov, 256), ng), dim3(256), 0, st, ng, nov, w.idx.p, w.V.p);
+    SEQX_LAUNCH_CHECK();
+    knew = ng;
+  }
+
+  std::vector<double> h_om(K), h_rn(K);
+  std::vector<int> sel;
+  hipEvent_t e0, e1;
+  SEQX_HIP(hipEventCreate(&e0));
+  SEQX_HIP(hipEventCreate(&e1));
+  bool converged = false;
+  int it = 0;
+  try {
+    for (it = 1; it <= opt.max_iter; ++it) {
+      // 1. products of the new vectors
+      SEQX_HIP(hipEventRecord(e0, st));
+      sigma_build(m, opt.theory, knew, w.V.p + S * nov, w.SP.p + S * nov, tdhf ? w.SM.p + S * nov : nullptr, w.sig,
+                  st, opt.sigma_chunk);
+      SEQX_HIP(hipEventRecord(e1, st));
+      res.n_sigma += knew;
+      const int S1 = S + knew;
+      // 2. projected matrices, new columns (column-major, ld = Smax)
+      dots(st, knew, w.SP.p + S * nov, nov, S1, w.V.p, nov, nov, w.Mp.p + static_cast<long>(S) * Smax, Smax, w.ws.p);
+      hipLaunchKernelGGL(sym_fill_kernel, dim3(ceil_div(S1, 256), knew), dim3(256), 0, st, w.Mp.p, Smax, S, S1);
+      if (tdhf) {
+        dots(st, knew, w.SM.p + S * nov, nov, S1, w.V.p, nov, nov, w.Mm.p + static_cast<long>(S) * Smax, Smax,
+             w.ws.p);
+        hipLaunchKernelGGL(sym_fill_kernel, dim3(ceil_div(S1, 256), knew), dim3(256), 0, st, w.Mm.p, Smax, S, S1);
+      }
+      SEQX_LAUNCH_CHECK();
+      S = S1;
+      // 3. subspace eigenproblem
+      double* tco = w.coef.p;                          // t (TDHF) or x (CIS): S x K, ld Smax
+      double* uco = w.coef.p + static_cast<long>(K) * Smax;  // u (TDHF)
+      if (tdhf) {
+        copy(st, w.Lm.p, w.Mm.p, static_cast<long>(S) * Smax);
+        ds.potrf(S, w.Lm.p, Smax);
+        zero_upper_cm(st, S, w.Lm.p, Smax);
+        dgemm_cm(st, false, false, S, S, S, 1.0, w.Mp.p, Smax, w.Lm.p, Smax, 0.0, w.Tmp.p, Smax);  // M+ L
+        dgemm_cm(st, true, false, S, S, S, 1.0, w.Lm.p, Smax, w.Tmp.p, Smax, 0.0, w.Hs.p, Smax);    // L^T M+ L
+        ds.eigh(S, w.Hs.p, Smax, w.w2.p);
+        hipLaunchKernelGGL(omega_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, w.w2.p, om, 1);
+        dgemm_cm(st, false, false, S, K, S, 1.0, w.Lm.p, Smax, w.Hs.p, Smax, 0.0, tco, Smax);   // L z
+        dgemm_cm(st, false, false, S, K, S, 1.0, w.Tmp.p, Smax, w.Hs.p, Smax, 0.0, uco, Smax);  // M+ L z
+        hipLaunchKernelGGL(scale_cols_kernel, dim3(K), dim3(256), 0, st, tco, Smax, S, K, om, 0.5);
+        hipLaunchKernelGGL(scale_cols_kernel, dim3(K), dim3(256), 0, st, uco, Smax, S, K, om, 1.5);
+      } else {
+        copy(st, w.Hs.p, w.Mp.p, static_cast<long>(S) * Smax);
+        ds.eigh(S, w.Hs.p, Smax, w.w2.p);
+        hipLaunchKernelGGL(omega_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, w.w2.p, om, 0);
+        copy(st, tco, w.Hs.p, static_cast<long>(K) * Smax);
+      }
+      SEQX_LAUNCH_CHECK();
+      // 4. Ritz vectors and products: rows j of Tv = sum_s t(s, j) V_s, etc.
+      dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.V.p, nov, 0, 0.0, w.Tv.p, nov, 0, 1,
+            nullptr);
+      dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.SP.p, nov, 0, 0.0, w.PT.p, nov, 0, 1,
+            nullptr);
+      if (tdhf) {
+        dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, uco, Smax, 0, w.V.p, nov, 0, 0.0, w.Uv.p, nov, 0, 1,
+              nullptr);
+        dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, uco, Smax, 0, w.SM.p, nov, 0, 0.0, w.MU.p, nov, 0,
+              1, nullptr);
+      }
+      // 5. residual norms
+      hipLaunchKernelGGL(residual_norm_kernel, dim3(nbres, K), dim3(256), 0, st, nov, tdhf ? 1 : 0, om, w.Tv.p,
+                         w.Uv.p, w.PT.p, w.MU.p, w.part.p);
+      hipLaunchKernelGGL(reduce_rows_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, nbres, w.part.p, w.rn.p);
+      SEQX_LAUNCH_CHECK();
+      d2h(h_rn.data(), w.rn.p, K, st);
+      d2h(h_om.data(), om, K, st);
+      SEQX_HIP(hipStreamSynchronize(st));
+      float ms = 0.f;
+      SEQX_HIP(hipEventElapsedTime(&ms, e0, e1));
+      res.t_sigma_ms += ms;
+      if (tdhf && ds.info_potrf() != 0)
+        throw Error(kEUnstable, "A-B projected matrix not positive definite (unstable reference)");
+      if (ds.info_eigh() != 0) throw Error(kEDevice, "subspace eigensolver failed");
+      res.t_iter.push_back(now_s() - t0);
+      res.omega_iter.push_back(h_om);
+      if (log_enabled()) {
+        double rmax = 0.0;
+        for (double r : h_rn) rmax = std::max(rmax, r);
+        std::fprintf(stderr,
+                     "{\"davidson_iter\": %d, \"subspace\": %d, \"new\": %d, \"max_residual\": %.3e, "
+                     "\"omega0_eV\": %.9f, \"omegaK_eV\": %.9f, \"t_s\": %.4f}\n",
+                     it, S, knew, rmax, h_om[0] * kHartreeEV, h_om[K - 1] * kHartreeEV, res.t_iter.back());
+      }
+      sel.clear();
+      for (int j = 0; j < K; ++j) {
+        if (!std::isfinite(h_rn[j]) || !std::isfinite(h_om[j])) throw Error(kEDavNoConv, "Davidson produced NaN");
+        if (h_rn[j] > opt.tol) sel.push_back(j);
+      }
+      if (sel.empty()) {
+        converged = true;
+        break;
+      }
+      if (it == opt.max_iter) break;
+      // 6. preconditioned residuals of the unconverged roots
+      const int nsel = static_cast<int>(sel.size());
+      SEQX_HIP(hipMemcpyAsync(w.sel.p, sel.data(), nsel * sizeof(int), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(precond_kernel, dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov, tdhf ? 1 : 0,
+                         w.sel.p, om, w.d.p, w.Tv.p, w.Uv.p, w.PT.p, w.MU.p, w.W.p);
+      SEQX_LAUNCH_CHECK();
+      const int nc = tdhf ? 2 * nsel : nsel;
+      // 7. collapse onto the best Ritz vectors when the basis would overflow
+      if (S + nc > Smax) {
+        const int q0 = tdhf ? 2 * K : std::min(2 * K, S);
+        // coefficient block Cc (S x q0) = [t u] (TDHF) or the q0 lowest eigenvectors (CIS)
+        double* Cc = w.Q.p;
+        if (tdhf) {
+          copy(st, Cc, tco, static_cast<long>(2 * K) * Smax);  // t and u are adjacent columns
+        } else {
+          copy(st, Cc, w.Hs.p, static_cast<long>(q0) * Smax);
+        }
+        // orthonormal columns: Q = Cc Qg diag(lam^-1/2) over the kept eigenpairs of Cc^T Cc
+        dgemm_cm(st, true, false, q0, q0, S, 1.0, Cc, Smax, Cc, Smax, 0.0, w.G.p, q0);
+        ds.eigh(q0, w.G.p, q0, w.w2.p);
+        std::vector<double> lam(q0);
+        d2h(lam.data(), w.w2.p, q0, st);
+        SEQX_HIP(hipStreamSynchronize(st));
+        int j0 = 0;
+        while (j0 < q0 && !(lam[j0] > 1e-12 * lam[q0 - 1])) ++j0;
+        const int q = q0 - j0;
+        hipLaunchKernelGGL(invsqrt_cols_kernel, dim3(q), dim3(64), 0, st, w.G.p, q0, q0, j0, w.w2.p);
+        dgemm_cm(st, false, false, S, q, q0, 1.0, Cc, Smax, w.G.p + static_cast<long>(j0) * q0, q0, 0.0, w.Lm.p,
+                 Smax);  // Qc (S x q) in Lm
+        double* Qc = w.Lm.p;
+        for (double* B : {w.V.p, w.SP.p, tdhf ? w.SM.p : nullptr}) {
+          if (!B) continue;
+          dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, B, nov, 0, 0.0, w.scratch.p, nov, 0,
+                1, nullptr);
+          copy(st, B, w.scratch.p, static_cast<long>(q) * nov);
+        }
+        for (double* Mx : {w.Mp.p, tdhf ? w.Mm.p : nullptr}) {
+          if (!Mx) continue;
+          dgemm_cm(st, false, false, S, q, S, 1.0, Mx, Smax, Qc, Smax, 0.0, w.Tmp.p, Smax);
+          dgemm_cm(st, true, false, q, q, S, 1.0, Qc, Smax, w.Tmp.p, Smax, 0.0, w.Hs.p, Smax);
+          copy(st, Mx, w.Hs.p, static_cast<long>(q) * Smax);
+        }
+        S = q;
+      }
+      // 8. orthonormalise and append
+      knew = orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V.p, Smax - S);
+      if (knew == 0) break;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  res.iterations = it;
+  if (!converged) throw Error(kEDavNoConv, "Davidson did not converge in " + std::to_string(opt.max_iter) + " iterations");
+
+  // 9. amplitudes, sign convention, properties
+  copy(st, m.omega.p, om, K);
+  hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(nov, 256), K), dim3(256), 0, st, nov, tdhf ? 1 : 0, w.Tv.p,
+                     w.Uv.p, m.X.p, m.Y.p);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3(K), dim3(256), 0, st, nov, m.X.p, m.Y.p);
+  SEQX_LAUNCH_CHECK();
+  // transition densities of X + Y (T for TDHF, X for CIS)
+  const long nn = static_cast<long>(m.nao) * m.nao;
+  w.scratch.ensure(std::max<size_t>(static_cast<size_t>(2 * K) * nov, static_cast<size_t>(K) * nn));
+  copy(st, w.Tv.p, m.X.p, K * nov);
+  axpby(st, K * nov, 1.0, m.Y.p, 1.0, w.Tv.p);
+  forward_transform(m, K, w.Tv.p, w.scratch.p, w.sig, st);
+  hipLaunchKernelGGL(dipole_kernel, dim3(K), dim3(256), 0, st, m.natoms, m.nao, w.scratch.p, m.slot.p, m.ao_off.p,
+                     m.xyz.p, m.elems, m.omega.p, m.mu.p, m.f.p);
+  SEQX_LAUNCH_CHECK();
+  SEQX_HIP(hipStreamSynchronize(st));
+  m.nroots = K;
+  m.theory = opt.theory;
+  m.dav_iterations = it;
+  m.n_sigma = res.n_sigma;
+  return res;
+}
+
+}  // namespace seqx

@@ -1,0 +1,41 @@
+// Davidson iteration for CIS and TDHF on the device.
+#pragma once
+
+#include <vector>
+
+#include "linalg.hpp"
+#include "molecule.hpp"
+#include "sigma.hpp"
+
+namespace seqx {
+
+struct DavOptions {
+  int theory = 1;      // 0 CIS, 1 TDHF
+  int nroots = 1;
+  double tol = 1e-6;   // residual norm (hartree)
+  int max_iter = 100;
+  int max_sub = 0;     // subspace cap (vectors)
+  int sigma_chunk = 32;
+  const double* guess = nullptr;  // device [nguess][nov] (user / learned guess), or null for the gap guess
+  int nguess = 0;
+};
+
+struct DavWork {
+  DBuf<double> V, SP, SM, Mp, Mm, Lm, Tmp, Hs, w2, coef, Tv, Uv, PT, MU, W, G, Q, scratch, ws, d, rn, part;
+  DBuf<int> idx, sel;
+  SigmaWork sig;
+};
+
+struct DavResult {
+  int iterations = 0;
+  long n_sigma = 0;
+  double t_sigma_ms = 0.0;
+  std::vector<double> t_iter;                 // wall seconds at the end of each iteration
+  std::vector<std::vector<double>> omega_iter;  // Ritz values (hartree) per iteration
+};
+
+// Lowest roots of molecule m; fills m.omega, m.X, m.Y, m.f, m.mu.
+// Throws Error(kEDavNoConv) / Error(kEUnstable) on failure.
+DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, DavWork& w, hipStream_t st);
+
+}  // namespace seqx

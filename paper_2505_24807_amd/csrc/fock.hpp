@@ -1,0 +1,26 @@
+// NDDO contraction of AO densities with the ERI tables (Fock-like build).
+#pragma once
+
+#include "molecule.hpp"
+
+namespace seqx {
+
+// For k AO matrices R_I (row-major n x n, stride sR) with symmetric part
+// S = (R + R^T)/2 and antisymmetric part D = (R - R^T)/2, with
+//   J(X)_mn = sum_ls (mn|ls) X_ls,   K(X)_mn = sum_ls (ml|ns) X_ls,
+// write (every element of every output):
+//   kTwo   : F1 = cJ J(S) + cK K(S),   F2 = cKa K(D)
+//   kSum   : F1 = cJ J(S) + cK K(S) + cKa K(D)
+//   kSymm  : F1 = cJ J(S) + cK K(S)          (R symmetric, SCF)
+// J lives on atom-diagonal blocks; K has one-centre terms on diagonal blocks
+// and the two-centre term on every off-diagonal block.
+enum GMode { kTwo = 0, kSum = 1, kSymm = 2 };
+
+struct GWork {
+  DBuf<double> r, J;  // packed densities [k][np] and Coulomb [np][k]
+};
+
+void build_G(const DeviceMolecule& m, int k, const double* R, long sR, double* F1, double* F2, long sF, GMode mode,
+             double cJ, double cK, double cKa, GWork& w, hipStream_t st);
+
+}  // namespace seqx

@@ -1,0 +1,39 @@
+// Dense FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64), batched.
+#pragma once
+
+#include "common.hpp"
+
+namespace seqx {
+
+// Epilogue of the sigma back-transform: C[b][i][a] += (eps[nocc + a] - eps[i]) * V[b % kv][i][a]
+struct SigmaEpilogue {
+  const double* eps = nullptr;
+  int nocc = 0;
+  const double* V = nullptr;
+  long strideV = 0;
+  int kv = 1;
+};
+
+// Row-major semantics:  C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]
+//   op(A) is M x K: ta == false -> A[i*lda + k];  ta == true -> A[k*lda + i]
+//   op(B) is K x N: tb == false -> B[k*ldb + j];  tb == true -> B[j*ldb + k]
+// Batch b adds b*sA, b*sB, b*sC to the base pointers.  `skinny` selects a
+// 64 x 16 block tile for N <= 16 problems.  epi (optional) adds the sigma
+// diagonal term after the product.
+void dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda, long sA,
+           const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC, int batch = 1,
+           const SigmaEpilogue* epi = nullptr);
+
+// Column-major (BLAS) semantics for small subspace matrices:
+//   C = alpha * op(A) op(B) + beta * C, op(A) M x K, op(B) K x N, column-major.
+void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,
+              const double* B, long ldb, double beta, double* C, long ldc);
+
+// Split-K inner products out[s*ldo + t] = sum_x X[s*ldx + x] * Y[t*ldy + x]
+// for s < ns, t < nt, over x < len; fixed-order reduction (deterministic).
+// ws must hold dots_workspace(ns, nt, len) doubles.
+size_t dots_workspace(int ns, int nt, long len);
+void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len, double* out,
+          long ldo, double* ws);
+
+}  // namespace seqx

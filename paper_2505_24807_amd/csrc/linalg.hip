@@ -1,0 +1,228 @@
+// Small device kernels and the rocSOLVER wrapper.
+#include <rocsolver/rocsolver.h>
+
+#include "linalg.hpp"
+
+namespace seqx {
+
+#define SEQX_RB(call)                                                                                   \
+  do {                                                                                                  \
+    rocblas_status s_ = (call);                                                                         \
+    if (s_ != rocblas_status_success)                                                                   \
+      throw ::seqx::Error(::seqx::kEDevice, std::string(#call) + ": rocblas status " + std::to_string(s_)); \
+  } while (0)
+
+DenseSolver::DenseSolver(hipStream_t st) : st_(st) {
+  SEQX_RB(rocblas_create_handle(&h_));
+  SEQX_RB(rocblas_set_stream(h_, st_));
+  info_.alloc(2);
+}
+
+DenseSolver::~DenseSolver() {
+  if (h_) rocblas_destroy_handle(h_);
+}
+
+void DenseSolver::eigh(int n, double* A, int lda, double* w) {
+  work_.ensure(static_cast<size_t>(n));
+  SEQX_RB(rocsolver_dsyevd(h_, rocblas_evect_original, rocblas_fill_lower, n, A, lda, w, work_.p, info_.p));
+}
+
+void DenseSolver::potrf(int n, double* A, int lda) {
+  SEQX_RB(rocsolver_dpotrf(h_, rocblas_fill_lower, n, A, lda, info_.p + 1));
+}
+
+int DenseSolver::info_eigh() {
+  int v = 0;
+  SEQX_HIP(hipMemcpyAsync(&v, info_.p, sizeof(int), hipMemcpyDeviceToHost, st_));
+  SEQX_HIP(hipStreamSynchronize(st_));
+  return v;
+}
+
+int DenseSolver::info_potrf() {
+  int v = 0;
+  SEQX_HIP(hipMemcpyAsync(&v, info_.p + 1, sizeof(int), hipMemcpyDeviceToHost, st_));
+  SEQX_HIP(hipStreamSynchronize(st_));
+  return v;
+}
+
+namespace {
+
+__global__ void fill_kernel(double* x, long n, double v) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+__global__ void axpby_kernel(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void transpose_kernel(int rows, int cols, const double* __restrict__ src, long lds, double* __restrict__ dst,
+                                 long ldd) {
+  __shared__ double tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int r = r0 + j, c = c0 + threadIdx.x;
+    if (r < rows && c < cols) tile[j][threadIdx.x] = src[static_cast<long>(r) * lds + c];
+  }
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
+    const int c = c0 + j, r = r0 + threadIdx.x;
+    if (r < rows && c < cols) dst[static_cast<long>(c) * ldd + r] = tile[threadIdx.x][j];
+  }
+}
+
+__global__ void max_abs_stage1(long n, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += 256L * gridDim.x) m = fmax(m, fabs(x[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void max_abs_stage2(int nb, const double* __restrict__ part, double* out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) m = fmax(m, part[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void antisym_kernel(int n, const double* __restrict__ X, double* __restrict__ E) {
+  const long idx = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<long>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  E[idx] = X[idx] - X[static_cast<long>(j) * n + i];
+}
+
+__global__ void zero_upper_kernel(int n, double* A, int lda) {
+  const int j = blockIdx.x;  // column
+  for (int i = threadIdx.x; i < j; i += blockDim.x) A[static_cast<long>(j) * lda + i] = 0.0;
+}
+
+__global__ void guess_density_kernel(int nao, const int* __restrict__ atom_of_ao, const int* __restrict__ slot,
+                                     const Elem* __restrict__ elems, double* __restrict__ P) {
+  const long idx = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<long>(nao) * nao) return;
+  const int i = static_cast<int>(idx / nao), j = static_cast<int>(idx % nao);
+  double v = 0.0;
+  if (i == j) {
+    const Elem& e = elems[slot[atom_of_ao[i]]];
+    v = e.core / e.nao;
+  }
+  P[idx] = v;
+}
+
+// Pulay DIIS: minimise |sum c_i e_i| subject to sum c_i = 1.  Gaussian
+// elimination with partial pivoting on the bordered (m+1) system.
+__global__ void diis_kernel(int m, const double* __restrict__ B, int ldb, double* __restrict__ c) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a[17][18];
+  const int n = m + 1;
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) a[i][j] = B[i * ldb + j];
+    a[i][m] = -1.0;
+    a[i][n] = 0.0;
+  }
+  for (int j = 0; j < m; ++j) a[m][j] = -1.0;
+  a[m][m] = 0.0;
+  a[m][n] = -1.0;
+  // scale the error block for conditioning
+  double sc = 0.0;
+  for (int i = 0; i < m; ++i) sc = fmax(sc, fabs(a[i][i]));
+  if (sc > 0)
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) a[i][j] /= sc;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+    if (piv != col)
+      for (int j = 0; j <= n; ++j) {
+        const double t = a[col][j];
+        a[col][j] = a[piv][j];
+        a[piv][j] = t;
+      }
+    const double d = a[col][col];
+    if (d == 0.0) {
+      // singular: fall back to the newest matrix only
+      for (int i = 0; i < m; ++i) c[i] = (i == m - 1) ? 1.0 : 0.0;
+      return;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = a[r][col] / d;
+      for (int j = col; j <= n; ++j) a[r][j] -= f * a[col][j];
+    }
+  }
+  for (int i = 0; i < m; ++i) c[i] = a[i][n] / a[i][i];
+}
+
+}  // namespace
+
+void fill(hipStream_t st, double* x, long n, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, x, n, v);
+  SEQX_LAUNCH_CHECK();
+}
+
+void copy(hipStream_t st, double* dst, const double* src, long n) {
+  if (n <= 0) return;
+  SEQX_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+
+void transpose(hipStream_t st, int rows, int cols, const double* src, long lds, double* dst, long ldd) {
+  hipLaunchKernelGGL(transpose_kernel, dim3(ceil_div(cols, 32), ceil_div(rows, 32)), dim3(32, 8), 0, st, rows, cols,
+                     src, lds, dst, ldd);
+  SEQX_LAUNCH_CHECK();
+}
+
+void axpby(hipStream_t st, long n, double a, const double* x, double b, double* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, a, x, b, y);
+  SEQX_LAUNCH_CHECK();
+}
+
+void max_abs(hipStream_t st, long n, const double* x, double* out, double* ws) {
+  const int nb = static_cast<int>(std::min<long>(1024, ceil_div(n, 256)));
+  hipLaunchKernelGGL(max_abs_stage1, dim3(nb), dim3(256), 0, st, n, x, ws);
+  hipLaunchKernelGGL(max_abs_stage2, dim3(1), dim3(256), 0, st, nb, ws, out);
+  SEQX_LAUNCH_CHECK();
+}
+
+void antisym(hipStream_t st, int n, const double* X, double* E) {
+  const long nn = static_cast<long>(n) * n;
+  hipLaunchKernelGGL(antisym_kernel, dim3(ceil_div(nn, 256)), dim3(256), 0, st, n, X, E);
+  SEQX_LAUNCH_CHECK();
+}
+
+void zero_upper_cm(hipStream_t st, int n, double* A, int lda) {
+  if (n <= 1) return;
+  hipLaunchKernelGGL(zero_upper_kernel, dim3(n), dim3(64), 0, st, n, A, lda);
+  SEQX_LAUNCH_CHECK();
+}
+
+void guess_density(hipStream_t st, int nao, const int* atom_of_ao, const int* slot, const void* elems, double* P) {
+  const long nn = static_cast<long>(nao) * nao;
+  hipLaunchKernelGGL(guess_density_kernel, dim3(ceil_div(nn, 256)), dim3(256), 0, st, nao, atom_of_ao, slot,
+                     static_cast<const Elem*>(elems), P);
+  SEQX_LAUNCH_CHECK();
+}
+
+void diis_coefficients(hipStream_t st, int m, const double* B, int ldb, double* c) {
+  if (m > 16) throw Error(kEArg, "DIIS history longer than 16");
+  hipLaunchKernelGGL(diis_kernel, dim3(1), dim3(64), 0, st, m, B, ldb, c);
+  SEQX_LAUNCH_CHECK();
+}
+
+}  // namespace seqx

@@ -1,0 +1,50 @@
+// Small device kernels and the dense eigensolver wrapper used by the SCF and
+// the Davidson iteration.
+#pragma once
+
+#include <rocblas/rocblas.h>
+
+#include "common.hpp"
+
+namespace seqx {
+
+// Dense symmetric eigensolver / Cholesky on the device (rocSOLVER), FP64,
+// column-major storage.  One instance per context stream.
+class DenseSolver {
+ public:
+  explicit DenseSolver(hipStream_t st);
+  ~DenseSolver();
+  DenseSolver(const DenseSolver&) = delete;
+  DenseSolver& operator=(const DenseSolver&) = delete;
+  // eigenvalues ascending into w[n]; eigenvectors overwrite A (columns)
+  void eigh(int n, double* A, int lda, double* w);
+  // lower Cholesky factor in place; returns false when not positive definite
+  void potrf(int n, double* A, int lda);
+  // device info word of the last eigh / potrf calls (0 = success); synchronises
+  int info_eigh();
+  int info_potrf();
+
+ private:
+  rocblas_handle h_ = nullptr;
+  hipStream_t st_;
+  DBuf<double> work_;
+  DBuf<int> info_;
+};
+
+// elementwise / reduction helpers (all ordered on `st`)
+void fill(hipStream_t st, double* x, long n, double v);
+void copy(hipStream_t st, double* dst, const double* src, long n);
+void transpose(hipStream_t st, int rows, int cols, const double* src, long lds, double* dst, long ldd);
+// y = a*x + b*y
+void axpby(hipStream_t st, long n, double a, const double* x, double b, double* y);
+// out = max |x| (deterministic two-stage reduction); ws >= 1024 doubles
+void max_abs(hipStream_t st, long n, const double* x, double* out, double* ws);
+// E = X - X^T for a square n x n row-major X (commutator from F P)
+void antisym(hipStream_t st, int n, const double* X, double* E);
+void zero_upper_cm(hipStream_t st, int n, double* A, int lda);
+// diagonal guess density: each atom's core charge spread over its AOs
+void guess_density(hipStream_t st, int nao, const int* atom_of_ao, const int* slot, const void* elems, double* P);
+// solve the (m+1) x (m+1) DIIS system for m coefficients, B (m x m, ld) given; single thread
+void diis_coefficients(hipStream_t st, int m, const double* B, int ldb, double* c);
+
+}  // namespace seqx

@@ -1,0 +1,126 @@
+// Matrix-free products of Eqs. 8-9 (paper, GPU-implementation subsection).
+//
+//   R_I   = C_o V_I C_v^T                     two MFMA GEMMs (n x o x v, n x v x n)
+//   F_I   = G(R_I)                            NDDO contraction (fock.hip)
+//   out_I = C_o^T F_I C_v + de o V_I          two MFMA GEMMs, de added in the epilogue
+// Singlet CIS:  F = 2 J(R) - K(R).  TDHF:  (A+B) <-> 4 J(S) - 2 K(S) and
+// (A-B) <-> -2 K(D) with S, D the symmetric / antisymmetric parts of R: A V
+// pairs with K(R) and B V with K(R^T), which gives exactly these combinations.
+#include "gemm.hpp"
+#include "sigma.hpp"
+
+namespace seqx {
+
+void PhaseTimer::reset() {
+  resolve();
+  for (int p = 0; p < kNumPhases; ++p) {
+    ms[p] = flops[p] = bytes[p] = 0.0;
+    launches[p] = 0;
+  }
+}
+
+void PhaseTimer::resolve() {
+  for (size_t c = 0; c < pending.size(); ++c) {
+    auto& ev = pending[c];
+    SEQX_HIP(hipEventSynchronize(ev[kNumPhases]));
+    for (int p = 0; p < kNumPhases; ++p) {
+      float t = 0.f;
+      SEQX_HIP(hipEventElapsedTime(&t, ev[p], ev[p + 1]));
+      ms[p] += t;
+      flops[p] += pending_flops[c][p];
+      bytes[p] += pending_bytes[c][p];
+      launches[p] += pending_launches[c][p];
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  pending.clear();
+  pending_flops.clear();
+  pending_bytes.clear();
+  pending_launches.clear();
+}
+
+PhaseTimer::~PhaseTimer() {
+  for (auto& ev : pending)
+    for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
+void forward_transform(const DeviceMolecule& m, int k, const double* X, double* T, SigmaWork& w, hipStream_t st) {
+  const int n = m.nao, o = m.nocc, v = m.nvirt;
+  w.T1.ensure(static_cast<size_t>(k) * n * v);
+  // T1_I (n x v) = C[:, :o] (n x o, ld n) * X_I (o x v)
+  dgemm(st, false, false, n, v, o, 1.0, m.C.p, n, 0, X, v, static_cast<long>(o) * v, 0.0, w.T1.p, v,
+        static_cast<long>(n) * v, k);
+  // T_I (n x n) = T1_I * C[:, o:]^T
+  dgemm(st, false, true, n, n, v, 1.0, w.T1.p, v, static_cast<long>(n) * v, m.C.p + o, n, 0, 0.0, T, n,
+        static_cast<long>(n) * n, k);
+}
+
+void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
+                 SigmaWork& w, hipStream_t st, int chunk) {
+  const int n = m.nao, o = m.nocc, v = m.nvirt;
+  const long nn = static_cast<long>(n) * n, nv = static_cast<long>(n) * v, ov = static_cast<long>(o) * v;
+  const bool tdhf = theory == 1;
+  for (int c0 = 0; c0 < k; c0 += chunk) {
+    const int kc = std::min(chunk, k - c0);
+    const int nb = tdhf ? 2 * kc : kc;
+    const double* Vc = V + c0 * ov;
+    w.R.ensure(static_cast<size_t>(kc) * nn);
+    w.F.ensure(static_cast<size_t>(nb) * nn);
+    w.Z.ensure(static_cast<size_t>(nb) * nv);
+    w.T1.ensure(static_cast<size_t>(kc) * nv);
+    std::array<hipEvent_t, kNumPhases + 1> ev;
+    for (auto& e : ev) SEQX_HIP(hipEventCreate(&e));
+    SEQX_HIP(hipEventRecord(ev[0], st));
+    // T1_I (n x v) = C[:, :o] V_I
+    dgemm(st, false, false, n, v, o, 1.0, m.C.p, n, 0, Vc, v, ov, 0.0, w.T1.p, v, nv, kc);
+    SEQX_HIP(hipEventRecord(ev[1], st));
+    // R_I (n x n) = T1_I C[:, o:]^T
+    dgemm(st, false, true, n, n, v, 1.0, w.T1.p, v, nv, m.C.p + o, n, 0, 0.0, w.R.p, n, nn, kc);
+    SEQX_HIP(hipEventRecord(ev[2], st));
+    if (tdhf)
+      build_G(m, kc, w.R.p, nn, w.F.p, w.F.p + kc * nn, nn, kTwo, 4.0, -2.0, -2.0, w.g, st);
+    else
+      build_G(m, kc, w.R.p, nn, w.F.p, nullptr, nn, kSum, 2.0, -1.0, -1.0, w.g, st);
+    SEQX_HIP(hipEventRecord(ev[3], st));
+    // Z_b (n x v) = F_b (n x n) * C[:, o:]
+    dgemm(st, false, false, n, v, n, 1.0, w.F.p, n, nn, m.C.p + o, n, 0, 0.0, w.Z.p, v, nv, nb);
+    SEQX_HIP(hipEventRecord(ev[4], st));
+    // out_b (o x v) = C[:, :o]^T * Z_b + de o V_b
+    SigmaEpilogue ep;
+    ep.eps = m.eps.p;
+    ep.nocc = o;
+    ep.V = Vc;
+    ep.strideV = ov;
+    ep.kv = kc;
+    dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p, v, nv, 0.0, out1 + c0 * ov, v, ov, kc, &ep);
+    if (tdhf)
+      dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p + kc * nv, v, nv, 0.0, out2 + c0 * ov, v, ov, kc, &ep);
+    SEQX_HIP(hipEventRecord(ev[5], st));
+    // algorithmic work of this chunk
+    const double d = 8.0;
+    std::array<double, kNumPhases> fl{}, by{};
+    std::array<long, kNumPhases> la{};
+    fl[kPhaseFwd1] = 2.0 * n * o * v * kc;
+    by[kPhaseFwd1] = d * (static_cast<double>(n) * o + (ov + nv) * static_cast<double>(kc));
+    fl[kPhaseFwd2] = 2.0 * n * static_cast<double>(n) * v * kc;
+    by[kPhaseFwd2] = d * (static_cast<double>(n) * v + (nv + nn) * static_cast<double>(kc));
+    // contraction: read R, write every F, read the packed ERIs once
+    by[kPhaseG] = d * (static_cast<double>(kc) * nn + static_cast<double>(nb) * nn + static_cast<double>(m.np) * m.np);
+    fl[kPhaseG] = 0.0;
+    fl[kPhaseBwd1] = 2.0 * n * static_cast<double>(n) * v * nb;
+    by[kPhaseBwd1] = d * (static_cast<double>(n) * v + (nn + nv) * static_cast<double>(nb));
+    fl[kPhaseBwd2] = 2.0 * o * static_cast<double>(n) * v * nb;
+    by[kPhaseBwd2] = d * (static_cast<double>(n) * o + (nv + 2.0 * ov) * static_cast<double>(nb));
+    la[kPhaseFwd1] = 1;
+    la[kPhaseFwd2] = 1;
+    la[kPhaseG] = 1;
+    la[kPhaseBwd1] = 1;
+    la[kPhaseBwd2] = tdhf ? 2 : 1;
+    w.timer.pending.push_back(ev);
+    w.timer.pending_flops.push_back(fl);
+    w.timer.pending_bytes.push_back(by);
+    w.timer.pending_launches.push_back(la);
+  }
+}
+
+}  // namespace seqx

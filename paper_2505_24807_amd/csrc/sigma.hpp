@@ -1,0 +1,47 @@
+// Matrix-free CIS / TDHF products (Eqs. 8-9 of the paper) on the device.
+#pragma once
+
+#include <array>
+#include <vector>
+
+#include "fock.hpp"
+#include "molecule.hpp"
+
+namespace seqx {
+
+// Phases of one sigma build, timed with HIP events on the build's stream.
+enum SigmaPhase { kPhaseFwd1 = 0, kPhaseFwd2 = 1, kPhaseG = 2, kPhaseBwd1 = 3, kPhaseBwd2 = 4, kNumPhases = 5 };
+
+struct PhaseTimer {
+  std::vector<std::array<hipEvent_t, kNumPhases + 1>> pending;
+  std::vector<std::array<double, kNumPhases>> pending_flops, pending_bytes;
+  std::vector<std::array<long, kNumPhases>> pending_launches;
+  double ms[kNumPhases] = {};
+  double flops[kNumPhases] = {};
+  double bytes[kNumPhases] = {};
+  long launches[kNumPhases] = {};
+  void reset();
+  // wait for the recorded events and fold them into the totals
+  void resolve();
+  ~PhaseTimer();
+};
+
+struct SigmaWork {
+  DBuf<double> T1, R, F, Z;
+  GWork g;
+  PhaseTimer timer;
+};
+
+// k trial vectors V[k][nocc][nvirt] (device) ->
+//   CIS : out1 = A V
+//   TDHF: out1 = (A+B) V, out2 = (A-B) V
+// R_I = C_occ V_I C_virt^T; G(R) by the NDDO contraction; then
+// C_occ^T G C_virt + (eps_a - eps_i) V_I.  Works in chunks of at most
+// `chunk` vectors (memory cap).
+void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
+                 SigmaWork& w, hipStream_t st, int chunk = 32);
+
+// AO transition densities T_I = C_occ X_I C_virt^T for k amplitude vectors (no G, no back-transform).
+void forward_transform(const DeviceMolecule& m, int k, const double* X, double* T, SigmaWork& w, hipStream_t st);
+
+}  // namespace seqx

@@ -1,0 +1,275 @@
+"""Thin Python binding of libseqx (include/seqx.h): argument marshalling only.
+
+Every step of the computation runs inside the HIP library; this module
+converts NumPy arrays / torch device tensors to plain pointers and status
+codes to exceptions.  It never falls back to a CPU path: when the library is
+missing or no GPU is usable, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libseqx.so")
+
+CIS, TDHF = 0, 1
+FP64, FP32, BF16, BF16X3 = 0, 1, 2, 3
+GUESS_GAP, GUESS_LEARNED, GUESS_USER = 0, 1, 2
+NPARAM = 11
+HARTREE_EV = 27.211386245988
+
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_ELEMENT", 3: "E_OPEN_SHELL", 4: "E_GEOMETRY", 5: "E_NOMEM",
+          6: "E_DEVICE", 7: "E_SCF_NOCONV", 8: "E_DAV_NOCONV", 9: "E_UNSTABLE", 10: "E_BUFSIZE", 11: "E_STATE"}
+
+
+class SeqxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class ScfOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ndiis", C.c_int32), ("integrals_only", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("theory", C.c_int32), ("nroots", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("max_subspace", C.c_int32), ("mem_budget_bytes", C.c_size_t), ("precision", C.c_int32),
+                ("guess", C.c_int32), ("n_user_guess", C.c_int32), ("user_guess", C.POINTER(C.c_double))]
+
+
+class Stats(C.Structure):
+    _fields_ = [("scf_iterations", C.c_int32), ("dav_iterations", C.c_int32), ("n_sigma", C.c_int64),
+                ("commutator", C.c_double), ("t_integrals_s", C.c_double), ("t_scf_s", C.c_double),
+                ("t_davidson_s", C.c_double), ("t_sigma_s", C.c_double), ("time_to_roots_s", C.c_double * 64),
+                ("n_history", C.c_int32), ("phase_ms", C.c_double * 5), ("phase_launches", C.c_int64 * 5),
+                ("phase_flops", C.c_double * 5), ("phase_bytes", C.c_double * 5)]
+
+    PHASES = ["C_occ V", "(C_occ V) C_virt^T", "G(R)", "G C_virt", "C_occ^T (G C_virt) + de V"]
+
+
+_lib = None
+
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int32)
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libseqx.so from the package directory; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libseqx.so not found at {path}; build it with `python -m paper_2505_24807_amd.build`")
+    lib = C.CDLL(path)
+    sig = {
+        "seqx_abi_version": (C.c_int, []),
+        "seqx_validate": (C.c_int, [C.c_int32, _I, _I, _D, C.c_char_p, C.c_size_t]),
+        "seqx_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+        "seqx_destroy": (None, [C.c_void_p]),
+        "seqx_last_error": (C.c_char_p, [C.c_void_p]),
+        "seqx_set_params": (C.c_int, [C.c_void_p, C.c_int32, _I, _D]),
+        "seqx_prepare": (C.c_int, [C.c_void_p, C.c_int32, _I, _I, _D, C.POINTER(ScfOpts), C.POINTER(C.c_void_p)]),
+        "seqx_job_free": (None, [C.c_void_p]),
+        "seqx_dims": (C.c_int, [C.c_void_p, C.c_int32, _I, _I, _I]),
+        "seqx_scf_results": (C.c_int, [C.c_void_p, C.c_int32, _D, _D, _D]),
+        "seqx_core_hamiltonian": (C.c_int, [C.c_void_p, C.c_int32, _D]),
+        "seqx_integrals": (C.c_int, [C.c_void_p, C.c_int32, _D, C.c_size_t, C.POINTER(C.c_size_t)]),
+        "seqx_sigma": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _D, _D, _D, C.c_int32]),
+        "seqx_sigma_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_int32]),
+        "seqx_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts)]),
+        "seqx_results": (C.c_int, [C.c_void_p, C.c_int32, _D, _D, _D, _D, _D]),
+        "seqx_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+        "seqx_history": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _I, _D, _D]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def _iptr(a):
+    return None if a is None else a.ctypes.data_as(_I)
+
+
+def validate(natoms, Z, xyz):
+    """Host-only input check; returns (status, message)."""
+    lib = load_library()
+    natoms = np.ascontiguousarray(natoms, dtype=np.int32)
+    Z = np.ascontiguousarray(Z, dtype=np.int32)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    buf = C.create_string_buffer(512)
+    s = lib.seqx_validate(len(natoms), _iptr(natoms), _iptr(Z), _dptr(xyz), buf, 512)
+    return s, buf.value.decode()
+
+
+@dataclass
+class Results:
+    omega_eV: np.ndarray
+    X: np.ndarray
+    Y: np.ndarray
+    f: np.ndarray
+    mu: np.ndarray
+
+
+class Context:
+    """One GPU and one stream.  `stream`: a hipStream_t as int (torch's cuda_stream) or None."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.lib = load_library()
+        h = C.c_void_p()
+        s = self.lib.seqx_create(device, C.c_void_p(stream) if stream else None, C.byref(h))
+        if s != 0:
+            raise SeqxError(s, self.lib.seqx_last_error(None).decode())
+        self.h = h
+
+    def _check(self, s):
+        if s != 0:
+            raise SeqxError(s, self.lib.seqx_last_error(self.h).decode())
+
+    def set_params(self, Zs, values):
+        Zs = np.ascontiguousarray(Zs, dtype=np.int32)
+        values = np.ascontiguousarray(values, dtype=np.float64).reshape(len(Zs), NPARAM)
+        self._check(self.lib.seqx_set_params(self.h, len(Zs), _iptr(Zs), _dptr(values)))
+
+    def prepare(self, natoms, Z, xyz, tol=None, max_iter=None, ndiis=None, integrals_only=False) -> "Job":
+        natoms = np.ascontiguousarray(np.atleast_1d(natoms), dtype=np.int32)
+        Z = np.ascontiguousarray(Z, dtype=np.int32)
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        o = ScfOpts(tol or 0.0, max_iter or 0, ndiis or 0, 1 if integrals_only else 0)
+        h = C.c_void_p()
+        self._check(self.lib.seqx_prepare(self.h, len(natoms), _iptr(natoms), _iptr(Z), _dptr(xyz), C.byref(o),
+                                          C.byref(h)))
+        return Job(self, h, len(natoms))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.seqx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Job:
+    def __init__(self, ctx: Context, h, nmol: int):
+        self.ctx, self.h, self.nmol = ctx, h, nmol
+        self.lib = ctx.lib
+
+    def _check(self, s):
+        self.ctx._check(s)
+
+    def dims(self, mol=0):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.seqx_dims(self.h, mol, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def scf_results(self, mol=0):
+        n, _, _ = self.dims(mol)
+        eps, Cm, P = np.zeros(n), np.zeros((n, n)), np.zeros((n, n))
+        self._check(self.lib.seqx_scf_results(self.h, mol, _dptr(eps), _dptr(Cm), _dptr(P)))
+        return eps, Cm, P
+
+    def core_hamiltonian(self, mol=0):
+        n, _, _ = self.dims(mol)
+        H = np.zeros((n, n))
+        self._check(self.lib.seqx_core_hamiltonian(self.h, mol, _dptr(H)))
+        return H
+
+    def integrals(self, mol=0):
+        need = C.c_size_t()
+        self._check(self.lib.seqx_integrals(self.h, mol, None, 0, C.byref(need)))
+        np_ = int(round(need.value ** 0.5))
+        W = np.zeros((np_, np_))
+        self._check(self.lib.seqx_integrals(self.h, mol, _dptr(W), W.size, C.byref(need)))
+        return W
+
+    def sigma(self, V, theory=TDHF, mol=0, precision=FP64):
+        """Host arrays V[k, nocc, nvirt] -> (out1, out2) (A V, None) or ((A+B)V, (A-B)V)."""
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        k = V.shape[0]
+        o1 = np.zeros_like(V)
+        o2 = np.zeros_like(V) if theory == TDHF else None
+        self._check(self.lib.seqx_sigma(self.h, mol, theory, k, _dptr(V), _dptr(o1), _dptr(o2), precision))
+        return o1, o2
+
+    def sigma_device(self, V, out1, out2=None, theory=TDHF, mol=0, precision=FP64):
+        """torch device tensors (float64, contiguous [k, nocc, nvirt]); ordered on the context stream."""
+        k = V.shape[0]
+        self._check(self.lib.seqx_sigma_device(self.h, mol, theory, k, C.c_void_p(V.data_ptr()),
+                                               C.c_void_p(out1.data_ptr()),
+                                               C.c_void_p(out2.data_ptr()) if out2 is not None else None,
+                                               precision))
+
+    def solve(self, theory=TDHF, nroots=3, tol=1e-6, max_iter=100, max_subspace=0, mem_budget_bytes=0,
+              precision=FP64, guess=GUESS_GAP, user_guess=None):
+        ug = None
+        n_ug = 0
+        if user_guess is not None:
+            ug = np.ascontiguousarray(user_guess, dtype=np.float64)
+            n_ug = ug.shape[0]
+        o = SolveOpts(theory, nroots, tol, max_iter, max_subspace, mem_budget_bytes, precision, guess, n_ug,
+                      _dptr(ug) if ug is not None else None)
+        self.nroots = 0
+        self._check(self.lib.seqx_solve(self.h, C.byref(o)))
+        self.nroots = nroots
+
+    def results(self, mol=0) -> Results:
+        _, o, v = self.dims(mol)
+        K = getattr(self, "nroots", 0)
+        om, f, mu = np.zeros(K), np.zeros(K), np.zeros((K, 3))
+        X, Y = np.zeros((K, o, v)), np.zeros((K, o, v))
+        self._check(self.lib.seqx_results(self.h, mol, _dptr(om), _dptr(X), _dptr(Y), _dptr(f), _dptr(mu)))
+        return Results(om, X, Y, f, mu)
+
+    def history(self, mol=0):
+        """(t_s[iterations], omega_eV[iterations, K]) of the last solve."""
+        n = C.c_int32()
+        self._check(self.lib.seqx_history(self.h, mol, 0, C.byref(n), None, None))
+        K = getattr(self, "nroots", 0)
+        t = np.zeros(n.value)
+        om = np.zeros((n.value, K))
+        self._check(self.lib.seqx_history(self.h, mol, n.value, C.byref(n), _dptr(t), _dptr(om)))
+        return t, om
+
+    def stats(self) -> Stats:
+        s = Stats()
+        self._check(self.lib.seqx_get_stats(self.h, C.byref(s)))
+        return s
+
+    def free(self):
+        if getattr(self, "h", None):
+            self.lib.seqx_job_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def params_table(params: dict):
+    """{Z: {name: value}} (eV, 1/bohr) -> (Z[nel], values[nel, 11]) in the ABI's parameter order."""
+    names = ["zeta_s", "zeta_p", "U_ss", "U_pp", "beta_s", "beta_p", "g_ss", "g_sp", "g_pp", "g_p2", "h_sp"]
+    Zs = sorted(params)
+    vals = np.zeros((len(Zs), NPARAM))
+    for r, z in enumerate(Zs):
+        for c, nm in enumerate(names):
+            vals[r, c] = params[z].get(nm, 0.0)
+    return np.array(Zs, dtype=np.int32), vals
