@@ -105,7 +105,7 @@ def main():
 
     def step():
         job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
-        job.solve(theory=seqx.TDHF, nroots=NROOTS, tol=TOL)
+        job.solve(theory=seqx.TDHF, nroots=NROOTS, tol=TOL, max_iter=400)
         return job
 
     for _ in range(args.warmup):
