@@ -21,7 +21,11 @@ Readings where the paper is silent:
     (r_T - r_U)/(-omega - d), d = eps_a - eps_i, denominators kept >= 1e-8 in
     magnitude;
   * orthonormalisation: classical Gram-Schmidt applied twice; a new vector
-    whose norm drops below 1e-10 is discarded.
+    whose norm drops below 1e-10 is discarded;
+  * optional subspace cap `max_sub`: when the basis would exceed it, it is
+    replaced by the orthonormalised current Ritz vectors (X+Y and X-Y for TDHF,
+    the 2K lowest for CIS) -- the restart from the current best estimates the
+    paper describes when memory runs out (Results section).
 """
 from __future__ import annotations
 
@@ -49,12 +53,18 @@ def _guard(d):
 
 
 def _orthonormalise(V: np.ndarray, W: np.ndarray) -> np.ndarray:
-    """Rows of W orthonormalised against the rows of V and each other (CGS twice)."""
+    """Rows of W orthonormalised against the rows of V and each other.
+
+    Classical Gram-Schmidt applied twice: every projection coefficient against
+    V is taken from the vector before that pass (done for the whole block at
+    once), then the block is orthonormalised row by row the same way."""
+    W = np.array(W, dtype=np.float64, copy=True)
+    if V.shape[0]:
+        for _ in range(2):
+            W -= (W @ V.T) @ V
     out = []
     for w in W:
         for _ in range(2):
-            if V.shape[0]:
-                w = w - V.T @ (V @ w)
             for u in out:
                 w = w - u * (u @ w)
         nrm = np.linalg.norm(w)
@@ -63,9 +73,30 @@ def _orthonormalise(V: np.ndarray, W: np.ndarray) -> np.ndarray:
     return np.array(out).reshape(len(out), V.shape[1])
 
 
+class _Rows:
+    """Growable row storage (amortised doubling) without per-iteration copies of the whole basis."""
+
+    def __init__(self, ncol: int):
+        self.a = np.empty((64, ncol))
+        self.n = 0
+
+    def append(self, rows: np.ndarray):
+        need = self.n + rows.shape[0]
+        if need > self.a.shape[0]:
+            b = np.empty((max(need, 2 * self.a.shape[0]), self.a.shape[1]))
+            b[:self.n] = self.a[:self.n]
+            self.a = b
+        self.a[self.n:need] = rows
+        self.n = need
+
+    @property
+    def v(self) -> np.ndarray:
+        return self.a[:self.n]
+
+
 def solve(ints: I.Integrals, eps: np.ndarray, C: np.ndarray, nocc: int, nroots: int,
           theory: str = "tdhf", tol: float = 1e-7, max_iter: int = 200,
-          guess: np.ndarray | None = None) -> DavidsonResult:
+          guess: np.ndarray | None = None, max_sub: int | None = None) -> DavidsonResult:
     o = nocc
     v = C.shape[1] - nocc
     nov = o * v
@@ -78,23 +109,37 @@ def solve(ints: I.Integrals, eps: np.ndarray, C: np.ndarray, nocc: int, nroots: 
     else:
         V = _orthonormalise(np.zeros((0, nov)), guess.reshape(guess.shape[0], -1))
     tdhf = theory == "tdhf"
-    SP = np.zeros((0, nov))   # (A+B) V   (CIS: A V)
-    SM = np.zeros((0, nov))   # (A-B) V
+    Vs, SPs, SMs = _Rows(nov), _Rows(nov), _Rows(nov)   # basis, (A+B) V (CIS: A V), (A-B) V
+    Mp = np.zeros((0, 0))
+    Mm = np.zeros((0, 0))
     new = V
-    V = np.zeros((0, nov))
     n_sigma = 0
     hist = []
+
+    def grow(M, Vall, S_new, s0):
+        # projected matrix V^T S V: new columns from the new products, rows by symmetry
+        n1 = Vall.shape[0]
+        out = np.zeros((n1, n1))
+        out[:s0, :s0] = M
+        col = Vall @ S_new.T                    # [n1, k]
+        out[:, s0:] = col
+        out[s0:, :s0] = col[:s0].T
+        out[s0:, s0:] = 0.5 * (col[s0:] + col[s0:].T)
+        return out
+
     for it in range(1, max_iter + 1):
         AV, BV = X.sigma(ints, eps, C, nocc, new.reshape(-1, o, v))
         AV, BV = AV.reshape(-1, nov), BV.reshape(-1, nov)
         n_sigma += new.shape[0]
-        V = np.vstack([V, new])
+        s0 = Vs.n
+        Vs.append(new)
+        V = Vs.v
         if tdhf:
-            SP = np.vstack([SP, AV + BV])
-            SM = np.vstack([SM, AV - BV])
-            Mp = V @ SP.T
-            Mm = V @ SM.T
-            Mp, Mm = 0.5 * (Mp + Mp.T), 0.5 * (Mm + Mm.T)
+            SPs.append(AV + BV)
+            SMs.append(AV - BV)
+            SP, SM = SPs.v, SMs.v
+            Mp = grow(Mp, V, SP[s0:], s0)
+            Mm = grow(Mm, V, SM[s0:], s0)
             L = np.linalg.cholesky(Mm)
             w2, W = np.linalg.eigh(L.T @ Mp @ L)
             om = np.sqrt(w2[:nroots])
@@ -105,10 +150,10 @@ def solve(ints: I.Integrals, eps: np.ndarray, C: np.ndarray, nocc: int, nroots: 
             rU = u.T @ SM - om[:, None] * T
             res = np.sqrt(np.sum(rT * rT, axis=1) + np.sum(rU * rU, axis=1))
         else:
-            SP = np.vstack([SP, AV])
-            M = V @ SP.T
-            M = 0.5 * (M + M.T)
-            w, W = np.linalg.eigh(M)
+            SPs.append(AV)
+            SP = SPs.v
+            Mp = grow(Mp, V, SP[s0:], s0)
+            w, W = np.linalg.eigh(Mp)
             om = w[:nroots]
             x = W[:, :nroots]
             T = x.T @ V
@@ -124,6 +169,20 @@ def solve(ints: I.Integrals, eps: np.ndarray, C: np.ndarray, nocc: int, nroots: 
                 cand.append((rT[k] - rU[k]) / _guard(-om[k] - d))
             else:
                 cand.append(r[k] / _guard(om[k] - d))
+        if max_sub is not None and Vs.n + len(cand) > max_sub:
+            # restart from the current best estimates (paper, Results: collapse of the subspace)
+            base = np.vstack([T, U]) if tdhf else W[:, :min(2 * nroots, W.shape[1])].T @ V
+            Vn = _orthonormalise(np.zeros((0, nov)), base)
+            G = Vn @ V.T                      # new basis expressed in the old orthonormal one
+            Vs, SPs = _Rows(nov), _Rows(nov)
+            Vs.append(Vn)
+            SPs.append(G @ SP)
+            Mp = G @ Mp @ G.T
+            if tdhf:
+                SMs = _Rows(nov)
+                SMs.append(G @ SM)
+                Mm = G @ Mm @ G.T
+            V = Vs.v
         new = _orthonormalise(V, np.array(cand))
         if new.shape[0] == 0:
             break

@@ -172,11 +172,11 @@ def sigma(ints: I.Integrals, eps: np.ndarray, C: np.ndarray, nocc: int, V: np.nd
     single = V.ndim == 2
     if single:
         V = V[None]
-    R = np.einsum("mi,kia,na->kmn", Co, V, Cv)
+    R = Co[None] @ V @ Cv.T[None]
     J, K = I.jk(ints, R)
     _, KT = I.jk(ints, np.ascontiguousarray(R.transpose(0, 2, 1)))
-    AV = de[None] * V + np.einsum("mi,kmn,na->kia", Co, 2 * J - K, Cv)
-    BV = np.einsum("mi,kmn,na->kia", Co, 2 * J - KT, Cv)
+    AV = de[None] * V + Co.T[None] @ (2 * J - K) @ Cv[None]
+    BV = Co.T[None] @ (2 * J - KT) @ Cv[None]
     if single:
         return AV[0], BV[0]
     return AV, BV

@@ -70,11 +70,11 @@ def c3():
     sy, ints, res = _setup(mol)
     o = res.nocc
     t = time.time()
-    dv = davidson.solve(ints, res.eps, res.C, o, 10, "tdhf", tol=1e-7)
+    dv = davidson.solve(ints, res.eps, res.C, o, 10, "tdhf", tol=1e-7, max_sub=600, max_iter=1000)
     secs = time.time() - t
     ex = excited.Excitations(dv.omega, dv.X, dv.Y)
     _, f = excited.transition_properties(sy, res.C, o, ex)
-    _dump("c3_water330_tdhf.json", {"config": "(H2O)330, seed 330", "method": "oracle CPU Davidson, tol 1e-7 Eh",
+    _dump("c3_water330_tdhf.json", {"config": "(H2O)330, seed 330", "method": "oracle CPU Davidson, tol 1e-7 Eh, subspace cap 600",
                                     "seconds": secs, "iterations": dv.iterations, "n_sigma": dv.n_sigma,
                                     "homo_lumo_eV": float((res.eps[o] - res.eps[o - 1]) * model.HARTREE_EV),
                                     "omega_eV": (dv.omega * model.HARTREE_EV).tolist(), "f": f.tolist(),

@@ -343,3 +343,15 @@ def test_cpu_davidson_matches_dense(mol, theory):
     assert np.abs(dv.omega - ref.omega).max() * HA < 1e-9
     for k in range(K):
         assert abs(abs(np.sum(dv.X[k] * ref.X[k]) - np.sum(dv.Y[k] * ref.Y[k])) - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("theory", ["cis", "tdhf"])
+def test_cpu_davidson_collapse_keeps_roots(theory):
+    """Restarting from the Ritz vectors under a tight subspace cap converges to the same roots."""
+    mol = molecules.add_noise(molecules.polyene(10), 0.02, np.random.default_rng(4))
+    sy, ints, res = _run(mol)
+    o, v = res.nocc, sy.nao - res.nocc
+    A, B = excited.build_AB(ints, res.eps, res.C, o)
+    ref = excited.cis_dense(A, 3, o, v) if theory == "cis" else excited.tdhf_dense(A, B, 3, o, v)
+    dv = davidson.solve(ints, res.eps, res.C, o, 3, theory, tol=1e-8, max_sub=16, max_iter=500)
+    assert np.abs(dv.omega - ref.omega).max() * HA < 1e-9
