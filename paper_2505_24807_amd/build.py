@@ -23,7 +23,7 @@ SOURCES = ["model.cpp", "integrals.hip", "gemm.hip", "fock.hip", "linalg.hip", "
            "davidson.hip", "abi.cpp"]
 
 CFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
           f"-I{ROCM}/include", f"-I{os.path.join(HERE, '..', 'include')}"]
 

@@ -12,9 +12,11 @@
 // u = M+ t / w, so that t^T u = 1 (X^T X - Y^T Y = 1).  Residuals:
 // r_T = (A+B) T - w U, r_U = (A-B) U - w T.  New directions per unconverged
 // root: (r_T + r_U)/(w - d) and (r_T - r_U)/(-w - d), d = eps_a - eps_i.
-// Orthonormalisation: unit rows, classical Gram-Schmidt twice against V,
-// then symmetric (Loewdin) orthonormalisation inside the new block with
-// near-dependent directions dropped.  All subspace arithmetic is FP64.
+// Orthonormalisation: unit rows, classical Gram-Schmidt against V (a second
+// pass when a row lost most of its norm), then symmetric (Loewdin)
+// orthonormalisation inside the new block with near-dependent directions
+// dropped.  (A+B)V and (A-B)V rows are stored interleaved so that one pass over
+// the basis serves both projected matrices.  All subspace arithmetic is FP64.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -76,6 +78,17 @@ __global__ void sym_fill_kernel(double* M, int ld, int S0, int S1) {
       M[static_cast<long>(s) * ld + t] = a;
     }
   }
+}
+
+// G (nr x S1, row r = product p = r % ps of new vector r / ps against V_0..V_S1-1)
+// -> column S0 + r / ps of Mp (p = 0) or Mm (p = 1), column-major, ld ldm
+__global__ void scatter_cols_kernel(const double* __restrict__ G, int S1, int ps, int S0, double* Mp, double* Mm,
+                                    int ldm) {
+  const int r = blockIdx.y;
+  double* M = (r % ps == 0) ? Mp : Mm;
+  const int t = S0 + r / ps;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S1; s += gridDim.x * blockDim.x)
+    M[static_cast<long>(t) * ldm + s] = G[static_cast<long>(r) * S1 + s];
 }
 
 __global__ void omega_kernel(int K, const double* __restrict__ w2, double* __restrict__ om, int tdhf) {
@@ -288,13 +301,21 @@ int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov,
   dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
   hipLaunchKernelGGL(scale_rows_kernel, dim3(ceil_div(nov, 256), nc), dim3(256), 0, st, nov, Wc, G, nc);
   SEQX_LAUNCH_CHECK();
-  if (S > 0) {
-    for (int pass = 0; pass < 2; ++pass) {
-      dots(st, nc, Wc, nov, S, V, nov, nov, Cc, S, w.ws.p);
-      dgemm(st, false, false, nc, static_cast<int>(nov), S, -1.0, Cc, S, 0, V, nov, 0, 1.0, Wc, nov, 0, 1, nullptr);
-    }
+  // classical Gram-Schmidt against V; a second pass only when a unit row lost
+  // more than three quarters of its norm ("twice is enough")
+  for (int pass = 0; pass < 2 && S > 0; ++pass) {
+    dots(st, nc, Wc, nov, S, V, nov, nov, Cc, S, w.ws.p);
+    dgemm(st, false, false, nc, static_cast<int>(nov), S, -1.0, Cc, S, 0, V, nov, 0, 1.0, Wc, nov, 0, 1, nullptr);
+    dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
+    if (pass == 1) break;
+    std::vector<double> g(static_cast<size_t>(nc) * nc);
+    d2h(g.data(), G, g.size(), st);
+    SEQX_HIP(hipStreamSynchronize(st));
+    bool again = false;
+    for (int r = 0; r < nc; ++r) again = again || g[static_cast<size_t>(r) * nc + r] < 0.25;
+    if (!again) break;
   }
-  dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
+  if (S == 0) dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
   ds.eigh(nc, G, nc, w.w2.p);
   std::vector<double> lam(nc);
   d2h(lam.data(), w.w2.p, nc, st);
@@ -332,8 +353,10 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   const double t0 = now_s();
 
   w.V.ensure(static_cast<size_t>(Smax) * nov);
-  w.SP.ensure(static_cast<size_t>(Smax) * nov);
-  if (tdhf) w.SM.ensure(static_cast<size_t>(Smax) * nov);
+  // products of basis vector s: row ps*s holds (A+B)V_s (CIS: A V_s), row ps*s+1 holds (A-B)V_s
+  const int ps = tdhf ? 2 : 1;
+  const long ldp = ps * nov;
+  w.SP.ensure(static_cast<size_t>(ps) * Smax * nov);
   w.Mp.ensure(static_cast<size_t>(Smax) * Smax);
   w.Mm.ensure(static_cast<size_t>(Smax) * Smax);
   w.Lm.ensure(static_cast<size_t>(Smax) * Smax);
@@ -341,12 +364,16 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   w.Hs.ensure(static_cast<size_t>(Smax) * Smax);
   w.w2.ensure(Smax);
   w.coef.ensure(static_cast<size_t>(Smax) * 2 * K);
-  for (DBuf<double>* b : {&w.Tv, &w.Uv, &w.PT, &w.MU}) b->ensure(static_cast<size_t>(K) * nov);
+  // Ritz rows: Tv holds [T; U] (U only for TDHF), PT holds [(A+B)T; (A-B)U] (CIS: A X)
+  w.Tv.ensure(static_cast<size_t>(ps) * K * nov);
+  w.PT.ensure(static_cast<size_t>(ps) * K * nov);
+  double* Uv = w.Tv.p + static_cast<long>(K) * nov;
+  double* MU = w.PT.p + static_cast<long>(K) * nov;
   w.W.ensure(static_cast<size_t>(std::max(ncand_max, opt.guess ? opt.nguess : 0)) * nov);
-  w.scratch.ensure(static_cast<size_t>(2 * K) * nov);
-  w.G.ensure(static_cast<size_t>(Smax) * Smax);
+  w.scratch.ensure(static_cast<size_t>(ps) * 2 * K * nov);
+  w.G.ensure(static_cast<size_t>(ps) * Smax * Smax);
   w.Q.ensure(static_cast<size_t>(std::max(ncand_max, 2 * K)) * Smax);
-  w.ws.ensure(std::max<size_t>(dots_workspace(Smax, Smax, nov), 4096));
+  w.ws.ensure(std::max<size_t>(dots_workspace(2 * Smax, Smax, nov), 4096));
   w.d.ensure(nov);
   w.rn.ensure(2 * K);
   const int nbres = static_cast<int>(std::min<long>(256, ceil_div(nov, 256)));
@@ -384,19 +411,20 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
     for (it = 1; it <= opt.max_iter; ++it) {
       // 1. products of the new vectors
       SEQX_HIP(hipEventRecord(e0, st));
-      sigma_build(m, opt.theory, knew, w.V.p + S * nov, w.SP.p + S * nov, tdhf ? w.SM.p + S * nov : nullptr, w.sig,
-                  st, opt.sigma_chunk);
+      double* sp_new = w.SP.p + static_cast<long>(S) * ldp;
+      sigma_build(m, opt.theory, knew, w.V.p + S * nov, sp_new, tdhf ? sp_new + nov : nullptr, w.sig, st,
+                  opt.sigma_chunk, ldp);
       SEQX_HIP(hipEventRecord(e1, st));
       res.n_sigma += knew;
       const int S1 = S + knew;
-      // 2. projected matrices, new columns (column-major, ld = Smax)
-      dots(st, knew, w.SP.p + S * nov, nov, S1, w.V.p, nov, nov, w.Mp.p + static_cast<long>(S) * Smax, Smax, w.ws.p);
+      // 2. projected matrices, new columns (column-major, ld = Smax): one pass over
+      // V for (A+B) and (A-B) together, since their rows are interleaved
+      dots(st, ps * knew, sp_new, nov, S1, w.V.p, nov, nov, w.G.p, S1, w.ws.p);
+      hipLaunchKernelGGL(scatter_cols_kernel, dim3(ceil_div(S1, 256), ps * knew), dim3(256), 0, st, w.G.p, S1, ps, S,
+                         w.Mp.p, w.Mm.p, Smax);
       hipLaunchKernelGGL(sym_fill_kernel, dim3(ceil_div(S1, 256), knew), dim3(256), 0, st, w.Mp.p, Smax, S, S1);
-      if (tdhf) {
-        dots(st, knew, w.SM.p + S * nov, nov, S1, w.V.p, nov, nov, w.Mm.p + static_cast<long>(S) * Smax, Smax,
-             w.ws.p);
+      if (tdhf)
         hipLaunchKernelGGL(sym_fill_kernel, dim3(ceil_div(S1, 256), knew), dim3(256), 0, st, w.Mm.p, Smax, S, S1);
-      }
       SEQX_LAUNCH_CHECK();
       S = S1;
       // 3. subspace eigenproblem
@@ -422,19 +450,17 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       }
       SEQX_LAUNCH_CHECK();
       // 4. Ritz vectors and products: rows j of Tv = sum_s t(s, j) V_s, etc.
-      dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.V.p, nov, 0, 0.0, w.Tv.p, nov, 0, 1,
+      // [T; U] in one pass over V (t and u are adjacent coefficient columns)
+      dgemm(st, false, false, ps * K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.V.p, nov, 0, 0.0, w.Tv.p, nov, 0,
+            1, nullptr);
+      dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.SP.p, ldp, 0, 0.0, w.PT.p, nov, 0, 1,
             nullptr);
-      dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.SP.p, nov, 0, 0.0, w.PT.p, nov, 0, 1,
-            nullptr);
-      if (tdhf) {
-        dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, uco, Smax, 0, w.V.p, nov, 0, 0.0, w.Uv.p, nov, 0, 1,
-              nullptr);
-        dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, uco, Smax, 0, w.SM.p, nov, 0, 0.0, w.MU.p, nov, 0,
+      if (tdhf)
+        dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, uco, Smax, 0, w.SP.p + nov, ldp, 0, 0.0, MU, nov, 0,
               1, nullptr);
-      }
       // 5. residual norms
-      hipLaunchKernelGGL(residual_norm_kernel, dim3(nbres, K), dim3(256), 0, st, nov, tdhf ? 1 : 0, om, w.Tv.p,
-                         w.Uv.p, w.PT.p, w.MU.p, w.part.p);
+      hipLaunchKernelGGL(residual_norm_kernel, dim3(nbres, K), dim3(256), 0, st, nov, tdhf ? 1 : 0, om, w.Tv.p, Uv,
+                         w.PT.p, MU, w.part.p);
       hipLaunchKernelGGL(reduce_rows_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, nbres, w.part.p, w.rn.p);
       SEQX_LAUNCH_CHECK();
       d2h(h_rn.data(), w.rn.p, K, st);
@@ -470,7 +496,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       const int nsel = static_cast<int>(sel.size());
       SEQX_HIP(hipMemcpyAsync(w.sel.p, sel.data(), nsel * sizeof(int), hipMemcpyHostToDevice, st));
       hipLaunchKernelGGL(precond_kernel, dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov, tdhf ? 1 : 0,
-                         w.sel.p, om, w.d.p, w.Tv.p, w.Uv.p, w.PT.p, w.MU.p, w.W.p);
+                         w.sel.p, om, w.d.p, w.Tv.p, Uv, w.PT.p, MU, w.W.p);
       SEQX_LAUNCH_CHECK();
       const int nc = tdhf ? 2 * nsel : nsel;
       // 7. collapse onto the best Ritz vectors when the basis would overflow
@@ -496,12 +522,13 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
         dgemm_cm(st, false, false, S, q, q0, 1.0, Cc, Smax, w.G.p + static_cast<long>(j0) * q0, q0, 0.0, w.Lm.p,
                  Smax);  // Qc (S x q) in Lm
         double* Qc = w.Lm.p;
-        for (double* B : {w.V.p, w.SP.p, tdhf ? w.SM.p : nullptr}) {
-          if (!B) continue;
-          dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, B, nov, 0, 0.0, w.scratch.p, nov, 0,
-                1, nullptr);
-          copy(st, B, w.scratch.p, static_cast<long>(q) * nov);
-        }
+        dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.V.p, nov, 0, 0.0, w.scratch.p, nov, 0,
+              1, nullptr);
+        copy(st, w.V.p, w.scratch.p, static_cast<long>(q) * nov);
+        for (int p = 0; p < ps; ++p)  // keep the interleaved product rows interleaved
+          dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.SP.p + p * nov, ldp, 0, 0.0,
+                w.scratch.p + p * nov, ldp, 0, 1, nullptr);
+        copy(st, w.SP.p, w.scratch.p, static_cast<long>(q) * ldp);
         for (double* Mx : {w.Mp.p, tdhf ? w.Mm.p : nullptr}) {
           if (!Mx) continue;
           dgemm_cm(st, false, false, S, q, S, 1.0, Mx, Smax, Qc, Smax, 0.0, w.Tmp.p, Smax);
@@ -526,8 +553,8 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
 
   // 9. amplitudes, sign convention, properties
   copy(st, m.omega.p, om, K);
-  hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(nov, 256), K), dim3(256), 0, st, nov, tdhf ? 1 : 0, w.Tv.p,
-                     w.Uv.p, m.X.p, m.Y.p);
+  hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(nov, 256), K), dim3(256), 0, st, nov, tdhf ? 1 : 0, w.Tv.p, Uv,
+                     m.X.p, m.Y.p);
   hipLaunchKernelGGL(sign_fix_kernel, dim3(K), dim3(256), 0, st, nov, m.X.p, m.Y.p);
   SEQX_LAUNCH_CHECK();
   // transition densities of X + Y (T for TDHF, X for CIS)

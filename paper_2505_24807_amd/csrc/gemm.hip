@@ -13,6 +13,7 @@ namespace seqx {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 template <int WM, int WN, int TM, int TN, bool TA, bool TB, bool EPI>
 __global__ void __launch_bounds__(256) dgemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
@@ -86,6 +87,179 @@ __global__ void __launch_bounds__(256) dgemm_kernel(int M, int N, int K, double 
       }
 }
 
+// Large-tile variant for the dense transforms: 128 x 128 block tile, each of the
+// four wavefronts owns a 64 x 64 quadrant (4 x 4 MFMA tiles), 16-byte global
+// loads, and the next K panel is fetched into registers while the MFMAs of the
+// current one run.  Needs even leading dimensions / batch strides and 16-byte
+// aligned base pointers (checked by the host dispatcher).
+constexpr int kBM = 128, kBN = 128, kBK = 16, kPad = 2;
+
+// Global -> register load of one K panel (4 x 16-byte pieces of A and of B per
+// thread).  CHECKED adds per-element bounds tests for edge tiles.
+template <bool TA, bool TB, bool CHECKED>
+__device__ __forceinline__ void panel_load(const double* __restrict__ A, long lda, const double* __restrict__ B,
+                                           long ldb, int M, int N, int K, int m0, int n0, int k0, int tid, d2* ra,
+                                           d2* rb) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = tid + 256 * j;
+    int gi, gk;
+    if (!TA) { gi = m0 + (c >> 3); gk = k0 + (c & 7) * 2; } else { gk = k0 + (c >> 6); gi = m0 + (c & 63) * 2; }
+    const double* p = TA ? A + static_cast<long>(gk) * lda + gi : A + static_cast<long>(gi) * lda + gk;
+    if (!CHECKED) {
+      ra[j] = *reinterpret_cast<const d2*>(__builtin_assume_aligned(p, 16));
+    } else {
+      const int gi1 = TA ? gi + 1 : gi, gk1 = TA ? gk : gk + 1;
+      ra[j].x = (gi < M && gk < K) ? p[0] : 0.0;
+      ra[j].y = (gi1 < M && gk1 < K) ? p[1] : 0.0;
+    }
+    int gj;
+    if (!TB) { gk = k0 + (c >> 6); gj = n0 + (c & 63) * 2; } else { gj = n0 + (c >> 3); gk = k0 + (c & 7) * 2; }
+    const double* q = TB ? B + static_cast<long>(gj) * ldb + gk : B + static_cast<long>(gk) * ldb + gj;
+    if (!CHECKED) {
+      rb[j] = *reinterpret_cast<const d2*>(__builtin_assume_aligned(q, 16));
+    } else {
+      const int gj1 = TB ? gj : gj + 1, gk1 = TB ? gk + 1 : gk;
+      rb[j].x = (gj < N && gk < K) ? q[0] : 0.0;
+      rb[j].y = (gj1 < N && gk1 < K) ? q[1] : 0.0;
+    }
+  }
+}
+
+template <bool TA, bool TB>
+__device__ __forceinline__ void panel_store(double (*As)[kBM + kPad], double (*Bs)[kBN + kPad], int tid, const d2* ra,
+                                            const d2* rb) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = tid + 256 * j;
+    if (!TA) {
+      const int i = c >> 3, kk = (c & 7) * 2;
+      As[kk][i] = ra[j].x;
+      As[kk + 1][i] = ra[j].y;
+    } else {
+      const int kk = c >> 6, i = (c & 63) * 2;
+      As[kk][i] = ra[j].x;
+      As[kk][i + 1] = ra[j].y;
+    }
+    if (!TB) {
+      const int kk = c >> 6, jj = (c & 63) * 2;
+      Bs[kk][jj] = rb[j].x;
+      Bs[kk][jj + 1] = rb[j].y;
+    } else {
+      const int jj = c >> 3, kk = (c & 7) * 2;
+      Bs[kk][jj] = rb[j].x;
+      Bs[kk + 1][jj] = rb[j].y;
+    }
+  }
+}
+
+__device__ __forceinline__ void panel_mfma(const double (*As)[kBM + kPad], const double (*Bs)[kBN + kPad], int lane,
+                                           int wm, int wn, d4 (*acc)[4]) {
+#pragma unroll
+  for (int ks = 0; ks < kBK; ks += 4) {
+    double a[4], bb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = As[ks + (lane >> 4)][wm + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bb[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+// One block tile: full K panels stream through registers and LDS, the ragged K
+// tail (if any) and, for edge tiles, every panel use bounds-checked loads.
+template <bool TA, bool TB, bool EPI, bool EDGE>
+__device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const double* __restrict__ A, long lda,
+                                        const double* __restrict__ B, long ldb, double beta, double* __restrict__ C,
+                                        long ldc, long b, const SigmaEpilogue& ep, int m0, int n0,
+                                        double (*As)[kBM + kPad], double (*Bs)[kBN + kPad]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  d2 ra[4], rb[4];
+  const int nfull = K / kBK;  // panels without a K tail
+  if (nfull > 0) {
+    panel_load<TA, TB, EDGE>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
+    panel_store<TA, TB>(As, Bs, tid, ra, rb);
+    __syncthreads();
+    for (int kt = 0; kt < nfull; ++kt) {
+      // prefetch the next full panel (the last iteration re-reads its own panel)
+      const int kn = (kt + 1 < nfull ? kt + 1 : kt) * kBK;
+      panel_load<TA, TB, EDGE>(A, lda, B, ldb, M, N, K, m0, n0, kn, tid, ra, rb);
+      panel_mfma(As, Bs, lane, wm, wn, acc);
+      __syncthreads();
+      panel_store<TA, TB>(As, Bs, tid, ra, rb);
+      __syncthreads();
+    }
+  }
+  if (nfull * kBK < K) {
+    panel_load<TA, TB, true>(A, lda, B, ldb, M, N, K, m0, n0, nfull * kBK, tid, ra, rb);
+    panel_store<TA, TB>(As, Bs, tid, ra, rb);
+    __syncthreads();
+    panel_mfma(As, Bs, lane, wm, wn, acc);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (!EDGE || (row < M && col < N)) {
+          double v = alpha * acc[i][j][r];
+          double* cp = C + static_cast<long>(row) * ldc + col;
+          if (beta != 0.0) v += beta * *cp;
+          if (EPI) {
+            const double* Vb = ep.V + (b % ep.kv) * ep.strideV;
+            v += (ep.eps[ep.nocc + col] - ep.eps[row]) * Vb[static_cast<long>(row) * ldc + col];
+          }
+          *cp = v;
+        }
+      }
+}
+
+template <bool TA, bool TB, bool EPI>
+__global__ void __launch_bounds__(256) dgemm128_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                       long lda, long sA, const double* __restrict__ B, long ldb,
+                                                       long sB, double beta, double* __restrict__ C, long ldc, long sC,
+                                                       SigmaEpilogue ep) {
+  __shared__ double As[kBK][kBM + kPad];
+  __shared__ double Bs[kBK][kBN + kPad];
+  const long b = blockIdx.z;
+  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+  if (m0 + kBM <= M && n0 + kBN <= N)
+    tile128<TA, TB, EPI, false>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
+                                n0, As, Bs);
+  else
+    tile128<TA, TB, EPI, true>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0, n0,
+                               As, Bs);
+}
+
+template <bool EPI>
+void launch128(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda, long sA,
+               const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC, int batch,
+               const SigmaEpilogue& ep) {
+  dim3 grid(ceil_div(N, kBN), ceil_div(M, kBM), batch);
+#define SEQX_GEMM128_CASE(TA_, TB_)                                                                                 \
+  hipLaunchKernelGGL((dgemm128_kernel<TA_, TB_, EPI>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb, \
+                     sB, beta, C, ldc, sC, ep)
+  if (!ta && !tb) SEQX_GEMM128_CASE(false, false);
+  else if (!ta && tb) SEQX_GEMM128_CASE(false, true);
+  else if (ta && !tb) SEQX_GEMM128_CASE(true, false);
+  else SEQX_GEMM128_CASE(true, true);
+#undef SEQX_GEMM128_CASE
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 template <int WM, int WN, int TM, int TN, bool EPI>
 void launch_cfg(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,
                 long sA, const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC, int batch,
@@ -131,7 +305,15 @@ void dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, 
   SigmaEpilogue ep;
   if (epi) ep = *epi;
   const bool skinny = N <= 16;
-  if (epi) {
+  const bool even = ((lda | ldb | sA | sB) & 1) == 0 && aligned16(A) && aligned16(B);
+  if (even && M >= 96 && N >= 96 && K >= 16) {
+    if (epi)
+      launch128<true>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
+    else
+      launch128<false>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
+  } else if (!epi && !skinny && M <= 32) {
+    launch_cfg<1, 4, 2, 1, false>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
+  } else if (epi) {
     launch_cfg<2, 2, 2, 2, true>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
   } else if (skinny) {
     launch_cfg<4, 1, 1, 1, false>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);

@@ -56,9 +56,10 @@ void forward_transform(const DeviceMolecule& m, int k, const double* X, double* 
 }
 
 void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
-                 SigmaWork& w, hipStream_t st, int chunk) {
+                 SigmaWork& w, hipStream_t st, int chunk, long out_stride) {
   const int n = m.nao, o = m.nocc, v = m.nvirt;
   const long nn = static_cast<long>(n) * n, nv = static_cast<long>(n) * v, ov = static_cast<long>(o) * v;
+  const long os = out_stride > 0 ? out_stride : ov;
   const bool tdhf = theory == 1;
   for (int c0 = 0; c0 < k; c0 += chunk) {
     const int kc = std::min(chunk, k - c0);
@@ -92,9 +93,9 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
     ep.V = Vc;
     ep.strideV = ov;
     ep.kv = kc;
-    dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p, v, nv, 0.0, out1 + c0 * ov, v, ov, kc, &ep);
+    dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p, v, nv, 0.0, out1 + c0 * os, v, os, kc, &ep);
     if (tdhf)
-      dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p + kc * nv, v, nv, 0.0, out2 + c0 * ov, v, ov, kc, &ep);
+      dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p + kc * nv, v, nv, 0.0, out2 + c0 * os, v, os, kc, &ep);
     SEQX_HIP(hipEventRecord(ev[5], st));
     // algorithmic work of this chunk
     const double d = 8.0;

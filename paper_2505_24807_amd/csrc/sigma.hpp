@@ -37,9 +37,10 @@ struct SigmaWork {
 //   TDHF: out1 = (A+B) V, out2 = (A-B) V
 // R_I = C_occ V_I C_virt^T; G(R) by the NDDO contraction; then
 // C_occ^T G C_virt + (eps_a - eps_i) V_I.  Works in chunks of at most
-// `chunk` vectors (memory cap).
+// `chunk` vectors (memory cap).  out_stride: distance (doubles) between the
+// outputs of consecutive vectors (0: nocc*nvirt, i.e. contiguous).
 void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
-                 SigmaWork& w, hipStream_t st, int chunk = 32);
+                 SigmaWork& w, hipStream_t st, int chunk = 32, long out_stride = 0);
 
 // AO transition densities T_I = C_occ X_I C_virt^T for k amplitude vectors (no G, no back-transform).
 void forward_transform(const DeviceMolecule& m, int k, const double* X, double* T, SigmaWork& w, hipStream_t st);
