@@ -113,6 +113,7 @@ def main():
     torch.cuda.synchronize()
     totals = {"n_sigma": 0, "scf": 0.0, "dav": 0.0, "sig": 0.0, "iters": 0}
     phase = np.zeros((4, 5))
+    dav_phase = np.zeros(8)
     ttr, parity = [], []
     t0 = time.perf_counter()
     jobs = []
@@ -129,6 +130,7 @@ def main():
         totals["sig"] += st.t_sigma_s
         totals["iters"] += st.dav_iterations
         phase += np.array([list(st.phase_ms), list(st.phase_launches), list(st.phase_flops), list(st.phase_bytes)])
+        dav_phase += np.array(list(st.dav_phase_ms))
         t, om = job.history()
         tt = time_to_roots(t, om, ref)
         if tt is not None:
@@ -166,6 +168,7 @@ def main():
         "n_sigma_per_step": totals["n_sigma"] // K, "davidson_iterations": totals["iters"] // K,
         "phase_ms_per_step": {seqx.Stats.PHASES[i]: round(phase[0, i] / K, 2) for i in range(5)},
         "contraction_GBps": round(g_gbs, 1),
+        "davidson_phase_ms_per_step": {seqx.Stats.DAV_PHASES[i]: round(dav_phase[i] / K, 1) for i in range(8)},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

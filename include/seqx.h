@@ -109,6 +109,11 @@ typedef struct {
   int64_t phase_launches[5];
   double phase_flops[5];
   double phase_bytes[5];
+  /* Davidson device time by phase in the last seqx_solve (ms, HIP events):
+   * 0 sigma build, 1 projected matrices, 2 subspace eigenproblem, 3 Ritz
+   * vectors and residuals, 4 convergence check (host read), 5 preconditioner,
+   * 6 subspace collapse, 7 orthonormalisation. */
+  double dav_phase_ms[8];
 } seqx_stats;
 
 /* Version of this header the library was built with (SEQX_ABI_VERSION). */

@@ -397,6 +397,7 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
     DBuf<double> guess;
     job->solved = false;
     job->stats.n_sigma = 0;
+    for (double& x : job->stats.dav_phase_ms) x = 0.0;
     job->dw.sig.timer.reset();
     job->stats.dav_iterations = 0;
     job->stats.t_sigma_s = 0;
@@ -433,6 +434,7 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
       m.hist_omega.clear();
       for (const auto& w : r.omega_iter) m.hist_omega.insert(m.hist_omega.end(), w.begin(), w.end());
       job->stats.n_sigma += r.n_sigma;
+      for (int p = 0; p < kNumDavPhases; ++p) job->stats.dav_phase_ms[p] += r.phase_ms[p];
       job->stats.dav_iterations = std::max(job->stats.dav_iterations, r.iterations);
       job->stats.t_sigma_s += r.t_sigma_ms * 1e-3;
       if (mi == 0) {

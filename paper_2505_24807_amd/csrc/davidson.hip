@@ -288,6 +288,35 @@ bool log_enabled() {
   return on;
 }
 
+// Event marks on the stream; the time between consecutive marks is charged to
+// the phase of the earlier mark.
+class IterTimer {
+ public:
+  explicit IterTimer(hipStream_t st) : st_(st) {}
+  ~IterTimer() {
+    for (auto& m : marks_) (void)hipEventDestroy(m.second);
+  }
+  void mark(int phase) {
+    hipEvent_t e;
+    SEQX_HIP(hipEventCreate(&e));
+    SEQX_HIP(hipEventRecord(e, st_));
+    marks_.emplace_back(phase, e);
+  }
+  void accumulate(double* ms) {
+    if (marks_.empty()) return;
+    SEQX_HIP(hipEventSynchronize(marks_.back().second));
+    for (size_t i = 0; i + 1 < marks_.size(); ++i) {
+      float t = 0.f;
+      SEQX_HIP(hipEventElapsedTime(&t, marks_[i].second, marks_[i + 1].second));
+      ms[marks_[i].first] += t;
+    }
+  }
+
+ private:
+  hipStream_t st_;
+  std::vector<std::pair<int, hipEvent_t>> marks_;
+};
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -403,6 +432,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   std::vector<double> h_om(K), h_rn(K);
   std::vector<int> sel;
   hipEvent_t e0, e1;
+  IterTimer itimer(st);
   SEQX_HIP(hipEventCreate(&e0));
   SEQX_HIP(hipEventCreate(&e1));
   bool converged = false;
@@ -410,11 +440,13 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   try {
     for (it = 1; it <= opt.max_iter; ++it) {
       // 1. products of the new vectors
+      itimer.mark(kDavSigma);
       SEQX_HIP(hipEventRecord(e0, st));
       double* sp_new = w.SP.p + static_cast<long>(S) * ldp;
       sigma_build(m, opt.theory, knew, w.V.p + S * nov, sp_new, tdhf ? sp_new + nov : nullptr, w.sig, st,
                   opt.sigma_chunk, ldp);
       SEQX_HIP(hipEventRecord(e1, st));
+      itimer.mark(kDavProject);
       res.n_sigma += knew;
       const int S1 = S + knew;
       // 2. projected matrices, new columns (column-major, ld = Smax): one pass over
@@ -428,6 +460,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       SEQX_LAUNCH_CHECK();
       S = S1;
       // 3. subspace eigenproblem
+      itimer.mark(kDavSmallEig);
       double* tco = w.coef.p;                          // t (TDHF) or x (CIS): S x K, ld Smax
       double* uco = w.coef.p + static_cast<long>(K) * Smax;  // u (TDHF)
       if (tdhf) {
@@ -450,6 +483,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       }
       SEQX_LAUNCH_CHECK();
       // 4. Ritz vectors and products: rows j of Tv = sum_s t(s, j) V_s, etc.
+      itimer.mark(kDavRitz);
       // [T; U] in one pass over V (t and u are adjacent coefficient columns)
       dgemm(st, false, false, ps * K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.V.p, nov, 0, 0.0, w.Tv.p, nov, 0,
             1, nullptr);
@@ -463,6 +497,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
                          w.PT.p, MU, w.part.p);
       hipLaunchKernelGGL(reduce_rows_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, nbres, w.part.p, w.rn.p);
       SEQX_LAUNCH_CHECK();
+      itimer.mark(kDavCheck);
       d2h(h_rn.data(), w.rn.p, K, st);
       d2h(h_om.data(), om, K, st);
       SEQX_HIP(hipStreamSynchronize(st));
@@ -493,6 +528,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       }
       if (it == opt.max_iter) break;
       // 6. preconditioned residuals of the unconverged roots
+      itimer.mark(kDavPrecond);
       const int nsel = static_cast<int>(sel.size());
       SEQX_HIP(hipMemcpyAsync(w.sel.p, sel.data(), nsel * sizeof(int), hipMemcpyHostToDevice, st));
       hipLaunchKernelGGL(precond_kernel, dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov, tdhf ? 1 : 0,
@@ -500,6 +536,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       SEQX_LAUNCH_CHECK();
       const int nc = tdhf ? 2 * nsel : nsel;
       // 7. collapse onto the best Ritz vectors when the basis would overflow
+      itimer.mark(kDavCollapse);
       if (S + nc > Smax) {
         const int q0 = tdhf ? 2 * K : std::min(2 * K, S);
         // coefficient block Cc (S x q0) = [t u] (TDHF) or the q0 lowest eigenvectors (CIS)
@@ -538,9 +575,11 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
         S = q;
       }
       // 8. orthonormalise and append
+      itimer.mark(kDavOrtho);
       knew = orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V.p, Smax - S);
       if (knew == 0) break;
     }
+    itimer.mark(kDavSigma);
   } catch (...) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -549,6 +588,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   res.iterations = it;
+  itimer.accumulate(res.phase_ms);
   if (!converged) throw Error(kEDavNoConv, "Davidson did not converge in " + std::to_string(opt.max_iter) + " iterations");
 
   // 9. amplitudes, sign convention, properties

@@ -26,7 +26,14 @@ struct DavWork {
   SigmaWork sig;
 };
 
+// Davidson iteration phases timed with HIP events on the solve's stream.
+enum DavPhase {
+  kDavSigma = 0, kDavProject = 1, kDavSmallEig = 2, kDavRitz = 3, kDavCheck = 4, kDavPrecond = 5,
+  kDavCollapse = 6, kDavOrtho = 7, kNumDavPhases = 8
+};
+
 struct DavResult {
+  double phase_ms[kNumDavPhases] = {};
   int iterations = 0;
   long n_sigma = 0;
   double t_sigma_ms = 0.0;

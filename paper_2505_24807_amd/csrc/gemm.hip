@@ -286,7 +286,9 @@ __global__ void reduce_partials_kernel(int nchunks, int ns, int nt, const double
   out[static_cast<long>(s) * ldo + t] = acc;
 }
 
-constexpr long kDotChunk = 8192;
+// split-K chunk of the inner products: short enough that a basis of a few
+// hundred vectors still spreads over thousands of workgroups
+constexpr long kDotChunk = 1024;
 
 }  // namespace
 

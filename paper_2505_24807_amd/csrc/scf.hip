@@ -4,10 +4,12 @@
 // replaced by the identity; the lowest nocc MOs are doubly occupied.
 //   F = H + J(P) - K(P)/2,  P = 2 C_occ C_occ^T
 // Guess: diagonal density (each atom's core charge spread evenly over its AOs),
-// diagonalised once to give the first idempotent density.  Converged when
-// max |F P - P F| <= tol.  The dense eigensolver is rocSOLVER's divide and
-// conquer; every other step is a kernel of this library.  The host reads one
-// scalar (the commutator norm) per iteration.
+// turned into the first idempotent density.  Converged when max |F P - P F| <=
+// tol.  Inside the loop the aufbau density of the (DIIS-extrapolated) Fock
+// matrix comes from SP2 purification (GEMMs only); the orbitals of the
+// converged Fock matrix come from one dense eigensolve (rocSOLVER divide and
+// conquer) at the end.  The host reads the commutator norm once per iteration
+// and two traces per purification step.
 #include <algorithm>
 
 #include "gemm.hpp"
@@ -36,6 +38,122 @@ double read_scalar(const double* d, hipStream_t st) {
   return v;
 }
 
+// Gershgorin bounds of a symmetric matrix: per row lo = F_ii - sum_j!=i |F_ij|,
+// hi = F_ii + sum_j!=i |F_ij|; one block per row
+__global__ void gershgorin_rows_kernel(int n, const double* __restrict__ F, double* __restrict__ lohi) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  const double* row = F + static_cast<long>(i) * n;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256)
+    if (j != i) s += fabs(row[j]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    lohi[2 * i] = row[i] - red[0];
+    lohi[2 * i + 1] = row[i] + red[0];
+  }
+}
+
+// scal[0] = min lo, scal[1] = max hi
+__global__ void bounds_reduce_kernel(int n, const double* __restrict__ lohi, double* __restrict__ scal) {
+  __shared__ double lo[256], hi[256];
+  double a = 1e300, b = -1e300;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    a = fmin(a, lohi[2 * i]);
+    b = fmax(b, lohi[2 * i + 1]);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + h]);
+      hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    scal[0] = lo[0];
+    scal[1] = hi[0];
+  }
+}
+
+// X = (hi I - F) / (hi - lo): spectrum mapped into [0, 1], occupied levels near 1
+__global__ void sp2_init_kernel(int n, const double* __restrict__ F, const double* __restrict__ scal,
+                                double* __restrict__ X) {
+  const long idx = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<long>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  const double lo = scal[0], hi = scal[1];
+  X[idx] = ((i == j ? hi : 0.0) - F[idx]) / (hi - lo);
+}
+
+// out[0] = tr X, out[1] = tr X2 (single block, fixed order)
+__global__ void traces_kernel(int n, const double* __restrict__ X, const double* __restrict__ X2,
+                              double* __restrict__ out) {
+  __shared__ double a[256], b[256];
+  double s = 0.0, t = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    s += X[static_cast<long>(i) * n + i];
+    t += X2[static_cast<long>(i) * n + i];
+  }
+  a[threadIdx.x] = s;
+  b[threadIdx.x] = t;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      a[threadIdx.x] += a[threadIdx.x + h];
+      b[threadIdx.x] += b[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = a[0];
+    out[1] = b[0];
+  }
+}
+
+// Second-order spectral projection (SP2, Niklasson): starting from F mapped into
+// [0, 1], repeatedly apply X^2 or 2X - X^2, whichever keeps the trace closer to
+// the number of occupied orbitals, until X is idempotent.  P = 2 X is the
+// aufbau density of F (lowest `nocc` levels), the same as diagonalising F and
+// occupying its lowest orbitals, without the eigensolver.
+void sp2_density(hipStream_t st, int n, int nocc, const double* F, double* P, ScfWork& w) {
+  const long nn = static_cast<long>(n) * n;
+  w.X2.ensure(nn);
+  double* X = w.FP.p;  // free during purification
+  double* X2 = w.X2.p;
+  hipLaunchKernelGGL(gershgorin_rows_kernel, dim3(n), dim3(256), 0, st, n, F, w.red.p);
+  hipLaunchKernelGGL(bounds_reduce_kernel, dim3(1), dim3(256), 0, st, n, w.red.p, w.scal.p);
+  hipLaunchKernelGGL(sp2_init_kernel, dim3(ceil_div(nn, 256)), dim3(256), 0, st, n, F, w.scal.p, X);
+  SEQX_LAUNCH_CHECK();
+  double e_prev[2] = {1e300, 1e300};
+  for (int it = 0; it < 200; ++it) {
+    dgemm(st, false, false, n, n, n, 1.0, X, n, 0, X, n, 0, 0.0, X2, n, 0, 1, nullptr);
+    hipLaunchKernelGGL(traces_kernel, dim3(1), dim3(256), 0, st, n, X, X2, w.scal.p + 2);
+    double tr[2];
+    SEQX_HIP(hipMemcpyAsync(tr, w.scal.p + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    SEQX_HIP(hipStreamSynchronize(st));
+    const double e = tr[0] - tr[1];  // sum of lambda (1 - lambda) >= 0
+    if (e <= 1e-13 * n || (e < 1e-6 && e >= e_prev[0])) break;
+    e_prev[0] = e_prev[1];
+    e_prev[1] = e;
+    if (std::fabs(tr[1] - nocc) < std::fabs(2.0 * tr[0] - tr[1] - nocc)) {
+      std::swap(X, X2);                                  // X <- X^2
+    } else {
+      axpby(st, nn, -1.0, X2, 2.0, X);                   // X <- 2X - X^2
+    }
+  }
+  // the converged X and X^2 agree to rounding; keep X
+  copy(st, P, X, nn);
+  axpby(st, nn, 0.0, X, 2.0, P);
+}
+
 }  // namespace
 
 void run_scf(DeviceMolecule& m, const ScfOptions& opt, DenseSolver& ds, GWork& gw, ScfWork& w, hipStream_t st) {
@@ -52,7 +170,7 @@ void run_scf(DeviceMolecule& m, const ScfOptions& opt, DenseSolver& ds, GWork& g
   w.B.ensure(nd * nd);
   w.c.ensure(nd);
   w.scal.ensure(4);
-  w.red.ensure(std::max<size_t>(1024, dots_workspace(nd, nd, nn)));
+  w.red.ensure(std::max<size_t>(std::max<size_t>(1024, 2 * static_cast<size_t>(n)), dots_workspace(nd, nd, nn)));
   m.C.ensure(nn);
   m.P.ensure(nn);
   m.eps.ensure(n);
@@ -60,9 +178,13 @@ void run_scf(DeviceMolecule& m, const ScfOptions& opt, DenseSolver& ds, GWork& g
   // first density from the diagonal guess
   guess_density(st, n, m.atom_of_ao.p, m.slot.p, m.elems, m.P.p);
   fock(m, m.P.p, w.G.p, w.F.p, gw, st);
-  copy(st, w.CT.p, w.F.p, nn);
-  ds.eigh(n, w.CT.p, n, m.eps.p);
-  density_from_CT(st, n, o, w.CT.p, m.P.p);
+  if (opt.purify) {
+    sp2_density(st, n, o, w.F.p, m.P.p, w);
+  } else {
+    copy(st, w.CT.p, w.F.p, nn);
+    ds.eigh(n, w.CT.p, n, m.eps.p);
+    density_from_CT(st, n, o, w.CT.p, m.P.p);
+  }
 
   double err = 1e300;
   int it = 0, count = 0;
@@ -91,9 +213,13 @@ void run_scf(DeviceMolecule& m, const ScfOptions& opt, DenseSolver& ds, GWork& g
         Fx = w.FP.p;
       }
     }
-    copy(st, w.CT.p, Fx, nn);
-    ds.eigh(n, w.CT.p, n, m.eps.p);
-    density_from_CT(st, n, o, w.CT.p, m.P.p);
+    if (opt.purify) {
+      sp2_density(st, n, o, Fx, m.P.p, w);
+    } else {
+      copy(st, w.CT.p, Fx, nn);
+      ds.eigh(n, w.CT.p, n, m.eps.p);
+      density_from_CT(st, n, o, w.CT.p, m.P.p);
+    }
   }
   m.commutator = err;
   m.scf_iterations = it;

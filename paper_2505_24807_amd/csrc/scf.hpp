@@ -11,10 +11,11 @@ struct ScfOptions {
   double tol = 1e-10;
   int max_iter = 300;
   int ndiis = 8;
+  bool purify = true;  // density from SP2 purification in the SCF loop (one eigensolve at the end)
 };
 
 struct ScfWork {
-  DBuf<double> G, F, FP, E, CT, Fhist, Ehist, B, c, scal, red;
+  DBuf<double> G, F, FP, E, CT, Fhist, Ehist, B, c, scal, red, X2;
 };
 
 // Fills m.C (row-major [mu][p]), m.eps, m.P; throws Error(kEScfNoConv) on failure.
