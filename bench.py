@@ -5,12 +5,15 @@ RHF SCF, then the Davidson solve for the 10 lowest TDHF roots (tol 1e-5 Eh),
 all through the C ABI of libseqx.  The geometry (24 KB) is handed over from the
 host at the start of each step; every array the method builds lives in HBM.
 
+The timed run uses the mixed mode by default (FP32 transforms, finished with
+FP64 products); the same steps with FP64 transforms follow as the comparison.
 Printed: ONE JSON line with the metric (sigma vectors per second of the whole
 step; time-to-roots alongside), the roofline of the dominant sigma-build kernel
 (HIP events inside the library, per launch) and the CPU oracle timed on a
 bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--precision fp32|fp64]
+                    [--no-fp64-comparison] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -76,11 +79,95 @@ def cpu_baseline(mol, params_eV, k=2):
                       f"{dt:.1f} s; ERI build excluded"}
 
 
+def run_mode(ctx, mol, ref, precision, steps, warmup):
+    """Warm up, then time `steps` whole steps (integrals + SCF + Davidson) in one transform precision."""
+    import torch
+    from paper_2505_24807_amd import seqx
+
+    def step():
+        job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+        job.solve(theory=seqx.TDHF, nroots=NROOTS, tol=TOL, max_iter=400, precision=precision)
+        return job
+
+    for _ in range(warmup):
+        step().free()
+    torch.cuda.synchronize()
+    totals = {"n_sigma": 0, "n_sigma_fp64": 0, "scf": 0.0, "dav": 0.0, "sig": 0.0, "iters": 0, "refine": 0}
+    phase = np.zeros((4, 5))
+    dav_phase = np.zeros(8)
+    ttr, parity = [], []
+    t0 = time.perf_counter()
+    jobs = []
+    for _ in range(steps):
+        jobs.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for job in jobs:
+        st = job.stats()
+        totals["n_sigma"] += st.n_sigma
+        totals["n_sigma_fp64"] += st.n_sigma_fp64
+        totals["refine"] = max(totals["refine"], st.refine_iteration)
+        totals["scf"] += st.t_scf_s + st.t_integrals_s
+        totals["dav"] += st.t_davidson_s
+        totals["sig"] += st.t_sigma_s
+        totals["iters"] += st.dav_iterations
+        phase += np.array([list(st.phase_ms), list(st.phase_launches), list(st.phase_flops), list(st.phase_bytes)])
+        dav_phase += np.array(list(st.dav_phase_ms))
+        t, om = job.history()
+        tt = time_to_roots(t, om, ref)
+        if tt is not None:
+            ttr.append(tt + st.t_scf_s + st.t_integrals_s)
+        if ref is not None:
+            parity.append(float(np.abs(job.results().omega_eV - ref).max()))
+        dims = job.dims()
+        job.free()
+    return {"elapsed": elapsed, "totals": totals, "phase": phase, "dav_phase": dav_phase, "ttr": ttr,
+            "parity": parity, "dims": dims}
+
+
+def summary(r, K):
+    from paper_2505_24807_amd import seqx
+    tot, phase = r["totals"], r["phase"]
+    g = 2
+    return {
+        "value": round(tot["n_sigma"] / r["elapsed"], 2),
+        "ms_per_step": round(1e3 * r["elapsed"] / K, 2),
+        "time_to_roots_s": round(r["elapsed"] / K, 3),
+        "time_to_10_roots_at_1e-4_eV_s": round(float(np.mean(r["ttr"])), 3) if r["ttr"] else None,
+        "parity_max_abs_eV_vs_oracle": max(r["parity"]) if r["parity"] else None,
+        "scf_s": round(tot["scf"] / K, 3), "davidson_s": round(tot["dav"] / K, 3),
+        "sigma_build_vectors_per_s": round(tot["n_sigma"] / tot["sig"], 1),
+        "n_sigma_per_step": tot["n_sigma"] // K, "n_sigma_fp64_per_step": tot["n_sigma_fp64"] // K,
+        "refine_iteration": tot["refine"], "davidson_iterations": tot["iters"] // K,
+        "phase_ms_per_step": {seqx.Stats.PHASES[i]: round(phase[0, i] / K, 2) for i in range(5)},
+        "contraction_GBps": round(phase[3, g] / (phase[0, g] * 1e-3) / 1e9, 1),
+        "davidson_phase_ms_per_step": {seqx.Stats.DAV_PHASES[i]: round(r["dav_phase"][i] / K, 1) for i in range(8)},
+    }
+
+
+def roofline_of(r, dtype):
+    """Dominant sigma-build kernel: the transform phase with the most device time (HIP events per launch)."""
+    from paper_2505_24807_amd import seqx
+    phase = r["phase"]
+    p = max([0, 1, 3, 4], key=lambda i: phase[0, i])
+    ms, launches, flops = phase[0, p], phase[1, p], phase[2, p]
+    avg_s = ms * 1e-3 / launches
+    achieved = flops / launches / avg_s / 1e12
+    ctype = "double" if dtype == "fp64" else "float"
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[dtype], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[dtype], 4), "traffic": None,
+            "kernel": f"gemm128_kernel<{ctype}> ({seqx.Stats.PHASES[p]})",
+            "flops_per_launch": flops / launches, "avg_launch_ms": ms / launches}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
+                    help="transform precision of the timed run (fp32: mixed mode finishing in FP64)")
+    ap.add_argument("--no-fp64-comparison", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-vectors", type=int, default=2)
     args = ap.parse_args()
@@ -102,75 +189,28 @@ def main():
     ctx.set_params(*seqx.params_table(pr))
     mol = molecules.workload_water330()
     ref = _golden()
-
-    def step():
-        job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
-        job.solve(theory=seqx.TDHF, nroots=NROOTS, tol=TOL, max_iter=400)
-        return job
-
-    for _ in range(args.warmup):
-        step().free()
-    torch.cuda.synchronize()
-    totals = {"n_sigma": 0, "scf": 0.0, "dav": 0.0, "sig": 0.0, "iters": 0}
-    phase = np.zeros((4, 5))
-    dav_phase = np.zeros(8)
-    ttr, parity = [], []
-    t0 = time.perf_counter()
-    jobs = []
-    for _ in range(args.steps):
-        job = step()
-        jobs.append(job)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for job in jobs:
-        st = job.stats()
-        totals["n_sigma"] += st.n_sigma
-        totals["scf"] += st.t_scf_s + st.t_integrals_s
-        totals["dav"] += st.t_davidson_s
-        totals["sig"] += st.t_sigma_s
-        totals["iters"] += st.dav_iterations
-        phase += np.array([list(st.phase_ms), list(st.phase_launches), list(st.phase_flops), list(st.phase_bytes)])
-        dav_phase += np.array(list(st.dav_phase_ms))
-        t, om = job.history()
-        tt = time_to_roots(t, om, ref)
-        if tt is not None:
-            ttr.append(tt + st.t_scf_s + st.t_integrals_s)
-        if ref is not None:
-            parity.append(float(np.abs(job.results().omega_eV - ref).max()))
-        n, o, v = job.dims()
-        job.free()
     K = args.steps
-    value = totals["n_sigma"] / elapsed
-    # dominant sigma-build kernel: the GEMM phase with the most device time
-    gemm_phases = [0, 1, 3, 4]
-    p = max(gemm_phases, key=lambda i: phase[0, i])
-    ms, launches, flops = phase[0, p], phase[1, p], phase[2, p]
-    avg_s = ms * 1e-3 / launches
-    achieved = flops / launches / avg_s / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK["fp64"], 4), "traffic": None,
-                "kernel": f"dgemm_kernel<2,2,2,2> ({seqx.Stats.PHASES[p]})",
-                "flops_per_launch": flops / launches, "avg_launch_ms": ms / launches}
-    g = 2
-    g_gbs = phase[3, g] / (phase[0, g] * 1e-3) / 1e9
+    prec = seqx.FP32 if args.precision == "fp32" else seqx.FP64
+    main_run = run_mode(ctx, mol, ref, prec, K, args.warmup)
+    n, o, v = main_run["dims"]
+    s = summary(main_run, K)
+    mode = ("FP32 transforms (FP64 contraction sums, FP64 subspace), finished with FP64 products"
+            if prec == seqx.FP32 else "FP64 transforms")
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "sigma-vectors/s", "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / K, 2), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "metric": METRIC, "value": s.pop("value"), "unit": "sigma-vectors/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": s.pop("ms_per_step"), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision.replace("fp", "f"), "data": "synthetic",
         "config": {"workload": "(H2O)330 water cluster, 990 atoms, 1980 AOs (1320 occ, 660 virt), TDHF, "
-                               "10 lowest singlet roots, residual tol 1e-5 Eh, FP64 transforms, gap guess",
+                               f"10 lowest singlet roots, residual tol 1e-5 Eh, {mode}, gap guess",
                    "seed": 330, "nov": o * v},
-        "time_to_roots_s": round(elapsed / K, 3),
-        "time_to_10_roots_at_1e-4_eV_s": round(float(np.mean(ttr)), 3) if ttr else None,
-        "parity_max_abs_eV_vs_oracle": max(parity) if parity else None,
-        "scf_s": round(totals["scf"] / K, 3), "davidson_s": round(totals["dav"] / K, 3),
-        "sigma_build_vectors_per_s": round(totals["n_sigma"] / totals["sig"], 1),
-        "n_sigma_per_step": totals["n_sigma"] // K, "davidson_iterations": totals["iters"] // K,
-        "phase_ms_per_step": {seqx.Stats.PHASES[i]: round(phase[0, i] / K, 2) for i in range(5)},
-        "contraction_GBps": round(g_gbs, 1),
-        "davidson_phase_ms_per_step": {seqx.Stats.DAV_PHASES[i]: round(dav_phase[i] / K, 1) for i in range(8)},
-        "roofline": roofline,
     }
+    out.update(s)
+    out["roofline"] = roofline_of(main_run, args.precision)
+    if prec != seqx.FP64 and not args.no_fp64_comparison:
+        r64 = run_mode(ctx, mol, ref, seqx.FP64, K, args.warmup)
+        s64 = summary(r64, K)
+        s64["roofline"] = roofline_of(r64, "fp64")
+        out["fp64_comparison"] = s64
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mol, pr, args.cpu_vectors)
     print(json.dumps(out))

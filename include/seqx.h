@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SEQX_ABI_VERSION 1
+#define SEQX_ABI_VERSION 2
 #define SEQX_NPARAM 11 /* per-element parameters, order below */
 
 typedef struct seqx_ctx seqx_ctx; /* one device + one stream */
@@ -60,7 +60,14 @@ typedef enum {
 typedef enum { SEQX_CIS = 0, SEQX_TDHF = 1 } seqx_theory;
 
 /* Arithmetic of the dense MO<->AO transforms inside the sigma build.  Subspace
- * projection, Gram-Schmidt, the small eigensolves and the SCF stay FP64. */
+ * projection, Gram-Schmidt, the small eigensolves and the SCF stay FP64.
+ * SEQX_FP32: C, V and the AO matrices stored in FP32, transforms on the FP32
+ * matrix cores with FP32 accumulation; the NDDO contraction sums in FP64 and
+ * the (eps_a - eps_i) V term is added in FP64 (mixed-precision mode of the
+ * paper's outlook).  A seqx_solve in FP32 restarts from its Ritz vectors with
+ * FP64 products once its residuals reach max(tol, the FP32 rounding floor) or
+ * stop improving, and converges to tol in FP64, so its roots carry FP64
+ * accuracy.  SEQX_BF16 and SEQX_BF16X3 are reserved and return SEQX_E_ARG. */
 typedef enum { SEQX_FP64 = 0, SEQX_FP32 = 1, SEQX_BF16 = 2, SEQX_BF16X3 = 3 } seqx_precision;
 
 typedef enum { SEQX_GUESS_GAP = 0, SEQX_GUESS_LEARNED = 1, SEQX_GUESS_USER = 2 } seqx_guess;
@@ -114,6 +121,11 @@ typedef struct {
    * vectors and residuals, 4 convergence check (host read), 5 preconditioner,
    * 6 subspace collapse, 7 orthonormalisation. */
   double dav_phase_ms[8];
+  /* Mixed-precision solves (precision != SEQX_FP64): sigma vectors formed with
+   * FP64 transforms, and the iteration at which the solve restarted from its
+   * Ritz vectors with FP64 products (0 when it never ran in low precision). */
+  int64_t n_sigma_fp64;
+  int32_t refine_iteration;
 } seqx_stats;
 
 /* Version of this header the library was built with (SEQX_ABI_VERSION). */
@@ -166,7 +178,8 @@ seqx_status seqx_integrals(const seqx_job* job, int32_t mol, double* out, size_t
 /* Matrix-free products (Eqs. 8-9) for k host vectors V[k][nocc][nvirt]:
  *   theory CIS : out1 = A V            (out2 unused, may be NULL)
  *   theory TDHF: out1 = (A+B) V, out2 = (A-B) V
- * in hartree, with the transforms in `precision`.  Blocking host copy. */
+ * in hartree, with the transforms in `precision` (SEQX_FP64 or SEQX_FP32; the
+ * others return SEQX_E_ARG).  Blocking host copy. */
 seqx_status seqx_sigma(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* V,
                        double* out1, double* out2, int32_t precision);
 /* Same on device buffers (ordered on the context stream, no host sync). */

@@ -350,6 +350,15 @@ seqx_status seqx_integrals(const seqx_job* job, int32_t mol, double* out, size_t
   });
 }
 
+namespace {
+void check_precision(int32_t precision) {
+  if (precision == SEQX_FP64 || precision == SEQX_FP32) return;
+  if (precision == SEQX_BF16 || precision == SEQX_BF16X3)
+    throw Error(kEArg, "BF16 transforms are not available in this build");
+  throw Error(kEArg, "unknown precision");
+}
+}  // namespace
+
 seqx_status seqx_sigma_device(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* dV, double* dout1,
                               double* dout2, int32_t precision) {
   if (!job) return SEQX_E_ARG;
@@ -357,8 +366,8 @@ seqx_status seqx_sigma_device(seqx_job* job, int32_t mol, int32_t theory, int32_
     DeviceMolecule& m = scf_mol_of(job, mol);
     if (theory != SEQX_CIS && theory != SEQX_TDHF) throw Error(kEArg, "theory must be CIS or TDHF");
     if (k <= 0 || !dV || !dout1 || (theory == SEQX_TDHF && !dout2)) throw Error(kEArg, "bad sigma arguments");
-    if (precision != SEQX_FP64) throw Error(kEArg, "only SEQX_FP64 transforms are available in this build");
-    sigma_build(m, theory, k, dV, dout1, dout2, job->dw.sig, job->ctx->stream);
+    check_precision(precision);
+    sigma_build(m, theory, k, dV, dout1, dout2, job->dw.sig, job->ctx->stream, 32, 0, precision);
   });
 }
 
@@ -369,12 +378,12 @@ seqx_status seqx_sigma(seqx_job* job, int32_t mol, int32_t theory, int32_t k, co
     DeviceMolecule& m = scf_mol_of(job, mol);
     if (theory != SEQX_CIS && theory != SEQX_TDHF) throw Error(kEArg, "theory must be CIS or TDHF");
     if (k <= 0 || !V || !out1 || (theory == SEQX_TDHF && !out2)) throw Error(kEArg, "bad sigma arguments");
-    if (precision != SEQX_FP64) throw Error(kEArg, "only SEQX_FP64 transforms are available in this build");
+    check_precision(precision);
     hipStream_t st = job->ctx->stream;
     const size_t n = static_cast<size_t>(k) * m.nocc * m.nvirt;
     DBuf<double> dV(n), d1(n), d2(theory == SEQX_TDHF ? n : 0);
     SEQX_HIP(hipMemcpyAsync(dV.p, V, n * sizeof(double), hipMemcpyHostToDevice, st));
-    sigma_build(m, theory, k, dV.p, d1.p, d2.p, job->dw.sig, st);
+    sigma_build(m, theory, k, dV.p, d1.p, d2.p, job->dw.sig, st, 32, 0, precision);
     d2h(out1, d1.p, n, st);
     if (theory == SEQX_TDHF) d2h(out2, d2.p, n, st);
     SEQX_HIP(hipStreamSynchronize(st));
@@ -385,7 +394,7 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
   if (!job || !opts) return SEQX_E_ARG;
   return guarded(job->ctx, [&] {
     if (opts->theory != SEQX_CIS && opts->theory != SEQX_TDHF) throw Error(kEArg, "theory must be CIS or TDHF");
-    if (opts->precision != SEQX_FP64) throw Error(kEArg, "only SEQX_FP64 transforms are available in this build");
+    check_precision(opts->precision);
     if (opts->guess == SEQX_GUESS_LEARNED) throw Error(kEArg, "learned guess needs a loaded network");
     hipStream_t st = job->ctx->stream;
     DavOptions d;
@@ -394,9 +403,12 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
     d.tol = opts->tol > 0 ? opts->tol : 1e-6;
     d.max_iter = opts->max_iter > 0 ? opts->max_iter : 100;
     d.max_sub = opts->max_subspace;
+    d.precision = opts->precision;
     DBuf<double> guess;
     job->solved = false;
     job->stats.n_sigma = 0;
+    job->stats.n_sigma_fp64 = 0;
+    job->stats.refine_iteration = 0;
     for (double& x : job->stats.dav_phase_ms) x = 0.0;
     job->dw.sig.timer.reset();
     job->stats.dav_iterations = 0;
@@ -434,6 +446,8 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
       m.hist_omega.clear();
       for (const auto& w : r.omega_iter) m.hist_omega.insert(m.hist_omega.end(), w.begin(), w.end());
       job->stats.n_sigma += r.n_sigma;
+      job->stats.n_sigma_fp64 += r.n_sigma_fp64;
+      job->stats.refine_iteration = std::max(job->stats.refine_iteration, r.refine_iter);
       for (int p = 0; p < kNumDavPhases; ++p) job->stats.dav_phase_ms[p] += r.phase_ms[p];
       job->stats.dav_iterations = std::max(job->stats.dav_iterations, r.iterations);
       job->stats.t_sigma_s += r.t_sigma_ms * 1e-3;

@@ -435,6 +435,63 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   IterTimer itimer(st);
   SEQX_HIP(hipEventCreate(&e0));
   SEQX_HIP(hipEventCreate(&e1));
+  // Collapse the basis of size S onto the span of the best Ritz vectors
+  // (TDHF: the 2K vectors t, u; CIS: the 2K lowest eigenvectors); V stays
+  // orthonormal.  products: carry the products and projected matrices along
+  // (else the caller recomputes them).  Returns the new basis size.
+  auto collapse = [&](int S, bool products) -> int {
+    double* tco = w.coef.p;
+    const int q0 = tdhf ? 2 * K : std::min(2 * K, S);
+    // coefficient block Cc (S x q0) = [t u] (TDHF) or the q0 lowest eigenvectors (CIS)
+    double* Cc = w.Q.p;
+    if (tdhf) {
+      copy(st, Cc, tco, static_cast<long>(2 * K) * Smax);  // t and u are adjacent columns
+    } else {
+      copy(st, Cc, w.Hs.p, static_cast<long>(q0) * Smax);
+    }
+    // orthonormal columns: Q = Cc Qg diag(lam^-1/2) over the kept eigenpairs of Cc^T Cc
+    dgemm_cm(st, true, false, q0, q0, S, 1.0, Cc, Smax, Cc, Smax, 0.0, w.G.p, q0);
+    ds.eigh(q0, w.G.p, q0, w.w2.p);
+    std::vector<double> lam(q0);
+    d2h(lam.data(), w.w2.p, q0, st);
+    SEQX_HIP(hipStreamSynchronize(st));
+    int j0 = 0;
+    while (j0 < q0 && !(lam[j0] > 1e-12 * lam[q0 - 1])) ++j0;
+    const int q = q0 - j0;
+    hipLaunchKernelGGL(invsqrt_cols_kernel, dim3(q), dim3(64), 0, st, w.G.p, q0, q0, j0, w.w2.p);
+    dgemm_cm(st, false, false, S, q, q0, 1.0, Cc, Smax, w.G.p + static_cast<long>(j0) * q0, q0, 0.0, w.Lm.p,
+             Smax);  // Qc (S x q) in Lm
+    double* Qc = w.Lm.p;
+    dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.V.p, nov, 0, 0.0, w.scratch.p, nov, 0, 1,
+          nullptr);
+    copy(st, w.V.p, w.scratch.p, static_cast<long>(q) * nov);
+    if (!products) return q;
+    for (int p = 0; p < ps; ++p)  // keep the interleaved product rows interleaved
+      dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.SP.p + p * nov, ldp, 0, 0.0,
+            w.scratch.p + p * nov, ldp, 0, 1, nullptr);
+    copy(st, w.SP.p, w.scratch.p, static_cast<long>(q) * ldp);
+    for (double* Mx : {w.Mp.p, tdhf ? w.Mm.p : nullptr}) {
+      if (!Mx) continue;
+      dgemm_cm(st, false, false, S, q, S, 1.0, Mx, Smax, Qc, Smax, 0.0, w.Tmp.p, Smax);
+      dgemm_cm(st, true, false, q, q, S, 1.0, Qc, Smax, w.Tmp.p, Smax, 0.0, w.Hs.p, Smax);
+      copy(st, Mx, w.Hs.p, static_cast<long>(q) * Smax);
+    }
+    return q;
+  };
+
+  int prec = opt.precision;
+  double floor_low = 0.0, rbest = 1e300;
+  int stall = 0;
+  if (prec != kPrecFP64) {
+    // rounding floor of the FP32 products: FP32 sums over n terms carry a
+    // relative error of about sqrt(n) u (u = 2^-24), on a scale set by the
+    // largest orbital-energy gap; four times that
+    max_abs(st, nov, w.d.p, w.rn.p, w.ws.p);
+    double dmax = 0.0;
+    d2h(&dmax, w.rn.p, 1, st);
+    SEQX_HIP(hipStreamSynchronize(st));
+    floor_low = 4.0 * std::sqrt(static_cast<double>(m.nao)) * std::ldexp(1.0, -24) * dmax;
+  }
   bool converged = false;
   int it = 0;
   try {
@@ -444,10 +501,11 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       SEQX_HIP(hipEventRecord(e0, st));
       double* sp_new = w.SP.p + static_cast<long>(S) * ldp;
       sigma_build(m, opt.theory, knew, w.V.p + S * nov, sp_new, tdhf ? sp_new + nov : nullptr, w.sig, st,
-                  opt.sigma_chunk, ldp);
+                  opt.sigma_chunk, ldp, prec);
       SEQX_HIP(hipEventRecord(e1, st));
       itimer.mark(kDavProject);
       res.n_sigma += knew;
+      if (prec == kPrecFP64) res.n_sigma_fp64 += knew;
       const int S1 = S + knew;
       // 2. projected matrices, new columns (column-major, ld = Smax): one pass over
       // V for (A+B) and (A-B) together, since their rows are interleaved
@@ -518,15 +576,40 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
                      it, S, knew, rmax, h_om[0] * kHartreeEV, h_om[K - 1] * kHartreeEV, res.t_iter.back());
       }
       sel.clear();
+      double rmax = 0.0;
       for (int j = 0; j < K; ++j) {
         if (!std::isfinite(h_rn[j]) || !std::isfinite(h_om[j])) throw Error(kEDavNoConv, "Davidson produced NaN");
         if (h_rn[j] > opt.tol) sel.push_back(j);
+        rmax = std::max(rmax, h_rn[j]);
       }
-      if (sel.empty()) {
+      if (prec == kPrecFP64 && sel.empty()) {
         converged = true;
         break;
       }
       if (it == opt.max_iter) break;
+      if (prec != kPrecFP64) {
+        // Mixed-precision phase: the residuals cannot fall much below the
+        // rounding floor of the low-precision products.  Restart from the
+        // Ritz vectors with FP64 products once every root is below
+        // max(tol, floor), or once the largest residual, within 4x of the
+        // floor, has not halved for four iterations.
+        if (rmax < 4.0 * floor_low) {
+          stall = rmax < 0.5 * rbest ? 0 : stall + 1;
+          rbest = std::min(rbest, rmax);
+        }
+        if (rmax <= std::max(opt.tol, floor_low) || stall >= 4) {
+          if (log_enabled())
+            std::fprintf(stderr, "{\"refine_after_iter\": %d, \"max_residual\": %.3e, \"floor\": %.3e}\n", it, rmax,
+                         floor_low);
+          itimer.mark(kDavCollapse);
+          S = collapse(S, false);
+          knew = S;
+          S = 0;
+          prec = kPrecFP64;
+          res.refine_iter = it + 1;
+          continue;
+        }
+      }
       // 6. preconditioned residuals of the unconverged roots
       itimer.mark(kDavPrecond);
       const int nsel = static_cast<int>(sel.size());
@@ -537,43 +620,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       const int nc = tdhf ? 2 * nsel : nsel;
       // 7. collapse onto the best Ritz vectors when the basis would overflow
       itimer.mark(kDavCollapse);
-      if (S + nc > Smax) {
-        const int q0 = tdhf ? 2 * K : std::min(2 * K, S);
-        // coefficient block Cc (S x q0) = [t u] (TDHF) or the q0 lowest eigenvectors (CIS)
-        double* Cc = w.Q.p;
-        if (tdhf) {
-          copy(st, Cc, tco, static_cast<long>(2 * K) * Smax);  // t and u are adjacent columns
-        } else {
-          copy(st, Cc, w.Hs.p, static_cast<long>(q0) * Smax);
-        }
-        // orthonormal columns: Q = Cc Qg diag(lam^-1/2) over the kept eigenpairs of Cc^T Cc
-        dgemm_cm(st, true, false, q0, q0, S, 1.0, Cc, Smax, Cc, Smax, 0.0, w.G.p, q0);
-        ds.eigh(q0, w.G.p, q0, w.w2.p);
-        std::vector<double> lam(q0);
-        d2h(lam.data(), w.w2.p, q0, st);
-        SEQX_HIP(hipStreamSynchronize(st));
-        int j0 = 0;
-        while (j0 < q0 && !(lam[j0] > 1e-12 * lam[q0 - 1])) ++j0;
-        const int q = q0 - j0;
-        hipLaunchKernelGGL(invsqrt_cols_kernel, dim3(q), dim3(64), 0, st, w.G.p, q0, q0, j0, w.w2.p);
-        dgemm_cm(st, false, false, S, q, q0, 1.0, Cc, Smax, w.G.p + static_cast<long>(j0) * q0, q0, 0.0, w.Lm.p,
-                 Smax);  // Qc (S x q) in Lm
-        double* Qc = w.Lm.p;
-        dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.V.p, nov, 0, 0.0, w.scratch.p, nov, 0,
-              1, nullptr);
-        copy(st, w.V.p, w.scratch.p, static_cast<long>(q) * nov);
-        for (int p = 0; p < ps; ++p)  // keep the interleaved product rows interleaved
-          dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.SP.p + p * nov, ldp, 0, 0.0,
-                w.scratch.p + p * nov, ldp, 0, 1, nullptr);
-        copy(st, w.SP.p, w.scratch.p, static_cast<long>(q) * ldp);
-        for (double* Mx : {w.Mp.p, tdhf ? w.Mm.p : nullptr}) {
-          if (!Mx) continue;
-          dgemm_cm(st, false, false, S, q, S, 1.0, Mx, Smax, Qc, Smax, 0.0, w.Tmp.p, Smax);
-          dgemm_cm(st, true, false, q, q, S, 1.0, Qc, Smax, w.Tmp.p, Smax, 0.0, w.Hs.p, Smax);
-          copy(st, Mx, w.Hs.p, static_cast<long>(q) * Smax);
-        }
-        S = q;
-      }
+      if (S + nc > Smax) S = collapse(S, true);
       // 8. orthonormalise and append
       itimer.mark(kDavOrtho);
       knew = orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V.p, Smax - S);

@@ -16,6 +16,7 @@ struct DavOptions {
   int max_iter = 100;
   int max_sub = 0;     // subspace cap (vectors)
   int sigma_chunk = 32;
+  int precision = 0;   // SigmaPrecision of the transforms; the run finishes with FP64 products
   const double* guess = nullptr;  // device [nguess][nov] (user / learned guess), or null for the gap guess
   int nguess = 0;
 };
@@ -36,6 +37,8 @@ struct DavResult {
   double phase_ms[kNumDavPhases] = {};
   int iterations = 0;
   long n_sigma = 0;
+  long n_sigma_fp64 = 0;   // products formed with FP64 transforms
+  int refine_iter = 0;     // iteration whose products were the first FP64 ones after a mixed-precision phase
   double t_sigma_ms = 0.0;
   std::vector<double> t_iter;                 // wall seconds at the end of each iteration
   std::vector<std::vector<double>> omega_iter;  // Ritz values (hartree) per iteration

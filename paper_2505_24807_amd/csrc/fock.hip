@@ -15,37 +15,38 @@ namespace seqx {
 
 namespace {
 
+template <class TR>
 __global__ void pack_kernel(int k, int np, int n, const int* __restrict__ pi_mu, const int* __restrict__ pi_nu,
-                            const double* __restrict__ R, long sR, double* __restrict__ r) {
+                            const TR* __restrict__ R, long sR, double* __restrict__ r) {
   const int P = blockIdx.x * blockDim.x + threadIdx.x;
   const int I = blockIdx.y;
   if (P >= np) return;
-  const double* Rv = R + I * sR;
+  const TR* Rv = R + I * sR;
   const int mu = pi_mu[P], nu = pi_nu[P];
-  r[static_cast<long>(I) * np + P] =
-      (mu == nu) ? Rv[static_cast<long>(mu) * n + mu] : Rv[static_cast<long>(mu) * n + nu] + Rv[static_cast<long>(nu) * n + mu];
+  const double a = Rv[static_cast<long>(mu) * n + nu], b = Rv[static_cast<long>(nu) * n + mu];
+  r[static_cast<long>(I) * np + P] = (mu == nu) ? a : a + b;
 }
 
-template <int NA, int NB, int MODE>
+template <int NA, int NB, int MODE, class TR, class TF>
 __global__ void __launch_bounds__(128) exchange_pair_kernel(int npairs, const int2* __restrict__ pairs,
                                                             const int* __restrict__ ao_off, const int* __restrict__ pi_off,
                                                             const double* __restrict__ W, int ldw,
-                                                            const double* __restrict__ R, long sR, int n,
-                                                            double* __restrict__ F1, double* __restrict__ F2, long sF,
+                                                            const TR* __restrict__ R, long sR, int n,
+                                                            TF* __restrict__ F1, TF* __restrict__ F2, long sF,
                                                             double cK, double cKa) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
   const int I = blockIdx.y;
   const int A = pairs[p].x, B = pairs[p].y;
   const int oa = ao_off[A], ob = ao_off[B];
-  const double* Rv = R + I * sR;
+  const TR* Rv = R + I * sR;
   double S[NA][NB], D[NA][NB];
 #pragma unroll
   for (int i = 0; i < NA; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const double rab = Rv[static_cast<long>(oa + i) * n + ob + j];
-      const double rba = Rv[static_cast<long>(ob + j) * n + oa + i];
+      const double rab = static_cast<double>(Rv[static_cast<long>(oa + i) * n + ob + j]);
+      const double rba = static_cast<double>(Rv[static_cast<long>(ob + j) * n + oa + i]);
       S[i][j] = 0.5 * (rab + rba);
       D[i][j] = 0.5 * (rab - rba);
     }
@@ -84,8 +85,8 @@ __global__ void __launch_bounds__(128) exchange_pair_kernel(int npairs, const in
       }
     }
   }
-  double* f1 = F1 + I * sF;
-  double* f2 = (MODE == kTwo) ? F2 + I * sF : nullptr;
+  TF* f1 = F1 + I * sF;
+  TF* f2 = (MODE == kTwo) ? F2 + I * sF : nullptr;
 #pragma unroll
   for (int i = 0; i < NA; ++i)
 #pragma unroll
@@ -93,16 +94,16 @@ __global__ void __launch_bounds__(128) exchange_pair_kernel(int npairs, const in
       const long ab = static_cast<long>(oa + i) * n + ob + j;
       const long ba = static_cast<long>(ob + j) * n + oa + i;
       if (MODE == kTwo) {
-        f1[ab] = cK * KS[i][j];
-        f1[ba] = cK * KS[i][j];
-        f2[ab] = cKa * KD[i][j];
-        f2[ba] = -cKa * KD[i][j];
+        f1[ab] = static_cast<TF>(cK * KS[i][j]);
+        f1[ba] = static_cast<TF>(cK * KS[i][j]);
+        f2[ab] = static_cast<TF>(cKa * KD[i][j]);
+        f2[ba] = static_cast<TF>(-cKa * KD[i][j]);
       } else if (MODE == kSum) {
-        f1[ab] = cK * KS[i][j] + cKa * KD[i][j];
-        f1[ba] = cK * KS[i][j] - cKa * KD[i][j];
+        f1[ab] = static_cast<TF>(cK * KS[i][j] + cKa * KD[i][j]);
+        f1[ba] = static_cast<TF>(cK * KS[i][j] - cKa * KD[i][j]);
       } else {
-        f1[ab] = cK * KS[i][j];
-        f1[ba] = cK * KS[i][j];
+        f1[ab] = static_cast<TF>(cK * KS[i][j]);
+        f1[ba] = static_cast<TF>(cK * KS[i][j]);
       }
     }
 }
@@ -115,23 +116,23 @@ __device__ inline double g1(const Elem& e, int m, int n) {
 }
 __device__ inline double h1(const Elem& e, int m, int n) { return (m == 0 || n == 0) ? e.hsp : e.hpp; }
 
-template <int MODE>
+template <int MODE, class TR, class TF>
 __global__ void diag_block_kernel(int natoms, int k, const int* __restrict__ slot, const int* __restrict__ ao_off,
                                   const int* __restrict__ pi_off, const Elem* __restrict__ elems,
-                                  const double* __restrict__ J, const double* __restrict__ R, long sR, int n,
-                                  double* __restrict__ F1, double* __restrict__ F2, long sF, double cJ, double cK,
+                                  const double* __restrict__ J, const TR* __restrict__ R, long sR, int n,
+                                  TF* __restrict__ F1, TF* __restrict__ F2, long sF, double cJ, double cK,
                                   double cKa) {
   const int A = blockIdx.x * blockDim.x + threadIdx.x;
   const int I = blockIdx.y;
   if (A >= natoms) return;
   const Elem e = elems[slot[A]];
   const int na = e.nao, o = ao_off[A], po = pi_off[A];
-  const double* Rv = R + I * sR;
+  const TR* Rv = R + I * sR;
   double X[4][4];
   for (int i = 0; i < na; ++i)
-    for (int j = 0; j < na; ++j) X[i][j] = Rv[static_cast<long>(o + i) * n + o + j];
-  double* f1 = F1 + I * sF;
-  double* f2 = (MODE == kTwo) ? F2 + I * sF : nullptr;
+    for (int j = 0; j < na; ++j) X[i][j] = static_cast<double>(Rv[static_cast<long>(o + i) * n + o + j]);
+  TF* f1 = F1 + I * sF;
+  TF* f2 = (MODE == kTwo) ? F2 + I * sF : nullptr;
   for (int m = 0; m < na; ++m)
     for (int nn = 0; nn < na; ++nn) {
       const double S = 0.5 * (X[m][nn] + X[nn][m]), Dv = 0.5 * (X[m][nn] - X[nn][m]);
@@ -152,58 +153,72 @@ __global__ void diag_block_kernel(int natoms, int k, const int* __restrict__ slo
       const double jv = J[static_cast<long>(po + (na == 1 ? 0 : pair_index(m, nn))) * k + I];
       const long idx = static_cast<long>(o + m) * n + o + nn;
       if (MODE == kTwo) {
-        f1[idx] = cJ * jv + cK * kS;
-        f2[idx] = cKa * kD;
+        f1[idx] = static_cast<TF>(cJ * jv + cK * kS);
+        f2[idx] = static_cast<TF>(cKa * kD);
       } else if (MODE == kSum) {
-        f1[idx] = cJ * jv + cK * kS + cKa * kD;
+        f1[idx] = static_cast<TF>(cJ * jv + cK * kS + cKa * kD);
       } else {
-        f1[idx] = cJ * jv + cK * kS;
+        f1[idx] = static_cast<TF>(cJ * jv + cK * kS);
       }
     }
 }
 
-template <int MODE>
-void launch_pairs(const DeviceMolecule& m, int k, const double* R, long sR, double* F1, double* F2, long sF, double cK,
-                  double cKa, hipStream_t st) {
+template <int MODE, class TR, class TF>
+void launch_pairs(const DeviceMolecule& m, int k, const TR* R, long sR, TF* F1, TF* F2, long sF, double cK, double cKa,
+                  hipStream_t st) {
   const int n = m.nao;
   if (m.npairs[0])
-    hipLaunchKernelGGL((exchange_pair_kernel<4, 4, MODE>), dim3(ceil_div(m.npairs[0], 128), k), dim3(128), 0, st,
-                       m.npairs[0], m.pairs[0].p, m.ao_off.p, m.pi_off.p, m.W.p, m.np, R, sR, n, F1, F2, sF, cK, cKa);
+    hipLaunchKernelGGL((exchange_pair_kernel<4, 4, MODE, TR, TF>), dim3(ceil_div(m.npairs[0], 128), k), dim3(128), 0,
+                       st, m.npairs[0], m.pairs[0].p, m.ao_off.p, m.pi_off.p, m.W.p, m.np, R, sR, n, F1, F2, sF, cK,
+                       cKa);
   if (m.npairs[1])
-    hipLaunchKernelGGL((exchange_pair_kernel<4, 1, MODE>), dim3(ceil_div(m.npairs[1], 128), k), dim3(128), 0, st,
-                       m.npairs[1], m.pairs[1].p, m.ao_off.p, m.pi_off.p, m.W.p, m.np, R, sR, n, F1, F2, sF, cK, cKa);
+    hipLaunchKernelGGL((exchange_pair_kernel<4, 1, MODE, TR, TF>), dim3(ceil_div(m.npairs[1], 128), k), dim3(128), 0,
+                       st, m.npairs[1], m.pairs[1].p, m.ao_off.p, m.pi_off.p, m.W.p, m.np, R, sR, n, F1, F2, sF, cK,
+                       cKa);
   if (m.npairs[2])
-    hipLaunchKernelGGL((exchange_pair_kernel<1, 1, MODE>), dim3(ceil_div(m.npairs[2], 128), k), dim3(128), 0, st,
-                       m.npairs[2], m.pairs[2].p, m.ao_off.p, m.pi_off.p, m.W.p, m.np, R, sR, n, F1, F2, sF, cK, cKa);
+    hipLaunchKernelGGL((exchange_pair_kernel<1, 1, MODE, TR, TF>), dim3(ceil_div(m.npairs[2], 128), k), dim3(128), 0,
+                       st, m.npairs[2], m.pairs[2].p, m.ao_off.p, m.pi_off.p, m.W.p, m.np, R, sR, n, F1, F2, sF, cK,
+                       cKa);
+}
+
+template <class TR, class TF>
+void build_G_any(const DeviceMolecule& m, int k, const TR* R, long sR, TF* F1, TF* F2, long sF, GMode mode, double cJ,
+                 double cK, double cKa, GWork& w, hipStream_t st) {
+  const int np = m.np, n = m.nao;
+  w.r.ensure(static_cast<size_t>(k) * np);
+  w.J.ensure(static_cast<size_t>(k) * np);
+  hipLaunchKernelGGL(pack_kernel<TR>, dim3(ceil_div(np, 256), k), dim3(256), 0, st, k, np, n, m.pi_mu.p, m.pi_nu.p, R,
+                     sR, w.r.p);
+  SEQX_LAUNCH_CHECK();
+  // J[np][k] = W (np x np) * r^T ; r stored [k][np]; FP64 whatever the storage type of R and F
+  dgemm(st, false, true, np, k, np, 1.0, m.W.p, np, 0, w.r.p, np, 0, 0.0, w.J.p, k, 0, 1, nullptr);
+  const dim3 dgrid(ceil_div(m.natoms, 64), k);
+  if (mode == kTwo) {
+    hipLaunchKernelGGL((diag_block_kernel<kTwo, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p,
+                       m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
+    launch_pairs<kTwo>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
+  } else if (mode == kSum) {
+    hipLaunchKernelGGL((diag_block_kernel<kSum, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p,
+                       m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
+    launch_pairs<kSum>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
+  } else {
+    hipLaunchKernelGGL((diag_block_kernel<kSymm, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p,
+                       m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
+    launch_pairs<kSymm>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
+  }
+  SEQX_LAUNCH_CHECK();
 }
 
 }  // namespace
 
 void build_G(const DeviceMolecule& m, int k, const double* R, long sR, double* F1, double* F2, long sF, GMode mode,
              double cJ, double cK, double cKa, GWork& w, hipStream_t st) {
-  const int np = m.np, n = m.nao;
-  w.r.ensure(static_cast<size_t>(k) * np);
-  w.J.ensure(static_cast<size_t>(k) * np);
-  hipLaunchKernelGGL(pack_kernel, dim3(ceil_div(np, 256), k), dim3(256), 0, st, k, np, n, m.pi_mu.p, m.pi_nu.p, R, sR,
-                     w.r.p);
-  SEQX_LAUNCH_CHECK();
-  // J[np][k] = W (np x np) * r^T ; r stored [k][np]
-  dgemm(st, false, true, np, k, np, 1.0, m.W.p, np, 0, w.r.p, np, 0, 0.0, w.J.p, k, 0, 1, nullptr);
-  const dim3 dgrid(ceil_div(m.natoms, 64), k);
-  if (mode == kTwo) {
-    hipLaunchKernelGGL(diag_block_kernel<kTwo>, dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p, m.pi_off.p,
-                       m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
-    launch_pairs<kTwo>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
-  } else if (mode == kSum) {
-    hipLaunchKernelGGL(diag_block_kernel<kSum>, dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p, m.pi_off.p,
-                       m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
-    launch_pairs<kSum>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
-  } else {
-    hipLaunchKernelGGL(diag_block_kernel<kSymm>, dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p, m.pi_off.p,
-                       m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
-    launch_pairs<kSymm>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
-  }
-  SEQX_LAUNCH_CHECK();
+  build_G_any<double, double>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, w, st);
+}
+
+void build_G(const DeviceMolecule& m, int k, const float* R, long sR, float* F1, float* F2, long sF, GMode mode,
+             double cJ, double cK, double cKa, GWork& w, hipStream_t st) {
+  build_G_any<float, float>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, w, st);
 }
 
 }  // namespace seqx

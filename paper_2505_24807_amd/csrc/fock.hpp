@@ -22,5 +22,8 @@ struct GWork {
 
 void build_G(const DeviceMolecule& m, int k, const double* R, long sR, double* F1, double* F2, long sF, GMode mode,
              double cJ, double cK, double cKa, GWork& w, hipStream_t st);
+// FP32 storage of R and F; every product and sum is still formed in FP64.
+void build_G(const DeviceMolecule& m, int k, const float* R, long sR, float* F1, float* F2, long sF, GMode mode,
+             double cJ, double cK, double cKa, GWork& w, hipStream_t st);
 
 }  // namespace seqx

@@ -24,6 +24,14 @@ void dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, 
            const double* B, long ldb, long sB, double beta, double* C, long ldc, long sC, int batch = 1,
            const SigmaEpilogue* epi = nullptr);
 
+// FP32 inputs on the FP32 matrix cores, FP32 accumulation; alpha, beta and the
+// epilogue are applied in FP64.  sgemm writes FP32, sgemm_out64 writes FP64.
+void sgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda, long sA,
+           const float* B, long ldb, long sB, double beta, float* C, long ldc, long sC, int batch = 1);
+void sgemm_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda,
+                 long sA, const float* B, long ldb, long sB, double beta, double* C, long ldc, long sC, int batch = 1,
+                 const SigmaEpilogue* epi = nullptr);
+
 // Column-major (BLAS) semantics for small subspace matrices:
 //   C = alpha * op(A) op(B) + beta * C, op(A) M x K, op(B) K x N, column-major.
 void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,

@@ -181,6 +181,19 @@ void copy(hipStream_t st, double* dst, const double* src, long n) {
   SEQX_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, st));
 }
 
+namespace {
+__global__ void to_float_kernel(long n, const double* __restrict__ x, float* __restrict__ y) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i < n) y[i] = static_cast<float>(x[i]);
+}
+}  // namespace
+
+void to_float(hipStream_t st, long n, const double* x, float* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(to_float_kernel, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, st, n, x, y);
+  SEQX_LAUNCH_CHECK();
+}
+
 void transpose(hipStream_t st, int rows, int cols, const double* src, long lds, double* dst, long ldd) {
   hipLaunchKernelGGL(transpose_kernel, dim3(ceil_div(cols, 32), ceil_div(rows, 32)), dim3(32, 8), 0, st, rows, cols,
                      src, lds, dst, ldd);

@@ -34,6 +34,8 @@ class DenseSolver {
 // elementwise / reduction helpers (all ordered on `st`)
 void fill(hipStream_t st, double* x, long n, double v);
 void copy(hipStream_t st, double* dst, const double* src, long n);
+// y = x rounded to nearest FP32
+void to_float(hipStream_t st, long n, const double* x, float* y);
 void transpose(hipStream_t st, int rows, int cols, const double* src, long lds, double* dst, long ldd);
 // y = a*x + b*y
 void axpby(hipStream_t st, long n, double a, const double* x, double b, double* y);

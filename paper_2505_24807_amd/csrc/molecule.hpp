@@ -20,6 +20,7 @@ struct DeviceMolecule {
   DBuf<double> W;               // packed ERI matrix [np][np]
   DBuf<double> H;               // core Hamiltonian [nao][nao]
   DBuf<double> C;               // MO coefficients, row-major [nao][nao]: C[mu][p]
+  DBuf<float> C32;              // C rounded to FP32 (mixed-precision transforms)
   DBuf<double> eps;             // orbital energies [nao]
   DBuf<double> P;               // density [nao][nao]
   double commutator = 0.0;

@@ -229,6 +229,8 @@ void run_scf(DeviceMolecule& m, const ScfOptions& opt, DenseSolver& ds, GWork& g
   ds.eigh(n, w.CT.p, n, m.eps.p);
   if (ds.info_eigh() != 0) throw Error(kEDevice, "dense eigensolver failed in SCF");
   transpose(st, n, n, w.CT.p, n, m.C.p, n);  // C[mu][p] = CT[p][mu]
+  m.C32.ensure(nn);
+  to_float(st, nn, m.C.p, m.C32.p);
   density_from_CT(st, n, o, w.CT.p, m.P.p);
 }
 

@@ -26,8 +26,12 @@ struct PhaseTimer {
   ~PhaseTimer();
 };
 
+// Number type of the dense transforms (values of seqx_precision).
+enum SigmaPrecision { kPrecFP64 = 0, kPrecFP32 = 1, kPrecBF16 = 2, kPrecBF16x3 = 3 };
+
 struct SigmaWork {
   DBuf<double> T1, R, F, Z;
+  DBuf<float> V32, T1s, Rs, Fs, Zs;  // FP32 storage of the mixed-precision path
   GWork g;
   PhaseTimer timer;
 };
@@ -39,8 +43,12 @@ struct SigmaWork {
 // C_occ^T G C_virt + (eps_a - eps_i) V_I.  Works in chunks of at most
 // `chunk` vectors (memory cap).  out_stride: distance (doubles) between the
 // outputs of consecutive vectors (0: nocc*nvirt, i.e. contiguous).
+// precision kPrecFP32: V, C, R, F and the transform intermediates are stored in
+// FP32 and the four transforms run on the FP32 matrix cores; the NDDO
+// contraction still multiplies and adds in FP64 and the (eps_a - eps_i) V term
+// is added in FP64 to the FP64 output.
 void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
-                 SigmaWork& w, hipStream_t st, int chunk = 32, long out_stride = 0);
+                 SigmaWork& w, hipStream_t st, int chunk = 32, long out_stride = 0, int precision = kPrecFP64);
 
 // AO transition densities T_I = C_occ X_I C_virt^T for k amplitude vectors (no G, no back-transform).
 void forward_transform(const DeviceMolecule& m, int k, const double* X, double* T, SigmaWork& w, hipStream_t st);

@@ -48,7 +48,8 @@ class Stats(C.Structure):
                 ("commutator", C.c_double), ("t_integrals_s", C.c_double), ("t_scf_s", C.c_double),
                 ("t_davidson_s", C.c_double), ("t_sigma_s", C.c_double), ("time_to_roots_s", C.c_double * 64),
                 ("n_history", C.c_int32), ("phase_ms", C.c_double * 5), ("phase_launches", C.c_int64 * 5),
-                ("phase_flops", C.c_double * 5), ("phase_bytes", C.c_double * 5), ("dav_phase_ms", C.c_double * 8)]
+                ("phase_flops", C.c_double * 5), ("phase_bytes", C.c_double * 5), ("dav_phase_ms", C.c_double * 8),
+                ("n_sigma_fp64", C.c_int64), ("refine_iteration", C.c_int32)]
 
     DAV_PHASES = ["sigma", "projection", "subspace eig", "ritz+residual", "check", "precond", "collapse", "ortho"]
 

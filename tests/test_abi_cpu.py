@@ -31,7 +31,18 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert seqx.load_library().seqx_abi_version() == 1
+    text = open(os.path.join(ROOT, "include", "seqx.h")).read()
+    declared = int(re.search(r"#define SEQX_ABI_VERSION (\d+)", text).group(1))
+    assert seqx.load_library().seqx_abi_version() == declared
+
+
+def test_stats_struct_matches_header():
+    # the ctypes mirror must have one field per member of seqx_stats, in order
+    text = open(os.path.join(ROOT, "include", "seqx.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} seqx_stats;", text).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    members = re.findall(r"\b([a-z_0-9]+)(?:\[\d+\])?;", body)
+    assert [f[0] for f in seqx.Stats._fields_] == members
 
 
 def test_validate_accepts_workloads():

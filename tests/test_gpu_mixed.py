@@ -1,0 +1,120 @@
+"""Mixed-precision transforms (FP32 storage and matrix cores) against the FP64 oracle.
+
+Tolerance of the FP32 products.  Rounding C and V to FP32 and accumulating
+each of the four transforms in FP32 over at most n terms perturbs every
+element of the two-electron part C_o^T G(C_o V C_v^T) C_v by at most about
+4 n u |.|, u = 2^-24, relative to the largest element of that part (the
+orbital-energy term is added in FP64 and carries no FP32 error).  The tests
+take 8 n u, twice that estimate.
+
+Solves in FP32 finish in FP64 (restart from the Ritz vectors with FP64
+products), so their roots are held to the FP64 bar of 1e-6 eV.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import excited, integrals, model, scf
+from paper_2505_24807_amd import seqx
+from synthetic import molecules, params
+
+pytestmark = pytest.mark.gpu
+HA = model.HARTREE_EV
+HERE = os.path.dirname(os.path.abspath(__file__))
+PR = params.load()
+U32 = 2.0 ** -24
+
+MOLS = {
+    "C2H4": molecules.ethylene(),
+    "H2O3": molecules.water_cluster(3, 7),
+    "C20H22n": molecules.add_noise(molecules.polyene(20), 0.02, np.random.default_rng(20)),
+    "H2O12": molecules.water_cluster(12, 5),
+}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = seqx.Context(0)
+    Zs, vals = seqx.params_table(PR)
+    c.set_params(Zs, vals)
+    yield c
+    c.close()
+
+
+def _oracle(name):
+    mol = MOLS[name]
+    sy = model.make_system(mol.Z, mol.xyz, PR)
+    ints = integrals.build(sy)
+    res = scf.run(sy, ints)
+    return sy, ints, res
+
+
+def _ao(Cm, o, X):
+    return Cm[:, :o] @ X @ Cm[:, o:].T
+
+
+@pytest.mark.parametrize("name", ["C2H4", "H2O3", "C20H22n", "H2O12"])
+def test_sigma_fp32_products(ctx, name):
+    sy, ints, res = _oracle(name)
+    mol = MOLS[name]
+    print(f"[gpu] fp32 sigma {name}", flush=True)
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    eps_l, Cl, _ = job.scf_results()
+    n, o, v = job.dims()
+    A, B = excited.build_AB(ints, res.eps, res.C, o)
+    de = (res.eps[o:][None, :] - res.eps[:o][:, None]).ravel()
+    rng = np.random.default_rng(11)
+    Y = rng.normal(size=(6, n, n))
+    Vl = np.stack([Cl[:, :o].T @ y @ Cl[:, o:] for y in Y])
+    Vo = np.stack([res.C[:, :o].T @ y @ res.C[:, o:] for y in Y])
+    Vf = Vo.reshape(6, -1)
+    refs = {"A": Vf @ A.T, "ApB": Vf @ (A + B).T, "AmB": Vf @ (A - B).T}
+    a1, _ = job.sigma(Vl, theory=seqx.CIS, precision=seqx.FP32)
+    p1, m1 = job.sigma(Vl, theory=seqx.TDHF, precision=seqx.FP32)
+    a64, _ = job.sigma(Vl, theory=seqx.CIS, precision=seqx.FP64)
+    worst = 0.0
+    for lib, key in ((a1, "A"), (p1, "ApB"), (m1, "AmB")):
+        two_e = refs[key] - de[None, :] * Vf  # two-electron part of the oracle product
+        for k in range(6):
+            d = np.abs(_ao(Cl, o, lib[k]) - _ao(res.C, o, refs[key][k].reshape(o, v))).max()
+            scale = np.abs(_ao(res.C, o, two_e[k].reshape(o, v))).max()
+            worst = max(worst, d / (n * U32 * scale))
+            assert d <= 8 * n * U32 * scale, (key, k, d, scale)
+    print(f"[gpu] {name}: worst error / (n u max|2e part|) = {worst:.3f}", flush=True)
+    # FP32 differs from FP64, by far less than the bound but more than FP64 rounding
+    assert np.abs(a1 - a64).max() > 0.0
+    job.free()
+
+
+@pytest.mark.parametrize("name,theory,K", [("C2H4", seqx.TDHF, 3), ("C20H22n", seqx.TDHF, 5),
+                                           ("C20H22n", seqx.CIS, 4), ("H2O12", seqx.TDHF, 6)])
+def test_fp32_solve_finishes_in_fp64(ctx, name, theory, K):
+    sy, ints, res = _oracle(name)
+    o, v = res.nocc, sy.nao - res.nocc
+    A, B = excited.build_AB(ints, res.eps, res.C, o)
+    ref = excited.cis_dense(A, K, o, v) if theory == seqx.CIS else excited.tdhf_dense(A, B, K, o, v)
+    mol = MOLS[name]
+    print(f"[gpu] fp32 solve {name} theory={theory} K={K}", flush=True)
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    job.solve(theory=theory, nroots=K, tol=1e-7, precision=seqx.FP32)
+    lib = job.results()
+    st = job.stats()
+    assert np.abs(lib.omega_eV - ref.omega * HA).max() < 1e-6
+    _, f_ref = excited.transition_properties(sy, res.C, o, ref)
+    assert np.abs(lib.f - f_ref).max() < 1e-6
+    assert st.refine_iteration >= 1
+    assert 0 < st.n_sigma_fp64 <= st.n_sigma
+    job.free()
+
+
+def test_bf16_modes_are_rejected(ctx):
+    mol = MOLS["C2H4"]
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    _, o, v = job.dims()
+    for p in (seqx.BF16, seqx.BF16X3):
+        with pytest.raises(seqx.SeqxError) as e:
+            job.sigma(np.zeros((1, o, v)), theory=seqx.CIS, precision=p)
+        assert e.value.name == "E_ARG"
+    job.free()
