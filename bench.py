@@ -13,7 +13,7 @@ step; time-to-roots alongside), the roofline of the dominant sigma-build kernel
 bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--precision fp32|fp64]
-                    [--no-fp64-comparison] [--no-cpu-baseline]
+                    [--no-fp64-comparison] [--no-batched] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -160,6 +160,52 @@ def roofline_of(r, dtype):
             "flops_per_launch": flops / launches, "avg_launch_ms": ms / launches}
 
 
+def batched_c4(ctx, steps):
+    """512 uneven molecules, CIS, 5 roots, tol 1e-5: the batched solver (FP32
+    fused products, one launch per iteration, replayed graph) against the plain
+    FP64 Davidson run molecule by molecule on the same GPU.  Integrals and SCF
+    (done once, batched prepare) are outside both timings."""
+    import torch
+    from paper_2505_24807_amd import seqx
+    from synthetic import molecules
+    mols = molecules.workload_batch(512, 512)
+    natoms, Z, xyz = molecules.concat(mols)
+    t0 = time.perf_counter()
+    job = ctx.prepare(list(natoms), Z, xyz)
+    t_prep = time.perf_counter() - t0
+    job.solve(theory=seqx.CIS, nroots=5, tol=1e-5, max_iter=300, precision=seqx.FP32, batched=True)  # warm-up + tuning
+    t_tune = job.stats().t_autotune_s
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = []
+    for _ in range(steps):
+        job.solve(theory=seqx.CIS, nroots=5, tol=1e-5, max_iter=300, precision=seqx.FP32, batched=True)
+        sts.append(job.stats())
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    st = sts[-1]
+    t0 = time.perf_counter()
+    job.solve(theory=seqx.CIS, nroots=5, tol=1e-5, max_iter=300, precision=seqx.FP64)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    n_loop = job.stats().n_sigma
+    job.free()
+    fl, tsig = st.batched_sigma_flops, st.t_sigma_s
+    return {"workload": "512 uneven molecules (polyenes, alkanes, water clusters; 6-62 atoms, n 12-142), seed 512, "
+                        "CIS 5 roots, residual tol 1e-5 Eh",
+            "batched_s": round(t_b, 4), "batched_sigma_vectors_per_s": round(st.n_sigma / t_b, 1),
+            "batched_iterations": st.dav_iterations, "batched_n_sigma": st.n_sigma,
+            "batched_graph": bool(st.batched_graph), "tile_variant_by_size": list(st.tile_variant),
+            "autotune_s": round(t_tune, 3),
+            "fused_sigma_s": round(tsig, 4),
+            "fused_sigma_roofline": {"bound": "mfma", "achieved": round(fl / tsig / 1e12, 3) if tsig > 0 else None,
+                                     "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                                     "frac": round(fl / tsig / 1e12 / PEAK["fp32"], 4) if tsig > 0 else None,
+                                     "kernel": "sigma_items_kernel<float>"},
+            "per_molecule_fp64_loop_s": round(t_loop, 3), "per_molecule_fp64_loop_n_sigma": n_loop,
+            "speedup_vs_fp64_loop": round(t_loop / t_b, 2), "prepare_s": round(t_prep, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,8 +214,11 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
                     help="transform precision of the timed run (fp32: mixed mode finishing in FP64)")
     ap.add_argument("--no-fp64-comparison", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-molecule batched CIS section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-vectors", type=int, default=2)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU path is not built "
@@ -184,6 +233,12 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
+    if args.calibrate_copy_mib > 0:
+        x = torch.ones(args.calibrate_copy_mib * 2 ** 18, device="cuda", dtype=torch.float32)
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)  # reads and writes calibrate_copy_mib MiB each
+        torch.cuda.synchronize()
+        del x, y
     ctx = seqx.Context(0, stream)
     pr = params.load()
     ctx.set_params(*seqx.params_table(pr))
@@ -211,6 +266,8 @@ def main():
         s64 = summary(r64, K)
         s64["roofline"] = roofline_of(r64, "fp64")
         out["fp64_comparison"] = s64
+    if not args.no_batched:
+        out["batched_c4"] = batched_c4(ctx, K)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mol, pr, args.cpu_vectors)
     print(json.dumps(out))

@@ -95,6 +95,12 @@ typedef struct {
   int32_t guess;        /* seqx_guess */
   int32_t n_user_guess; /* SEQX_GUESS_USER: number of host vectors in user_guess */
   const double* user_guess; /* host [n_user_guess][nocc][nvirt], molecule 0 only */
+  int32_t batched;      /* nonzero: every molecule of the job in one batched Davidson
+                           (CIS, gap guess, 1-16 roots, SEQX_FP32 or SEQX_FP64 products):
+                           each iteration forms all (molecule, vector) products in one
+                           persistent launch and replays one captured HIP graph.  The
+                           subspace cap is min(max_subspace or 8 * nroots, 48) per molecule.
+                           Molecules need at most 1536 same-atom AO pairs. */
 } seqx_solve_opts;
 
 typedef struct {
@@ -126,6 +132,15 @@ typedef struct {
    * Ritz vectors with FP64 products (0 when it never ran in low precision). */
   int64_t n_sigma_fp64;
   int32_t refine_iteration;
+  /* Batched solves: wall time of the tile autotuner (excluded from t_davidson_s;
+   * zero once the context has tuned every size bucket), whether the iteration
+   * ran as a replayed HIP graph, and the tile variant (0: 16x16, 1: 32x16,
+   * 2: 32x32 MFMA tiles per wavefront) chosen for molecules with n < 32, < 64,
+   * < 96, < 128 and larger. */
+  double t_autotune_s;
+  int32_t batched_graph;
+  int32_t tile_variant[5];
+  double batched_sigma_flops; /* algorithmic transform flops of the batched products, 4 n v (n + o) each */
 } seqx_stats;
 
 /* Version of this header the library was built with (SEQX_ABI_VERSION). */

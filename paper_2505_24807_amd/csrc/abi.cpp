@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/seqx.h"
+#include "batch.hpp"
 #include "davidson.hpp"
 #include "integrals.hpp"
 #include "linalg.hpp"
@@ -26,6 +27,7 @@ struct seqx_ctx {
   bool have[kNumSlots] = {false, false, false};
   DBuf<Elem> d_elems;
   std::unique_ptr<DenseSolver> ds;
+  TileTuning tune;
 };
 
 struct seqx_job {
@@ -34,6 +36,7 @@ struct seqx_job {
   GWork gw;
   ScfWork sw;
   DavWork dw;
+  BatchWork bw;
   seqx_stats stats{};
   bool solved = false;
 };
@@ -414,6 +417,40 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
     job->stats.dav_iterations = 0;
     job->stats.t_sigma_s = 0;
     job->stats.n_history = 0;
+    job->stats.t_autotune_s = 0.0;
+    job->stats.batched_graph = 0;
+    job->stats.batched_sigma_flops = 0.0;
+    for (int32_t& x : job->stats.tile_variant) x = 0;
+    if (opts->batched) {
+      if (opts->theory != SEQX_CIS) throw Error(kEArg, "batched solve supports CIS only");
+      if (opts->guess != SEQX_GUESS_GAP) throw Error(kEArg, "batched solve uses the gap guess");
+      std::vector<DeviceMolecule*> ms;
+      for (size_t mi = 0; mi < job->mols.size(); ++mi) ms.push_back(&scf_mol_of(job, static_cast<int32_t>(mi)));
+      BatchOptions bo;
+      bo.nroots = opts->nroots;
+      bo.tol = d.tol;
+      bo.max_iter = d.max_iter;
+      bo.max_sub = opts->max_subspace;
+      bo.precision = opts->precision;
+      const auto tb = std::chrono::steady_clock::now();
+      BatchResult r = batched_cis(ms, bo, job->bw, job->ctx->tune, job->dw.sig, st);
+      const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
+      for (DeviceMolecule* m : ms) {
+        m->hist_t.clear();
+        m->hist_omega.clear();
+      }
+      job->stats.n_sigma = r.n_sigma;
+      job->stats.n_sigma_fp64 = opts->precision == SEQX_FP64 ? r.n_sigma : 0;
+      job->stats.dav_iterations = r.iterations;
+      job->stats.t_sigma_s = r.t_sigma_ms * 1e-3;
+      job->stats.t_autotune_s = r.t_autotune_ms * 1e-3;
+      job->stats.t_davidson_s = wall - job->stats.t_autotune_s;
+      job->stats.batched_graph = r.used_graph ? 1 : 0;
+      job->stats.batched_sigma_flops = r.sigma_flops;
+      for (int b = 0; b < kNumSizeBuckets; ++b) job->stats.tile_variant[b] = r.variant_of_bucket[b];
+      job->solved = true;
+      return;
+    }
     const auto t0 = std::chrono::steady_clock::now();
     for (size_t mi = 0; mi < job->mols.size(); ++mi) {
       DeviceMolecule& m = scf_mol_of(job, static_cast<int32_t>(mi));

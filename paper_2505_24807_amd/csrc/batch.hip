@@ -1,0 +1,960 @@
+// Batched CIS Davidson (batched outline of the paper's GPU-implementation
+// subsection and its Fig. 2) for many small molecules of uneven size.
+//
+// The paper pads every molecule to the largest and runs dense batched tensor
+// operations.  Here nothing is padded: a (molecule, trial vector) pair is a
+// work item, and one persistent launch of a fused kernel forms all products of
+// an iteration.  Each 256-thread workgroup takes items in a static round-robin
+// over a list ordered by molecule size (largest first), and for one item runs
+// Eqs. 8-9 end to end:
+//   T = C_o V,  R = T C_v^T           (workgroup MFMA GEMMs)
+//   F = 2 J(R) - K(R)                 (packed Coulomb, one-centre and pair exchange)
+//   Z = F C_v,  A V = C_o^T Z + de V  (workgroup MFMA GEMMs, FP64 epilogue)
+// with R, F and T/Z in a per-workgroup slice of global scratch (L2-resident).
+// The subspace steps (projection, Jacobi eigensolve, Ritz vectors and
+// residuals, preconditioning, collapse, Gram-Schmidt) are one launch each over
+// all molecules, with per-molecule flags on the device, so the iteration is a
+// fixed sequence of launches (captured once as a HIP graph); the host reads one
+// counter per iteration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+#include "batch.hpp"
+#include "fock_blocks.hpp"
+#include "linalg.hpp"
+
+namespace seqx {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct WgMfma;
+template <>
+struct WgMfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct WgMfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+// Workgroup GEMM (4 wavefronts): out(i, j) = sum_k A(i, k) B(k, j) for i < M,
+// j < N, with A(i, k) = A[i sai + k sak] and B(k, j) = B[k sbk + j sbj] (any
+// transposition through the strides).  Each wave owns macro tiles of
+// (16 TM) x (16 TN) in round-robin; operands come straight from global memory
+// (L1/L2) in the MFMA lane layout; store(i, j, value) writes the result.
+template <class T, int TM, int TN, class TA, class TB, class Store>
+__device__ __forceinline__ void wg_gemm(int M, int N, int K, const TA* __restrict__ A, long sai, long sak,
+                                        const TB* __restrict__ B, long sbk, long sbj, Store store) {
+  typedef WgMfma<T> MF;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int tm = (M + 16 * TM - 1) / (16 * TM), tn = (N + 16 * TN - 1) / (16 * TN);
+  for (int t = wave; t < tm * tn; t += 4) {
+    const int i0 = (t / tn) * 16 * TM, j0 = (t % tn) * 16 * TN;
+    typename MF::acc_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + k4;
+      T a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int row = i0 + i * 16 + r16;
+        a[i] = (row < M && k < K) ? static_cast<T>(A[row * sai + k * sak]) : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = j0 + j * 16 + r16;
+        b[j] = (col < N && k < K) ? static_cast<T>(B[k * sbk + col * sbj]) : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + i * 16 + MF::row(lane, r), col = j0 + j * 16 + r16;
+          if (row < M && col < N) store(row, col, static_cast<double>(acc[i][j][r]));
+        }
+  }
+}
+
+// One CIS product A V for one trial vector of one molecule (whole workgroup).
+// scr: n*n (R) + n*n (F) + n*v (T, then Z) elements of T; rs, js: LDS [np].
+template <class T, int TM, int TN>
+__device__ void sigma_item(const MolDesc& md, const T* __restrict__ C, const double* __restrict__ V,
+                           double* __restrict__ out, T* __restrict__ scr, double* rs, double* js) {
+  const int n = md.n, o = md.o, v = md.v, np = md.np;
+  T* R = scr;
+  T* F = scr + static_cast<long>(n) * n;
+  T* Tz = scr + 2L * n * n;
+  // T (n x v) = C[:, :o] V
+  wg_gemm<T, TM, TN>(n, v, o, C, n, 1, V, v, 1,
+                     [&](int i, int j, double x) { Tz[static_cast<long>(i) * v + j] = static_cast<T>(x); });
+  __syncthreads();
+  // R (n x n) = T C[:, o:]^T
+  wg_gemm<T, TM, TN>(n, n, v, Tz, v, 1, C + o, 1, n,
+                     [&](int i, int j, double x) { R[static_cast<long>(i) * n + j] = static_cast<T>(x); });
+  __syncthreads();
+  // packed same-atom densities r_P and Coulomb J = W r (one wave per row, fixed-order reduction)
+  for (int P = threadIdx.x; P < np; P += blockDim.x) {
+    const int mu = md.pi_mu[P], nu = md.pi_nu[P];
+    const double a = static_cast<double>(R[static_cast<long>(mu) * n + nu]);
+    const double b = static_cast<double>(R[static_cast<long>(nu) * n + mu]);
+    rs[P] = (mu == nu) ? a : a + b;
+  }
+  __syncthreads();
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int P = wave; P < np; P += 4) {
+      const double* Wr = md.W + static_cast<long>(P) * np;
+      double s = 0.0;
+      for (int Q = lane; Q < np; Q += 64) s += Wr[Q] * rs[Q];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      if (lane == 0) js[P] = s;
+    }
+  }
+  __syncthreads();
+  // F = 2 J(R) - K(R): atom-diagonal blocks, then every atom pair (both orders)
+  for (int A = threadIdx.x; A < md.natoms; A += blockDim.x)
+    diag_block<kSum, T, T>(md.elems[md.slot[A]], md.ao_off[A], md.pi_off[A], js, 1, R, n, F, static_cast<T*>(nullptr),
+                           2.0, -1.0, -1.0);
+  for (int p = threadIdx.x; p < md.npairs[0]; p += blockDim.x)
+    exchange_pair<4, 4, kSum, T, T>(md.pairs[0][p].x, md.pairs[0][p].y, md.ao_off, md.pi_off, md.W, np, R, n, F,
+                                    static_cast<T*>(nullptr), -1.0, -1.0);
+  for (int p = threadIdx.x; p < md.npairs[1]; p += blockDim.x)
+    exchange_pair<4, 1, kSum, T, T>(md.pairs[1][p].x, md.pairs[1][p].y, md.ao_off, md.pi_off, md.W, np, R, n, F,
+                                    static_cast<T*>(nullptr), -1.0, -1.0);
+  for (int p = threadIdx.x; p < md.npairs[2]; p += blockDim.x)
+    exchange_pair<1, 1, kSum, T, T>(md.pairs[2][p].x, md.pairs[2][p].y, md.ao_off, md.pi_off, md.W, np, R, n, F,
+                                    static_cast<T*>(nullptr), -1.0, -1.0);
+  __syncthreads();
+  // Z (n x v) = F C[:, o:]
+  wg_gemm<T, TM, TN>(n, v, n, F, n, 1, C + o, n, 1,
+                     [&](int i, int j, double x) { Tz[static_cast<long>(i) * v + j] = static_cast<T>(x); });
+  __syncthreads();
+  // A V (o x v) = C[:, :o]^T Z + (eps_a - eps_i) V, the diagonal term in FP64
+  const double* eps = md.eps;
+  wg_gemm<T, TM, TN>(o, v, n, C, 1, n, Tz, v, 1, [&](int i, int j, double x) {
+    const long ij = static_cast<long>(i) * v + j;
+    out[ij] = x + (eps[o + j] - eps[i]) * V[ij];
+  });
+  __syncthreads();
+}
+
+// counters: [0] number of items, [1] active molecules, [2] iteration
+template <class T>
+__global__ void __launch_bounds__(256) sigma_items_kernel(const MolDesc* __restrict__ mols,
+                                                          const int2* __restrict__ items, const int* __restrict__ counters,
+                                                          const double* __restrict__ Vp, double* __restrict__ AVp,
+                                                          T* __restrict__ scratch, long scratch_stride,
+                                                          long long* __restrict__ stamps) {
+  __shared__ double rs[kBatchMaxNp];
+  __shared__ double js[kBatchMaxNp];
+  if (threadIdx.x == 0) stamps[2 * blockIdx.x] = static_cast<long long>(wall_clock64());
+  const int nit = counters[0];
+  T* scr = scratch + blockIdx.x * scratch_stride;
+  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+    const int2 item = items[it];
+    const MolDesc md = mols[item.x];
+    const T* C = sizeof(T) == 4 ? reinterpret_cast<const T*>(md.C32) : reinterpret_cast<const T*>(md.C64);
+    const double* V = Vp + md.vbase + item.y * md.nov;
+    double* out = AVp + md.vbase + item.y * md.nov;
+    switch (md.variant) {
+      case 0: sigma_item<T, 1, 1>(md, C, V, out, scr, rs, js); break;
+      case 1: sigma_item<T, 2, 1>(md, C, V, out, scr, rs, js); break;
+      default: sigma_item<T, 2, 2>(md, C, V, out, scr, rs, js); break;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) stamps[2 * blockIdx.x + 1] = static_cast<long long>(wall_clock64());
+}
+
+// Span of the last sigma launch (latest end - earliest start over its
+// workgroups, device wall-clock ticks), added to acc[0]; fixed-order reduction.
+__global__ void __launch_bounds__(256) stamp_span_kernel(int G, const long long* __restrict__ stamps,
+                                                         long long* acc) {
+  __shared__ long long lo[256], hi[256];
+  long long a = 0x7fffffffffffffffLL, b = 0;
+  for (int i = threadIdx.x; i < G; i += 256) {
+    a = min(a, stamps[2 * i]);
+    b = max(b, stamps[2 * i + 1]);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + h]);
+      hi[threadIdx.x] = max(hi[threadIdx.x], hi[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += hi[0] - lo[0];
+}
+
+// ---------------------------------------------------------------- subspace kernels
+
+__device__ __forceinline__ double wave_sum(double s) {
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  return s;
+}
+
+// fixed-order block sum over 256 threads (result valid in every thread)
+__device__ double block_sum(double s, double* red) {
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Gap guess: unit vectors at the ng = min(nov, 2K) smallest eps_a - eps_i
+// (ties by flat index i*v + a), found by ng rounds of lexicographic minimum.
+__global__ void __launch_bounds__(256) guess_kernel(int nmol, const MolDesc* __restrict__ mols, int K,
+                                                    double* __restrict__ Vp, int* S, int* knew, int* active, int* conv,
+                                                    int* coll, int* qcol) {
+  __shared__ double bg[256];
+  __shared__ long bi[256];
+  const int m = blockIdx.x;
+  const MolDesc md = mols[m];
+  const long nov = md.nov;
+  const int ng = static_cast<int>(nov < 2L * K ? nov : 2L * K);
+  double* V = Vp + md.vbase;
+  for (long x = threadIdx.x; x < ng * nov; x += 256) V[x] = 0.0;
+  __syncthreads();
+  double lg = -1e300;
+  long li = -1;
+  for (int r = 0; r < ng; ++r) {
+    double g = 1e300;
+    long gi = nov;
+    for (long x = threadIdx.x; x < nov; x += 256) {
+      const double d = md.eps[md.o + x % md.v] - md.eps[x / md.v];
+      const bool after = d > lg || (d == lg && x > li);
+      if (after && (d < g || (d == g && x < gi))) {
+        g = d;
+        gi = x;
+      }
+    }
+    bg[threadIdx.x] = g;
+    bi[threadIdx.x] = gi;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (threadIdx.x < h) {
+        const double g2 = bg[threadIdx.x + h];
+        const long i2 = bi[threadIdx.x + h];
+        if (g2 < bg[threadIdx.x] || (g2 == bg[threadIdx.x] && i2 < bi[threadIdx.x])) {
+          bg[threadIdx.x] = g2;
+          bi[threadIdx.x] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    lg = bg[0];
+    li = bi[0];
+    if (threadIdx.x == 0) V[r * nov + li] = 1.0;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    S[m] = 0;
+    knew[m] = ng;
+    active[m] = 1;
+    conv[m] = 0;
+    coll[m] = 0;
+    qcol[m] = 0;
+  }
+}
+
+// Work list of the iteration: items (m, S_m + j), j < knew_m, molecules in
+// the size order `order` (largest first); block-wide exclusive scan.
+__global__ void __launch_bounds__(256) items_kernel(int nmol, const MolDesc* __restrict__ mols,
+                                                    const int* __restrict__ order, const int* __restrict__ S,
+                                                    const int* __restrict__ knew, const int* __restrict__ active,
+                                                    int2* __restrict__ items, int* counters, long long* nsig) {
+  __shared__ int part[256];
+  __shared__ long long fl[256];
+  const int per = (nmol + 255) / 256;
+  const int b0 = threadIdx.x * per, b1 = min(nmol, b0 + per);
+  int cnt = 0;
+  long long flops = 0;  // algorithmic transform flops of the items: 4 n v (n + o) each
+  for (int q = b0; q < b1; ++q) {
+    const int m = order[q];
+    if (active[m]) {
+      cnt += knew[m];
+      const long long n = mols[m].n, o = mols[m].o, v = mols[m].v;
+      flops += knew[m] * 4LL * n * v * (n + o);
+    }
+  }
+  part[threadIdx.x] = cnt;
+  fl[threadIdx.x] = flops;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) fl[threadIdx.x] += fl[threadIdx.x + h];
+    __syncthreads();
+  }
+  for (int h = 1; h < 256; h <<= 1) {  // inclusive Hillis-Steele scan
+    const int add = threadIdx.x >= h ? part[threadIdx.x - h] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int pos = part[threadIdx.x] - cnt;
+  for (int q = b0; q < b1; ++q) {
+    const int m = order[q];
+    if (!active[m]) continue;
+    for (int j = 0; j < knew[m]; ++j) items[pos++] = make_int2(m, S[m] + j);
+  }
+  if (threadIdx.x == 255) {
+    counters[0] = part[255];
+    nsig[0] += part[255];
+    nsig[2] += fl[0];
+  }
+}
+
+// New columns of M = V^T A V (column-major, ld Smax), both triangles; then S += knew.
+__global__ void __launch_bounds__(256) project_kernel(const MolDesc* __restrict__ mols, int Smax,
+                                                      const double* __restrict__ Vp, const double* __restrict__ AVp,
+                                                      double* __restrict__ Mp, int* S, const int* __restrict__ knew,
+                                                      const int* __restrict__ active) {
+  const int m = blockIdx.x;
+  if (!active[m]) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov;
+  const int S0 = S[m], S1 = S0 + knew[m];
+  const double* V = Vp + md.vbase;
+  const double* AV = AVp + md.vbase;
+  double* M = Mp + static_cast<long>(m) * Smax * Smax;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = S0; j < S1; ++j)
+    for (int s = wave; s <= j; s += 4) {
+      const double* a = V + s * nov;
+      const double* b = AV + j * nov;
+      double acc = 0.0;
+      for (long x = lane; x < nov; x += 64) acc += a[x] * b[x];
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        M[s + static_cast<long>(j) * Smax] = acc;
+        M[j + static_cast<long>(s) * Smax] = acc;
+      }
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) S[m] = S1;
+}
+
+// Symmetric eigensolve of the S x S projected matrix of each molecule by
+// cyclic Jacobi with the round-robin (tournament) ordering: each round rotates
+// ne/2 disjoint index pairs at once (rows, then columns), ne = S rounded up to
+// even.  Stops when the off-diagonal sum of squares is below 1e-32 of the
+// total.  Eigenvalues ascending in eval, eigenvectors as columns of evec (ld Smax).
+__global__ void __launch_bounds__(256) eig_kernel(int Smax, const double* __restrict__ Mp, const int* __restrict__ S,
+                                                  const int* __restrict__ active, double* __restrict__ evec,
+                                                  double* __restrict__ eval) {
+  __shared__ double A[kBatchMaxSub][kBatchMaxSub + 1];
+  __shared__ double Q[kBatchMaxSub][kBatchMaxSub + 1];
+  __shared__ double rc[kBatchMaxSub / 2], rsn[kBatchMaxSub / 2];
+  __shared__ int rp[kBatchMaxSub / 2], rq[kBatchMaxSub / 2];
+  __shared__ double red[256];
+  __shared__ int perm[kBatchMaxSub];
+  const int m = blockIdx.x;
+  if (!active[m]) return;
+  const int n = S[m];
+  const double* M = Mp + static_cast<long>(m) * Smax * Smax;
+  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+    const int i = idx / n, j = idx % n;
+    A[i][j] = M[i + static_cast<long>(j) * Smax];
+    Q[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int ne = n + (n & 1), half = ne / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+      const int i = idx / n, j = idx % n;
+      const double a2 = A[i][j] * A[i][j];
+      tot += a2;
+      if (i != j) off += a2;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (!(off > 1e-32 * tot)) break;
+    for (int r = 0; r < ne - 1; ++r) {
+      if (threadIdx.x < half) {
+        const int k = threadIdx.x;
+        int p = k == 0 ? r % (ne - 1) : (r + k) % (ne - 1);
+        int q = k == 0 ? ne - 1 : (r - k + ne - 1) % (ne - 1);
+        if (p > q) { const int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p][q];
+          if (apq != 0.0) {
+            const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        } else {
+          q = -1;
+        }
+        rp[k] = p;
+        rq[k] = q;
+        rc[k] = c;
+        rsn[k] = s;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < half * n; idx += 256) {  // rows p, q
+        const int k = idx / n, j = idx % n;
+        const int p = rp[k], q = rq[k];
+        if (q < 0) continue;
+        const double ap = A[p][j], aq = A[q][j];
+        A[p][j] = rc[k] * ap - rsn[k] * aq;
+        A[q][j] = rsn[k] * ap + rc[k] * aq;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < half * n; idx += 256) {  // columns p, q of A and Q
+        const int k = idx / n, i = idx % n;
+        const int p = rp[k], q = rq[k];
+        if (q < 0) continue;
+        const double ap = A[i][p], aq = A[i][q];
+        A[i][p] = rc[k] * ap - rsn[k] * aq;
+        A[i][q] = rsn[k] * ap + rc[k] * aq;
+        const double vp = Q[i][p], vq = Q[i][q];
+        Q[i][p] = rc[k] * vp - rsn[k] * vq;
+        Q[i][q] = rsn[k] * vp + rc[k] * vq;
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {  // ascending order (stable selection)
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    for (int i = 0; i < n; ++i) {
+      int b = i;
+      for (int j = i + 1; j < n; ++j)
+        if (A[perm[j]][perm[j]] < A[perm[b]][perm[b]]) b = j;
+      const int t = perm[i];
+      perm[i] = perm[b];
+      perm[b] = t;
+    }
+  }
+  __syncthreads();
+  double* ev = evec + static_cast<long>(m) * Smax * Smax;
+  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+    const int r = idx / n, i = idx % n;
+    ev[i + static_cast<long>(r) * Smax] = Q[i][perm[r]];
+  }
+  for (int r = threadIdx.x; r < n; r += 256) eval[static_cast<long>(m) * Smax + r] = A[perm[r]][perm[r]];
+}
+
+// Ritz vector j of molecule m, its residual r = A x - w x and norm; for an
+// unconverged root the preconditioned correction r / (w - de) (|w - de| kept
+// >= 1e-8) replaces r in Wc.
+__global__ void __launch_bounds__(256) ritz_kernel(const MolDesc* __restrict__ mols, int K, int Smax, double tol,
+                                                   const double* __restrict__ Vp, const double* __restrict__ AVp,
+                                                   const double* __restrict__ evec, const double* __restrict__ eval,
+                                                   const int* __restrict__ S, const int* __restrict__ active,
+                                                   double* __restrict__ Xp, double* __restrict__ Wcp,
+                                                   double* __restrict__ omega, double* __restrict__ rnorm) {
+  __shared__ double c[kBatchMaxSub];
+  __shared__ double red[256];
+  const int m = blockIdx.x, j = blockIdx.y;
+  if (!active[m]) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov;
+  const int n = S[m];
+  for (int s = threadIdx.x; s < n; s += 256) c[s] = evec[static_cast<long>(m) * Smax * Smax + s + static_cast<long>(j) * Smax];
+  __syncthreads();
+  const double w = eval[static_cast<long>(m) * Smax + j];
+  const double* V = Vp + md.vbase;
+  const double* AV = AVp + md.vbase;
+  double* X = Xp + md.xbase + j * nov;
+  double* Wc = Wcp + md.xbase + j * nov;
+  double ss = 0.0;
+  for (long x = threadIdx.x; x < nov; x += 256) {
+    double xv = 0.0, av = 0.0;
+    for (int s = 0; s < n; ++s) {
+      xv += c[s] * V[s * nov + x];
+      av += c[s] * AV[s * nov + x];
+    }
+    const double r = av - w * xv;
+    X[x] = xv;
+    Wc[x] = r;
+    ss += r * r;
+  }
+  const double rn = sqrt(block_sum(ss, red));
+  if (threadIdx.x == 0) {
+    rnorm[m * K + j] = rn;
+    omega[m * K + j] = w;
+  }
+  if (rn > tol)
+    for (long x = threadIdx.x; x < nov; x += 256) {
+      double den = w - (md.eps[md.o + x % md.v] - md.eps[x / md.v]);
+      if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
+      Wc[x] = Wc[x] / den;
+    }
+}
+
+// Convergence and bookkeeping for every molecule; counts the active ones.
+__global__ void __launch_bounds__(256) select_kernel(int nmol, int K, int Smax, double tol,
+                                                     const double* __restrict__ rnorm, const int* __restrict__ S,
+                                                     int* knew, int* active, int* coll, int* qcol, int* unc, int* conv,
+                                                     int* counters) {
+  __shared__ double red[256];
+  const int iter = counters[2] + 1;
+  double nact = 0.0;
+  for (int m = threadIdx.x; m < nmol; m += 256) {
+    if (!active[m]) continue;
+    int nu = 0;
+    for (int j = 0; j < K; ++j)
+      if (rnorm[m * K + j] > tol) unc[m * K + nu++] = j;
+    if (nu == 0) {
+      active[m] = 0;
+      conv[m] = iter;
+      continue;
+    }
+    knew[m] = nu;
+    coll[m] = S[m] + nu > Smax ? 1 : 0;
+    qcol[m] = min(2 * K, S[m]);
+    nact += 1.0;
+  }
+  nact = block_sum(nact, red);
+  if (threadIdx.x == 0) {
+    counters[1] = static_cast<int>(nact);
+    counters[2] = iter;
+  }
+}
+
+// Collapse onto the q lowest Ritz vectors: TV_s = sum_t evec(t, s) V_t (and A V).
+__global__ void __launch_bounds__(256) collapse_kernel(const MolDesc* __restrict__ mols, int Smax,
+                                                       const double* __restrict__ Vp, const double* __restrict__ AVp,
+                                                       const double* __restrict__ evec, const int* __restrict__ S,
+                                                       const int* __restrict__ coll, const int* __restrict__ qcol,
+                                                       double* __restrict__ TVp, double* __restrict__ TAVp) {
+  __shared__ double c[kBatchMaxSub];
+  const int m = blockIdx.x, s = blockIdx.y;
+  if (!coll[m] || s >= qcol[m]) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov;
+  const int n = S[m];
+  for (int t = threadIdx.x; t < n; t += 256) c[t] = evec[static_cast<long>(m) * Smax * Smax + t + static_cast<long>(s) * Smax];
+  __syncthreads();
+  const double* V = Vp + md.vbase;
+  const double* AV = AVp + md.vbase;
+  double* TV = TVp + md.tbase + s * nov;
+  double* TAV = TAVp + md.tbase + s * nov;
+  for (long x = threadIdx.x; x < nov; x += 256) {
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < n; ++t) {
+      a += c[t] * V[t * nov + x];
+      b += c[t] * AV[t * nov + x];
+    }
+    TV[x] = a;
+    TAV[x] = b;
+  }
+}
+
+// Second half of the collapse: copy back, M = diag(lowest q eigenvalues), S = q.
+__global__ void __launch_bounds__(256) collapse_copy_kernel(const MolDesc* __restrict__ mols, int Smax,
+                                                            const double* __restrict__ TVp,
+                                                            const double* __restrict__ TAVp,
+                                                            const double* __restrict__ eval, int* S, int* coll,
+                                                            const int* __restrict__ qcol, double* __restrict__ Vp,
+                                                            double* __restrict__ AVp, double* __restrict__ Mp) {
+  const int m = blockIdx.x, s = blockIdx.y;
+  if (!coll[m]) return;
+  const int q = qcol[m];
+  if (s > q) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov;
+  if (s < q) {
+    for (long x = threadIdx.x; x < nov; x += 256) {
+      Vp[md.vbase + s * nov + x] = TVp[md.tbase + s * nov + x];
+      AVp[md.vbase + s * nov + x] = TAVp[md.tbase + s * nov + x];
+    }
+  } else {  // block s == q: the projected matrix
+    double* M = Mp + static_cast<long>(m) * Smax * Smax;
+    for (int idx = threadIdx.x; idx < q * q; idx += 256) {
+      const int i = idx / q, j = idx % q;
+      M[i + static_cast<long>(j) * Smax] = (i == j) ? eval[static_cast<long>(m) * Smax + i] : 0.0;
+    }
+  }
+}
+
+// Orthonormalise the corrections of the unconverged roots against the basis
+// (classical Gram-Schmidt, two passes) and each other, append the survivors.
+__global__ void __launch_bounds__(256) ortho_kernel(const MolDesc* __restrict__ mols, int K, int Smax,
+                                                    double* __restrict__ Vp, double* __restrict__ Wcp, int* S,
+                                                    int* knew, int* active, int* coll, const int* __restrict__ qcol,
+                                                    const int* __restrict__ unc, int* conv,
+                                                    const int* __restrict__ counters) {
+  __shared__ double h[kBatchMaxSub];
+  __shared__ double red[256];
+  const int m = blockIdx.x;
+  if (!active[m]) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov;
+  int S0 = S[m];
+  if (coll[m]) S0 = qcol[m];
+  const int nu = knew[m];
+  double* V = Vp + md.vbase;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int acc = 0;
+  for (int u = 0; u < nu; ++u) {
+    if (S0 + acc >= Smax) break;
+    double* w = Wcp + md.xbase + unc[m * K + u] * nov;
+    double n0 = 0.0;
+    for (long x = threadIdx.x; x < nov; x += 256) n0 += w[x] * w[x];
+    n0 = sqrt(block_sum(n0, red));
+    const int nb = S0 + acc;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int s = wave; s < nb; s += 4) {
+        const double* a = V + s * nov;
+        double d = 0.0;
+        for (long x = lane; x < nov; x += 64) d += a[x] * w[x];
+        d = wave_sum(d);
+        if (lane == 0) h[s] = d;
+      }
+      __syncthreads();
+      for (long x = threadIdx.x; x < nov; x += 256) {
+        double t = w[x];
+        for (int s = 0; s < nb; ++s) t -= h[s] * V[s * nov + x];
+        w[x] = t;
+      }
+      __syncthreads();
+    }
+    double nw = 0.0;
+    for (long x = threadIdx.x; x < nov; x += 256) nw += w[x] * w[x];
+    nw = sqrt(block_sum(nw, red));
+    if (nw > 1e-8 * n0 && nw > 1e-14) {
+      double* dst = V + static_cast<long>(nb) * nov;
+      const double inv = 1.0 / nw;
+      for (long x = threadIdx.x; x < nov; x += 256) dst[x] = w[x] * inv;
+      ++acc;
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    S[m] = S0;
+    coll[m] = 0;
+    knew[m] = acc;
+    if (acc == 0) {  // no new direction: stop this molecule (flagged by a negative iteration)
+      active[m] = 0;
+      conv[m] = -counters[2];
+    }
+  }
+}
+
+int bucket_of(int n) { return n < 32 ? 0 : n < 64 ? 1 : n < 96 ? 2 : n < 128 ? 3 : 4; }
+
+double ms_between(hipEvent_t a, hipEvent_t b) {
+  float t = 0.f;
+  SEQX_HIP(hipEventElapsedTime(&t, a, b));
+  return t;
+}
+
+}  // namespace
+
+BatchWork::~BatchWork() {
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOptions& opt, BatchWork& w,
+                        TileTuning& tune, SigmaWork& sig, hipStream_t user_stream) {
+  const int nmol = static_cast<int>(mols.size());
+  const int K = opt.nroots;
+  const bool f32 = opt.precision == kPrecFP32;
+  if (opt.precision != kPrecFP32 && opt.precision != kPrecFP64)
+    throw Error(kEArg, "batched solve supports FP32 and FP64 products");
+  if (K < 1 || K > kBatchMaxRoots) throw Error(kEArg, "batched solve supports 1 to 16 roots");
+  int Smax = opt.max_sub > 0 ? opt.max_sub : 8 * K;
+  Smax = std::min(std::max(Smax, 3 * K), kBatchMaxSub);
+  if (Smax < 3 * K) throw Error(kEArg, "batched solve: subspace cap below 3 * nroots");
+  BatchResult res;
+  if (!w.stream) SEQX_HIP(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
+  hipStream_t st = w.stream;
+
+  // ---- molecule table, ordering and pools
+  std::vector<MolDesc> h(nmol);
+  long vtot = 0, xtot = 0, ttot = 0, scr = 0;
+  int maxnew = 2 * K;
+  for (int m = 0; m < nmol; ++m) {
+    const DeviceMolecule& d = *mols[m];
+    const long nov = static_cast<long>(d.nocc) * d.nvirt;
+    if (nov < K) throw Error(kEArg, "nroots exceeds nocc*nvirt of a molecule");
+    if (d.np > kBatchMaxNp) throw Error(kEArg, "molecule too large for the batched solver (pair indices > 1536)");
+    if (d.C32.n < static_cast<size_t>(d.nao) * d.nao) throw Error(kEState, "FP32 MO coefficients missing");
+    MolDesc& md = h[m];
+    md.n = d.nao;
+    md.o = d.nocc;
+    md.v = d.nvirt;
+    md.np = d.np;
+    md.natoms = d.natoms;
+    for (int g = 0; g < 3; ++g) {
+      md.npairs[g] = d.npairs[g];
+      md.pairs[g] = d.pairs[g].p;
+    }
+    md.variant = 2;
+    md.pad_ = 0;
+    md.nov = nov;
+    md.vbase = vtot;
+    md.xbase = xtot;
+    md.tbase = ttot;
+    vtot += static_cast<long>(Smax) * nov;
+    xtot += static_cast<long>(K) * nov;
+    ttot += static_cast<long>(2 * K) * nov;
+    md.C32 = d.C32.p;
+    md.C64 = d.C.p;
+    md.eps = d.eps.p;
+    md.W = d.W.p;
+    md.slot = d.slot.p;
+    md.ao_off = d.ao_off.p;
+    md.pi_off = d.pi_off.p;
+    md.pi_mu = d.pi_mu.p;
+    md.pi_nu = d.pi_nu.p;
+    md.elems = d.elems;
+    scr = std::max(scr, 2L * d.nao * d.nao + static_cast<long>(d.nao) * d.nvirt);
+  }
+  std::vector<int> order(nmol);
+  for (int m = 0; m < nmol; ++m) order[m] = m;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h[a].n > h[b].n; });
+
+  // persistent grid: as many workgroups as fit on the device at once
+  int dev = 0, ncu = 0, occ = 0;
+  SEQX_HIP(hipGetDevice(&dev));
+  SEQX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (f32)
+    SEQX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sigma_items_kernel<float>, 256, 0));
+  else
+    SEQX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sigma_items_kernel<double>, 256, 0));
+  const int G = std::max(1, ncu * std::max(1, occ));
+  const long scr_stride = (scr + 63) / 64 * 64;
+
+  w.mols.ensure(nmol);
+  w.order.ensure(nmol);
+  for (DBuf<int>* b : {&w.S, &w.knew, &w.active, &w.coll, &w.qcol, &w.conv}) b->ensure(nmol);
+  w.unc.ensure(static_cast<size_t>(nmol) * K);
+  w.counters.ensure(4);
+  w.nsig.ensure(3);
+  w.stamps.ensure(2 * static_cast<size_t>(G));
+  w.items.ensure(static_cast<size_t>(nmol) * std::max(maxnew, K));
+  w.V.ensure(vtot);
+  w.AV.ensure(vtot);
+  w.X.ensure(xtot);
+  w.Wc.ensure(xtot);
+  w.TV.ensure(ttot);
+  w.TAV.ensure(ttot);
+  w.Mp.ensure(static_cast<size_t>(nmol) * Smax * Smax);
+  w.evec.ensure(static_cast<size_t>(nmol) * Smax * Smax);
+  w.eval.ensure(static_cast<size_t>(nmol) * Smax);
+  w.omega.ensure(static_cast<size_t>(nmol) * K);
+  w.rnorm.ensure(static_cast<size_t>(nmol) * K);
+  if (f32) w.scratch32.ensure(static_cast<size_t>(G) * scr_stride);
+  else w.scratch64.ensure(static_cast<size_t>(G) * scr_stride);
+
+  // order against the caller's stream
+  hipEvent_t ev_in, ev_a, ev_b;
+  SEQX_HIP(hipEventCreate(&ev_in));
+  SEQX_HIP(hipEventCreate(&ev_a));
+  SEQX_HIP(hipEventCreate(&ev_b));
+  auto destroy_events = [&] {
+    for (hipEvent_t e : {ev_in, ev_a, ev_b}) (void)hipEventDestroy(e);
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  try {
+    SEQX_HIP(hipEventRecord(ev_in, user_stream));
+    SEQX_HIP(hipStreamWaitEvent(st, ev_in, 0));
+    SEQX_HIP(hipMemcpyAsync(w.order.p, order.data(), nmol * sizeof(int), hipMemcpyHostToDevice, st));
+    std::vector<int> zero4(4, 0);
+    SEQX_HIP(hipMemcpyAsync(w.counters.p, zero4.data(), 4 * sizeof(int), hipMemcpyHostToDevice, st));
+    const long long z3[3] = {0, 0, 0};
+    SEQX_HIP(hipMemcpyAsync(w.nsig.p, z3, 3 * sizeof(long long), hipMemcpyHostToDevice, st));
+
+    auto upload_desc = [&] {
+      SEQX_HIP(hipMemcpyAsync(w.mols.p, h.data(), nmol * sizeof(MolDesc), hipMemcpyHostToDevice, st));
+    };
+    auto launch_sigma = [&] {
+      if (f32)
+        hipLaunchKernelGGL(sigma_items_kernel<float>, dim3(G), dim3(256), 0, st, w.mols.p, w.items.p, w.counters.p,
+                           w.V.p, w.AV.p, w.scratch32.p, scr_stride, w.stamps.p);
+      else
+        hipLaunchKernelGGL(sigma_items_kernel<double>, dim3(G), dim3(256), 0, st, w.mols.p, w.items.p, w.counters.p,
+                           w.V.p, w.AV.p, w.scratch64.p, scr_stride, w.stamps.p);
+      SEQX_LAUNCH_CHECK();
+    };
+
+    // ---- autotuner: per size bucket, time each tile variant on the bucket's molecules
+    const int pk = f32 ? 0 : 1;
+    std::vector<int> bucket(nmol);
+    for (int m = 0; m < nmol; ++m) bucket[m] = bucket_of(h[m].n);
+    upload_desc();
+    hipLaunchKernelGGL(guess_kernel, dim3(nmol), dim3(256), 0, st, nmol, w.mols.p, K, w.V.p, w.S.p, w.knew.p,
+                       w.active.p, w.conv.p, w.coll.p, w.qcol.p);
+    SEQX_LAUNCH_CHECK();
+    const auto ta0 = std::chrono::steady_clock::now();
+    for (int b = 0; b < kNumSizeBuckets; ++b) {
+      std::vector<int> mb;
+      for (int m = 0; m < nmol; ++m)
+        if (bucket[m] == b) mb.push_back(m);
+      if (mb.empty()) continue;
+      if (!opt.autotune) {
+        tune.best[pk][b] = 2;
+        continue;
+      }
+      if (tune.tuned[pk][b]) continue;
+      // sample: up to 2 G items of this bucket (the first one or two guess vectors)
+      std::vector<int2> it;
+      for (int m : mb)
+        for (int j = 0; j < std::min<long>(2, h[m].nov) && static_cast<int>(it.size()) < 2 * G; ++j)
+          it.push_back(make_int2(m, j));
+      const int ni = static_cast<int>(it.size());
+      SEQX_HIP(hipMemcpyAsync(w.items.p, it.data(), ni * sizeof(int2), hipMemcpyHostToDevice, st));
+      SEQX_HIP(hipMemcpyAsync(w.counters.p, &ni, sizeof(int), hipMemcpyHostToDevice, st));
+      double best = 1e300;
+      for (int var = 0; var < kNumTileVariants; ++var) {
+        for (int m : mb) h[m].variant = var;
+        upload_desc();
+        launch_sigma();  // warm-up
+        SEQX_HIP(hipEventRecord(ev_a, st));
+        for (int rep = 0; rep < 3; ++rep) launch_sigma();
+        SEQX_HIP(hipEventRecord(ev_b, st));
+        SEQX_HIP(hipEventSynchronize(ev_b));
+        const double t = ms_between(ev_a, ev_b) / 3.0;
+        tune.ms[pk][b][var] = t;
+        if (t < best) {
+          best = t;
+          tune.best[pk][b] = var;
+        }
+      }
+      tune.tuned[pk][b] = true;
+    }
+    res.t_autotune_ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - ta0).count();
+    for (int m = 0; m < nmol; ++m) h[m].variant = tune.best[pk][bucket[m]];
+    for (int b = 0; b < kNumSizeBuckets; ++b) res.variant_of_bucket[b] = tune.best[pk][b];
+    upload_desc();
+    SEQX_HIP(hipMemcpyAsync(w.counters.p, zero4.data(), 4 * sizeof(int), hipMemcpyHostToDevice, st));
+
+    // ---- one iteration as a fixed launch sequence
+    const int Q = 2 * K;
+    auto iteration = [&](bool timed) {
+      hipLaunchKernelGGL(items_kernel, dim3(1), dim3(256), 0, st, nmol, w.mols.p, w.order.p, w.S.p, w.knew.p,
+                         w.active.p, w.items.p, w.counters.p, w.nsig.p);
+      launch_sigma();
+      if (timed) hipLaunchKernelGGL(stamp_span_kernel, dim3(1), dim3(256), 0, st, G, w.stamps.p, w.nsig.p + 1);
+      hipLaunchKernelGGL(project_kernel, dim3(nmol), dim3(256), 0, st, w.mols.p, Smax, w.V.p, w.AV.p, w.Mp.p, w.S.p,
+                         w.knew.p, w.active.p);
+      hipLaunchKernelGGL(eig_kernel, dim3(nmol), dim3(256), 0, st, Smax, w.Mp.p, w.S.p, w.active.p, w.evec.p,
+                         w.eval.p);
+      hipLaunchKernelGGL(ritz_kernel, dim3(nmol, K), dim3(256), 0, st, w.mols.p, K, Smax, opt.tol, w.V.p, w.AV.p,
+                         w.evec.p, w.eval.p, w.S.p, w.active.p, w.X.p, w.Wc.p, w.omega.p, w.rnorm.p);
+      hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, st, nmol, K, Smax, opt.tol, w.rnorm.p, w.S.p,
+                         w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.conv.p, w.counters.p);
+      hipLaunchKernelGGL(collapse_kernel, dim3(nmol, Q), dim3(256), 0, st, w.mols.p, Smax, w.V.p, w.AV.p, w.evec.p,
+                         w.S.p, w.coll.p, w.qcol.p, w.TV.p, w.TAV.p);
+      hipLaunchKernelGGL(collapse_copy_kernel, dim3(nmol, Q + 1), dim3(256), 0, st, w.mols.p, Smax, w.TV.p, w.TAV.p,
+                         w.eval.p, w.S.p, w.coll.p, w.qcol.p, w.V.p, w.AV.p, w.Mp.p);
+      hipLaunchKernelGGL(ortho_kernel, dim3(nmol), dim3(256), 0, st, w.mols.p, K, Smax, w.V.p, w.Wc.p, w.S.p,
+                         w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.conv.p, w.counters.p);
+      SEQX_LAUNCH_CHECK();
+    };
+    if (opt.graph) {
+      // capture one iteration; if the runtime refuses any step, run eagerly instead
+      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        try {
+          iteration(true);
+        } catch (const Error&) {
+          ok = false;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        graph = g;
+        ok = ok && e == hipSuccess && graph != nullptr;
+        ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipGetLastError();
+      }
+      if (!ok) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+      }
+      res.used_graph = ok;
+    }
+    SEQX_HIP(hipEventRecord(ev_a, st));
+    int it = 0, counters[4] = {0, 0, 0, 0};
+    for (it = 1; it <= opt.max_iter; ++it) {
+      if (exec) SEQX_HIP(hipGraphLaunch(exec, st));
+      else iteration(true);
+      SEQX_HIP(hipMemcpyAsync(counters, w.counters.p, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+      SEQX_HIP(hipStreamSynchronize(st));
+      if (counters[1] == 0) break;
+    }
+    SEQX_HIP(hipEventRecord(ev_b, st));
+    SEQX_HIP(hipEventSynchronize(ev_b));
+    res.t_solve_ms = ms_between(ev_a, ev_b);
+    res.iterations = std::min(it, opt.max_iter);
+    long long ns[3] = {0, 0, 0};
+    res.conv_iter.resize(nmol);
+    SEQX_HIP(hipMemcpyAsync(ns, w.nsig.p, 3 * sizeof(long long), hipMemcpyDeviceToHost, st));
+    SEQX_HIP(hipMemcpyAsync(res.conv_iter.data(), w.conv.p, nmol * sizeof(int), hipMemcpyDeviceToHost, st));
+    SEQX_HIP(hipStreamSynchronize(st));
+    res.n_sigma = ns[0];
+    res.sigma_flops = static_cast<double>(ns[2]);
+    int rate_khz = 0;  // device wall clock (the stamps of the sigma launches)
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && rate_khz > 0)
+      res.t_sigma_ms = static_cast<double>(ns[1]) / rate_khz;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    for (int m = 0; m < nmol; ++m)
+      if (res.conv_iter[m] <= 0)
+        throw Error(kEDavNoConv, res.conv_iter[m] < 0 ? "batched Davidson: no new direction for a molecule"
+                                                      : "batched Davidson did not converge in " +
+                                                            std::to_string(opt.max_iter) + " iterations");
+    // ---- amplitudes and properties per molecule, on the caller's stream
+    SEQX_HIP(hipEventRecord(ev_b, st));
+    SEQX_HIP(hipStreamWaitEvent(user_stream, ev_b, 0));
+    for (int m = 0; m < nmol; ++m) {
+      const double* Xm = w.X.p + h[m].xbase;
+      finalize_roots(*mols[m], 0, K, w.omega.p + static_cast<long>(m) * K, Xm, Xm, sig, w.fin, user_stream);
+      mols[m]->dav_iterations = res.conv_iter[m];
+    }
+  } catch (...) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamSynchronize(st);
+    destroy_events();
+    throw;
+  }
+  destroy_events();
+  return res;
+}
+
+}  // namespace seqx

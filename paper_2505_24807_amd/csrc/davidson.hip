@@ -367,6 +367,36 @@ int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov,
 
 }  // namespace
 
+void finalize_roots(DeviceMolecule& m, int theory, int K, const double* om, const double* Tv, const double* Uv,
+                    SigmaWork& sig, DBuf<double>& scratch, hipStream_t st) {
+  const long nov = static_cast<long>(m.nocc) * m.nvirt;
+  const bool tdhf = theory == 1;
+  m.omega.ensure(K);
+  m.X.ensure(static_cast<size_t>(K) * nov);
+  m.Y.ensure(static_cast<size_t>(K) * nov);
+  m.f.ensure(K);
+  m.mu.ensure(3 * K);
+  copy(st, m.omega.p, om, K);
+  hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(nov, 256), K), dim3(256), 0, st, nov, tdhf ? 1 : 0, Tv, Uv,
+                     m.X.p, m.Y.p);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3(K), dim3(256), 0, st, nov, m.X.p, m.Y.p);
+  SEQX_LAUNCH_CHECK();
+  // transition densities of X + Y (T for TDHF, X for CIS)
+  const long nn = static_cast<long>(m.nao) * m.nao;
+  scratch.ensure(static_cast<size_t>(K) * (nov + nn));
+  double* T = scratch.p;
+  double* TA = scratch.p + static_cast<long>(K) * nov;
+  copy(st, T, m.X.p, K * nov);
+  axpby(st, K * nov, 1.0, m.Y.p, 1.0, T);
+  forward_transform(m, K, T, TA, sig, st);
+  hipLaunchKernelGGL(dipole_kernel, dim3(K), dim3(256), 0, st, m.natoms, m.nao, TA, m.slot.p, m.ao_off.p, m.xyz.p,
+                     m.elems, m.omega.p, m.mu.p, m.f.p);
+  SEQX_LAUNCH_CHECK();
+  SEQX_HIP(hipStreamSynchronize(st));
+  m.nroots = K;
+  m.theory = theory;
+}
+
 DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, DavWork& w, hipStream_t st) {
   const int o = m.nocc, v = m.nvirt, K = opt.nroots;
   const long nov = static_cast<long>(o) * v;
@@ -639,21 +669,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   if (!converged) throw Error(kEDavNoConv, "Davidson did not converge in " + std::to_string(opt.max_iter) + " iterations");
 
   // 9. amplitudes, sign convention, properties
-  copy(st, m.omega.p, om, K);
-  hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(nov, 256), K), dim3(256), 0, st, nov, tdhf ? 1 : 0, w.Tv.p, Uv,
-                     m.X.p, m.Y.p);
-  hipLaunchKernelGGL(sign_fix_kernel, dim3(K), dim3(256), 0, st, nov, m.X.p, m.Y.p);
-  SEQX_LAUNCH_CHECK();
-  // transition densities of X + Y (T for TDHF, X for CIS)
-  const long nn = static_cast<long>(m.nao) * m.nao;
-  w.scratch.ensure(std::max<size_t>(static_cast<size_t>(2 * K) * nov, static_cast<size_t>(K) * nn));
-  copy(st, w.Tv.p, m.X.p, K * nov);
-  axpby(st, K * nov, 1.0, m.Y.p, 1.0, w.Tv.p);
-  forward_transform(m, K, w.Tv.p, w.scratch.p, w.sig, st);
-  hipLaunchKernelGGL(dipole_kernel, dim3(K), dim3(256), 0, st, m.natoms, m.nao, w.scratch.p, m.slot.p, m.ao_off.p,
-                     m.xyz.p, m.elems, m.omega.p, m.mu.p, m.f.p);
-  SEQX_LAUNCH_CHECK();
-  SEQX_HIP(hipStreamSynchronize(st));
+  finalize_roots(m, opt.theory, K, om, w.Tv.p, Uv, w.sig, w.scratch, st);
   m.nroots = K;
   m.theory = opt.theory;
   m.dav_iterations = it;

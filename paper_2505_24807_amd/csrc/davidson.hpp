@@ -44,6 +44,13 @@ struct DavResult {
   std::vector<std::vector<double>> omega_iter;  // Ritz values (hartree) per iteration
 };
 
+// Amplitudes and properties of K converged roots: X, Y from T = X+Y and
+// U = X-Y rows (TDHF; CIS passes X in Tv and ignores Uv), the sign convention,
+// AO transition densities and ZDO transition dipoles and oscillator strengths.
+// om: device omega [K] (hartree).  Fills m.omega, m.X, m.Y, m.f, m.mu.
+void finalize_roots(DeviceMolecule& m, int theory, int K, const double* om, const double* Tv, const double* Uv,
+                    SigmaWork& sig, DBuf<double>& scratch, hipStream_t st);
+
 // Lowest roots of molecule m; fills m.omega, m.X, m.Y, m.f, m.mu.
 // Throws Error(kEDavNoConv) / Error(kEUnstable) on failure.
 DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, DavWork& w, hipStream_t st);

@@ -37,84 +37,9 @@ __global__ void __launch_bounds__(128) exchange_pair_kernel(int npairs, const in
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
   const int I = blockIdx.y;
-  const int A = pairs[p].x, B = pairs[p].y;
-  const int oa = ao_off[A], ob = ao_off[B];
-  const TR* Rv = R + I * sR;
-  double S[NA][NB], D[NA][NB];
-#pragma unroll
-  for (int i = 0; i < NA; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const double rab = static_cast<double>(Rv[static_cast<long>(oa + i) * n + ob + j]);
-      const double rba = static_cast<double>(Rv[static_cast<long>(ob + j) * n + oa + i]);
-      S[i][j] = 0.5 * (rab + rba);
-      D[i][j] = 0.5 * (rab - rba);
-    }
-  double KS[NA][NB], KD[NA][NB];
-#pragma unroll
-  for (int i = 0; i < NA; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      KS[i][j] = 0.0;
-      KD[i][j] = 0.0;
-    }
-  constexpr int NPA = NA == 4 ? 10 : 1, NPB = NB == 4 ? 10 : 1;
-  const double* Wb = W + static_cast<long>(pi_off[A]) * ldw + pi_off[B];
-  // K(X)_AB[mu][nu] = sum_{lam in A, sig in B} (mu lam | nu sig) X[lam][sig]
-#pragma unroll
-  for (int P = 0; P < NPA; ++P) {
-    const int m = NA == 4 ? pair_first(P) : 0, l = NA == 4 ? pair_second(P) : 0;
-#pragma unroll
-    for (int Q = 0; Q < NPB; ++Q) {
-      const int u = NB == 4 ? pair_first(Q) : 0, s = NB == 4 ? pair_second(Q) : 0;
-      const double w = Wb[static_cast<long>(P) * ldw + Q];
-      // all orderings (mu, lam) of P and (nu, sig) of Q
-      KS[m][u] += w * S[l][s];
-      KD[m][u] += w * D[l][s];
-      if (u != s) {
-        KS[m][s] += w * S[l][u];
-        KD[m][s] += w * D[l][u];
-      }
-      if (m != l) {
-        KS[l][u] += w * S[m][s];
-        KD[l][u] += w * D[m][s];
-        if (u != s) {
-          KS[l][s] += w * S[m][u];
-          KD[l][s] += w * D[m][u];
-        }
-      }
-    }
-  }
-  TF* f1 = F1 + I * sF;
-  TF* f2 = (MODE == kTwo) ? F2 + I * sF : nullptr;
-#pragma unroll
-  for (int i = 0; i < NA; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const long ab = static_cast<long>(oa + i) * n + ob + j;
-      const long ba = static_cast<long>(ob + j) * n + oa + i;
-      if (MODE == kTwo) {
-        f1[ab] = static_cast<TF>(cK * KS[i][j]);
-        f1[ba] = static_cast<TF>(cK * KS[i][j]);
-        f2[ab] = static_cast<TF>(cKa * KD[i][j]);
-        f2[ba] = static_cast<TF>(-cKa * KD[i][j]);
-      } else if (MODE == kSum) {
-        f1[ab] = static_cast<TF>(cK * KS[i][j] + cKa * KD[i][j]);
-        f1[ba] = static_cast<TF>(cK * KS[i][j] - cKa * KD[i][j]);
-      } else {
-        f1[ab] = static_cast<TF>(cK * KS[i][j]);
-        f1[ba] = static_cast<TF>(cK * KS[i][j]);
-      }
-    }
+  exchange_pair<NA, NB, MODE, TR, TF>(pairs[p].x, pairs[p].y, ao_off, pi_off, W, ldw, R + I * sR, n, F1 + I * sF,
+                                      MODE == kTwo ? F2 + I * sF : nullptr, cK, cKa);
 }
-
-// one-centre exchange K1(X)_mn = g_mn X_mn + (m == n ? sum_{l != m} h_ml X_ll : h_mn X_nm)
-__device__ inline double g1(const Elem& e, int m, int n) {
-  if (m == 0 && n == 0) return e.gss;
-  if (m == 0 || n == 0) return e.gsp;
-  return m == n ? e.gpp : e.gp2;
-}
-__device__ inline double h1(const Elem& e, int m, int n) { return (m == 0 || n == 0) ? e.hsp : e.hpp; }
 
 template <int MODE, class TR, class TF>
 __global__ void diag_block_kernel(int natoms, int k, const int* __restrict__ slot, const int* __restrict__ ao_off,
@@ -126,41 +51,8 @@ __global__ void diag_block_kernel(int natoms, int k, const int* __restrict__ slo
   const int I = blockIdx.y;
   if (A >= natoms) return;
   const Elem e = elems[slot[A]];
-  const int na = e.nao, o = ao_off[A], po = pi_off[A];
-  const TR* Rv = R + I * sR;
-  double X[4][4];
-  for (int i = 0; i < na; ++i)
-    for (int j = 0; j < na; ++j) X[i][j] = static_cast<double>(Rv[static_cast<long>(o + i) * n + o + j]);
-  TF* f1 = F1 + I * sF;
-  TF* f2 = (MODE == kTwo) ? F2 + I * sF : nullptr;
-  for (int m = 0; m < na; ++m)
-    for (int nn = 0; nn < na; ++nn) {
-      const double S = 0.5 * (X[m][nn] + X[nn][m]), Dv = 0.5 * (X[m][nn] - X[nn][m]);
-      double kS, kD;
-      if (na == 1) {
-        kS = e.gss * S;
-        kD = 0.0;
-      } else if (m == nn) {
-        kS = g1(e, m, m) * X[m][m];
-        for (int l = 0; l < 4; ++l)
-          if (l != m) kS += h1(e, m, l) * X[l][l];
-        kD = 0.0;
-      } else {
-        // K1(S) and K1(D) for the symmetric / antisymmetric parts
-        kS = (g1(e, m, nn) + h1(e, m, nn)) * S;
-        kD = (g1(e, m, nn) - h1(e, m, nn)) * Dv;
-      }
-      const double jv = J[static_cast<long>(po + (na == 1 ? 0 : pair_index(m, nn))) * k + I];
-      const long idx = static_cast<long>(o + m) * n + o + nn;
-      if (MODE == kTwo) {
-        f1[idx] = static_cast<TF>(cJ * jv + cK * kS);
-        f2[idx] = static_cast<TF>(cKa * kD);
-      } else if (MODE == kSum) {
-        f1[idx] = static_cast<TF>(cJ * jv + cK * kS + cKa * kD);
-      } else {
-        f1[idx] = static_cast<TF>(cJ * jv + cK * kS);
-      }
-    }
+  diag_block<MODE, TR, TF>(e, ao_off[A], pi_off[A], J + I, k, R + I * sR, n, F1 + I * sF,
+                           MODE == kTwo ? F2 + I * sF : nullptr, cJ, cK, cKa);
 }
 
 template <int MODE, class TR, class TF>

@@ -1,6 +1,7 @@
 // NDDO contraction of AO densities with the ERI tables (Fock-like build).
 #pragma once
 
+#include "fock_blocks.hpp"
 #include "molecule.hpp"
 
 namespace seqx {
@@ -14,7 +15,6 @@ namespace seqx {
 //   kSymm  : F1 = cJ J(S) + cK K(S)          (R symmetric, SCF)
 // J lives on atom-diagonal blocks; K has one-centre terms on diagonal blocks
 // and the two-centre term on every off-diagonal block.
-enum GMode { kTwo = 0, kSum = 1, kSymm = 2 };
 
 struct GWork {
   DBuf<double> r, J;  // packed densities [k][np] and Coulomb [np][k]

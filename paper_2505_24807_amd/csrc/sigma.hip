@@ -51,9 +51,8 @@ void forward_transform(const DeviceMolecule& m, int k, const double* X, double* 
   // T1_I (n x v) = C[:, :o] (n x o, ld n) * X_I (o x v)
   dgemm(st, false, false, n, v, o, 1.0, m.C.p, n, 0, X, v, static_cast<long>(o) * v, 0.0, w.T1.p, v,
         static_cast<long>(n) * v, k);
-  // T_I (n x n) = T1_I * C[:, o:]^T
-  dgemm(st, false, true, n, n, v, 1.0, w.T1.p, v, static_cast<long>(n) * v, m.C.p + o, n, 0, 0.0, T, n,
-        static_cast<long>(n) * n, k);
+  // T_I (n x n) = T1_I * C[:, o:]^T, one GEMM over the stacked T1_I
+  dgemm(st, false, true, k * n, n, v, 1.0, w.T1.p, v, 0, m.C.p + o, n, 0, 0.0, T, n, 0, 1);
 }
 
 void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
@@ -94,16 +93,16 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
       // T1_I (n x v) = C[:, :o] V_I
       dgemm(st, false, false, n, v, o, 1.0, m.C.p, n, 0, Vc, v, ov, 0.0, w.T1.p, v, nv, kc);
       SEQX_HIP(hipEventRecord(ev[1], st));
-      // R_I (n x n) = T1_I C[:, o:]^T
-      dgemm(st, false, true, n, n, v, 1.0, w.T1.p, v, nv, m.C.p + o, n, 0, 0.0, w.R.p, n, nn, kc);
+      // R_I (n x n) = T1_I C[:, o:]^T: the T1_I are stacked rows, so one GEMM with M = kc n
+      dgemm(st, false, true, kc * n, n, v, 1.0, w.T1.p, v, 0, m.C.p + o, n, 0, 0.0, w.R.p, n, 0, 1);
       SEQX_HIP(hipEventRecord(ev[2], st));
       if (tdhf)
         build_G(m, kc, w.R.p, nn, w.F.p, w.F.p + kc * nn, nn, kTwo, 4.0, -2.0, -2.0, w.g, st);
       else
         build_G(m, kc, w.R.p, nn, w.F.p, static_cast<double*>(nullptr), nn, kSum, 2.0, -1.0, -1.0, w.g, st);
       SEQX_HIP(hipEventRecord(ev[3], st));
-      // Z_b (n x v) = F_b (n x n) * C[:, o:]
-      dgemm(st, false, false, n, v, n, 1.0, w.F.p, n, nn, m.C.p + o, n, 0, 0.0, w.Z.p, v, nv, nb);
+      // Z_b (n x v) = F_b (n x n) * C[:, o:], all nb at once (M = nb n)
+      dgemm(st, false, false, nb * n, v, n, 1.0, w.F.p, n, 0, m.C.p + o, n, 0, 0.0, w.Z.p, v, 0, 1);
       SEQX_HIP(hipEventRecord(ev[4], st));
       // out_b (o x v) = C[:, :o]^T * Z_b + de o V_b
       dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p, v, nv, 0.0, out1 + c0 * os, v, os, kc, &ep);
@@ -115,14 +114,14 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
       to_float(st, kc * ov, Vc, w.V32.p);
       sgemm(st, false, false, n, v, o, 1.0, C32, n, 0, w.V32.p, v, ov, 0.0, w.T1s.p, v, nv, kc);
       SEQX_HIP(hipEventRecord(ev[1], st));
-      sgemm(st, false, true, n, n, v, 1.0, w.T1s.p, v, nv, C32 + o, n, 0, 0.0, w.Rs.p, n, nn, kc);
+      sgemm(st, false, true, kc * n, n, v, 1.0, w.T1s.p, v, 0, C32 + o, n, 0, 0.0, w.Rs.p, n, 0, 1);
       SEQX_HIP(hipEventRecord(ev[2], st));
       if (tdhf)
         build_G(m, kc, w.Rs.p, nn, w.Fs.p, w.Fs.p + kc * nn, nn, kTwo, 4.0, -2.0, -2.0, w.g, st);
       else
         build_G(m, kc, w.Rs.p, nn, w.Fs.p, static_cast<float*>(nullptr), nn, kSum, 2.0, -1.0, -1.0, w.g, st);
       SEQX_HIP(hipEventRecord(ev[3], st));
-      sgemm(st, false, false, n, v, n, 1.0, w.Fs.p, n, nn, C32 + o, n, 0, 0.0, w.Zs.p, v, nv, nb);
+      sgemm(st, false, false, nb * n, v, n, 1.0, w.Fs.p, n, 0, C32 + o, n, 0, 0.0, w.Zs.p, v, 0, 1);
       SEQX_HIP(hipEventRecord(ev[4], st));
       sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, w.Zs.p, v, nv, 0.0, out1 + c0 * os, v, os, kc, &ep);
       if (tdhf)

@@ -40,7 +40,8 @@ class ScfOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("theory", C.c_int32), ("nroots", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("max_subspace", C.c_int32), ("mem_budget_bytes", C.c_size_t), ("precision", C.c_int32),
-                ("guess", C.c_int32), ("n_user_guess", C.c_int32), ("user_guess", C.POINTER(C.c_double))]
+                ("guess", C.c_int32), ("n_user_guess", C.c_int32), ("user_guess", C.POINTER(C.c_double)),
+                ("batched", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -49,7 +50,8 @@ class Stats(C.Structure):
                 ("t_davidson_s", C.c_double), ("t_sigma_s", C.c_double), ("time_to_roots_s", C.c_double * 64),
                 ("n_history", C.c_int32), ("phase_ms", C.c_double * 5), ("phase_launches", C.c_int64 * 5),
                 ("phase_flops", C.c_double * 5), ("phase_bytes", C.c_double * 5), ("dav_phase_ms", C.c_double * 8),
-                ("n_sigma_fp64", C.c_int64), ("refine_iteration", C.c_int32)]
+                ("n_sigma_fp64", C.c_int64), ("refine_iteration", C.c_int32), ("t_autotune_s", C.c_double),
+                ("batched_graph", C.c_int32), ("tile_variant", C.c_int32 * 5), ("batched_sigma_flops", C.c_double)]
 
     DAV_PHASES = ["sigma", "projection", "subspace eig", "ritz+residual", "check", "precond", "collapse", "ortho"]
 
@@ -220,14 +222,14 @@ class Job:
                                                precision))
 
     def solve(self, theory=TDHF, nroots=3, tol=1e-6, max_iter=100, max_subspace=0, mem_budget_bytes=0,
-              precision=FP64, guess=GUESS_GAP, user_guess=None):
+              precision=FP64, guess=GUESS_GAP, user_guess=None, batched=False):
         ug = None
         n_ug = 0
         if user_guess is not None:
             ug = np.ascontiguousarray(user_guess, dtype=np.float64)
             n_ug = ug.shape[0]
         o = SolveOpts(theory, nroots, tol, max_iter, max_subspace, mem_budget_bytes, precision, guess, n_ug,
-                      _dptr(ug) if ug is not None else None)
+                      _dptr(ug) if ug is not None else None, 1 if batched else 0)
         self.nroots = 0
         self._check(self.lib.seqx_solve(self.h, C.byref(o)))
         self.nroots = nroots
