@@ -13,7 +13,7 @@ step; time-to-roots alongside), the roofline of the dominant sigma-build kernel
 bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--precision fp32|fp64]
-                    [--no-fp64-comparison] [--no-batched] [--no-cpu-baseline]
+                    [--no-fp64-comparison] [--no-batched] [--no-batched-loop] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -160,7 +160,7 @@ def roofline_of(r, dtype):
             "flops_per_launch": flops / launches, "avg_launch_ms": ms / launches}
 
 
-def batched_c4(ctx, steps):
+def batched_c4(ctx, steps, loop=True):
     """512 uneven molecules, CIS, 5 roots, tol 1e-5: the batched solver (FP32
     fused products, one launch per iteration, replayed graph) against the plain
     FP64 Davidson run molecule by molecule on the same GPU.  Integrals and SCF
@@ -184,11 +184,13 @@ def batched_c4(ctx, steps):
     torch.cuda.synchronize()
     t_b = (time.perf_counter() - t0) / steps
     st = sts[-1]
-    t0 = time.perf_counter()
-    job.solve(theory=seqx.CIS, nroots=5, tol=1e-5, max_iter=300, precision=seqx.FP64)
-    torch.cuda.synchronize()
-    t_loop = time.perf_counter() - t0
-    n_loop = job.stats().n_sigma
+    t_loop, n_loop = None, None
+    if loop:
+        t0 = time.perf_counter()
+        job.solve(theory=seqx.CIS, nroots=5, tol=1e-5, max_iter=300, precision=seqx.FP64)
+        torch.cuda.synchronize()
+        t_loop = time.perf_counter() - t0
+        n_loop = job.stats().n_sigma
     job.free()
     fl, tsig = st.batched_sigma_flops, st.t_sigma_s
     return {"workload": "512 uneven molecules (polyenes, alkanes, water clusters; 6-62 atoms, n 12-142), seed 512, "
@@ -202,8 +204,31 @@ def batched_c4(ctx, steps):
                                      "peak": PEAK["fp32"], "unit": "TFLOP/s",
                                      "frac": round(fl / tsig / 1e12 / PEAK["fp32"], 4) if tsig > 0 else None,
                                      "kernel": "sigma_items_kernel<float>"},
-            "per_molecule_fp64_loop_s": round(t_loop, 3), "per_molecule_fp64_loop_n_sigma": n_loop,
-            "speedup_vs_fp64_loop": round(t_loop / t_b, 2), "prepare_s": round(t_prep, 3)}
+            "per_molecule_fp64_loop_s": round(t_loop, 3) if loop else None, "per_molecule_fp64_loop_n_sigma": n_loop,
+            "speedup_vs_fp64_loop": round(t_loop / t_b, 2) if loop else None, "prepare_s": round(t_prep, 3)}
+
+
+def sigma_only(ctx, mol, k, reps, precision):
+    """Only the sigma build on (H2O)330: k seeded trial vectors, `reps` builds,
+    after one warm-up (a short run for hardware-counter passes)."""
+    import torch
+    from paper_2505_24807_amd import seqx
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    n, o, v = job.dims()
+    g = torch.Generator(device="cuda").manual_seed(330)
+    V = torch.randn((k, o, v), generator=g, device="cuda", dtype=torch.float64)
+    out1 = torch.empty_like(V)
+    out2 = torch.empty_like(V)
+    job.sigma_device(V, out1, out2, theory=seqx.TDHF, precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        job.sigma_device(V, out1, out2, theory=seqx.TDHF, precision=precision)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    job.free()
+    return {"sigma_only": True, "k": k, "reps": reps, "precision": precision,
+            "sigma_vectors_per_s": round(k * reps / dt, 1), "seconds": round(dt, 4)}
 
 
 def main():
@@ -215,8 +240,12 @@ def main():
                     help="transform precision of the timed run (fp32: mixed mode finishing in FP64)")
     ap.add_argument("--no-fp64-comparison", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-molecule batched CIS section")
+    ap.add_argument("--no-batched-loop", action="store_true",
+                    help="skip the per-molecule FP64 comparison loop of the batched section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-vectors", type=int, default=2)
+    ap.add_argument("--sigma-only", type=int, default=0, metavar="K",
+                    help="time only K-vector sigma builds of (H2O)330 (for counter passes) and exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -243,6 +272,10 @@ def main():
     pr = params.load()
     ctx.set_params(*seqx.params_table(pr))
     mol = molecules.workload_water330()
+    if args.sigma_only > 0:
+        prec = seqx.FP32 if args.precision == "fp32" else seqx.FP64
+        print(json.dumps(sigma_only(ctx, mol, args.sigma_only, args.steps, prec)))
+        return
     ref = _golden()
     K = args.steps
     prec = seqx.FP32 if args.precision == "fp32" else seqx.FP64
@@ -267,7 +300,7 @@ def main():
         s64["roofline"] = roofline_of(r64, "fp64")
         out["fp64_comparison"] = s64
     if not args.no_batched:
-        out["batched_c4"] = batched_c4(ctx, K)
+        out["batched_c4"] = batched_c4(ctx, K, loop=not args.no_batched_loop)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mol, pr, args.cpu_vectors)
     print(json.dumps(out))

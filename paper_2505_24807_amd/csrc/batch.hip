@@ -24,9 +24,12 @@
 
 #include "batch.hpp"
 #include "fock_blocks.hpp"
+#include "jacobi.hpp"
 #include "linalg.hpp"
 
 namespace seqx {
+
+static_assert(kBatchMaxSub <= kJacobiMax, "the batched subspace must fit the LDS eigensolver");
 
 namespace {
 
@@ -338,137 +341,62 @@ __global__ void __launch_bounds__(256) items_kernel(int nmol, const MolDesc* __r
   }
 }
 
-// New columns of M = V^T A V (column-major, ld Smax), both triangles; then S += knew.
+// New columns of M = V^T A V (column-major, ld Smax), both triangles: block
+// (m, j) forms column S_m + j against rows s <= S_m + j.  S is advanced by
+// advance_kernel afterwards.
 __global__ void __launch_bounds__(256) project_kernel(const MolDesc* __restrict__ mols, int Smax,
                                                       const double* __restrict__ Vp, const double* __restrict__ AVp,
-                                                      double* __restrict__ Mp, int* S, const int* __restrict__ knew,
-                                                      const int* __restrict__ active) {
-  const int m = blockIdx.x;
-  if (!active[m]) return;
+                                                      double* __restrict__ Mp, const int* __restrict__ S,
+                                                      const int* __restrict__ knew, const int* __restrict__ active) {
+  const int m = blockIdx.x, jn = blockIdx.y;
+  if (!active[m] || jn >= knew[m]) return;
   const MolDesc md = mols[m];
   const long nov = md.nov;
-  const int S0 = S[m], S1 = S0 + knew[m];
+  const int j = S[m] + jn;
   const double* V = Vp + md.vbase;
-  const double* AV = AVp + md.vbase;
+  const double* b = AVp + md.vbase + j * nov;
   double* M = Mp + static_cast<long>(m) * Smax * Smax;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = S0; j < S1; ++j)
-    for (int s = wave; s <= j; s += 4) {
-      const double* a = V + s * nov;
-      const double* b = AV + j * nov;
-      double acc = 0.0;
-      for (long x = lane; x < nov; x += 64) acc += a[x] * b[x];
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        M[s + static_cast<long>(j) * Smax] = acc;
-        M[j + static_cast<long>(s) * Smax] = acc;
-      }
+  for (int s = wave; s <= j; s += 4) {
+    const double* a = V + s * nov;
+    double acc = 0.0;
+    for (long x = lane; x < nov; x += 64) acc += a[x] * b[x];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      M[s + static_cast<long>(j) * Smax] = acc;
+      M[j + static_cast<long>(s) * Smax] = acc;
     }
-  __syncthreads();
-  if (threadIdx.x == 0) S[m] = S1;
+  }
 }
 
-// Symmetric eigensolve of the S x S projected matrix of each molecule by
-// cyclic Jacobi with the round-robin (tournament) ordering: each round rotates
-// ne/2 disjoint index pairs at once (rows, then columns), ne = S rounded up to
-// even.  Stops when the off-diagonal sum of squares is below 1e-32 of the
-// total.  Eigenvalues ascending in eval, eigenvectors as columns of evec (ld Smax).
+__global__ void advance_kernel(int nmol, int* S, const int* __restrict__ knew, const int* __restrict__ active) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < nmol && active[m]) S[m] += knew[m];
+}
+
+// Symmetric eigensolve of the S x S projected matrix of each molecule
+// (Jacobi in LDS, jacobi.hpp).  Eigenvalues ascending in eval, eigenvectors
+// as columns of evec (ld Smax).
 __global__ void __launch_bounds__(256) eig_kernel(int Smax, const double* __restrict__ Mp, const int* __restrict__ S,
                                                   const int* __restrict__ active, double* __restrict__ evec,
                                                   double* __restrict__ eval) {
-  __shared__ double A[kBatchMaxSub][kBatchMaxSub + 1];
-  __shared__ double Q[kBatchMaxSub][kBatchMaxSub + 1];
-  __shared__ double rc[kBatchMaxSub / 2], rsn[kBatchMaxSub / 2];
-  __shared__ int rp[kBatchMaxSub / 2], rq[kBatchMaxSub / 2];
-  __shared__ double red[256];
-  __shared__ int perm[kBatchMaxSub];
+  __shared__ JacobiLds L;
   const int m = blockIdx.x;
   if (!active[m]) return;
   const int n = S[m];
   const double* M = Mp + static_cast<long>(m) * Smax * Smax;
   for (int idx = threadIdx.x; idx < n * n; idx += 256) {
     const int i = idx / n, j = idx % n;
-    A[i][j] = M[i + static_cast<long>(j) * Smax];
-    Q[i][j] = (i == j) ? 1.0 : 0.0;
+    L.A[i][j] = M[i + static_cast<long>(j) * Smax];
   }
   __syncthreads();
-  const int ne = n + (n & 1), half = ne / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
-      const int i = idx / n, j = idx % n;
-      const double a2 = A[i][j] * A[i][j];
-      tot += a2;
-      if (i != j) off += a2;
-    }
-    off = block_sum(off, red);
-    tot = block_sum(tot, red);
-    if (!(off > 1e-32 * tot)) break;
-    for (int r = 0; r < ne - 1; ++r) {
-      if (threadIdx.x < half) {
-        const int k = threadIdx.x;
-        int p = k == 0 ? r % (ne - 1) : (r + k) % (ne - 1);
-        int q = k == 0 ? ne - 1 : (r - k + ne - 1) % (ne - 1);
-        if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p][q];
-          if (apq != 0.0) {
-            const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
-            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-          }
-        } else {
-          q = -1;
-        }
-        rp[k] = p;
-        rq[k] = q;
-        rc[k] = c;
-        rsn[k] = s;
-      }
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < half * n; idx += 256) {  // rows p, q
-        const int k = idx / n, j = idx % n;
-        const int p = rp[k], q = rq[k];
-        if (q < 0) continue;
-        const double ap = A[p][j], aq = A[q][j];
-        A[p][j] = rc[k] * ap - rsn[k] * aq;
-        A[q][j] = rsn[k] * ap + rc[k] * aq;
-      }
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < half * n; idx += 256) {  // columns p, q of A and Q
-        const int k = idx / n, i = idx % n;
-        const int p = rp[k], q = rq[k];
-        if (q < 0) continue;
-        const double ap = A[i][p], aq = A[i][q];
-        A[i][p] = rc[k] * ap - rsn[k] * aq;
-        A[i][q] = rsn[k] * ap + rc[k] * aq;
-        const double vp = Q[i][p], vq = Q[i][q];
-        Q[i][p] = rc[k] * vp - rsn[k] * vq;
-        Q[i][q] = rsn[k] * vp + rc[k] * vq;
-      }
-      __syncthreads();
-    }
-  }
-  if (threadIdx.x == 0) {  // ascending order (stable selection)
-    for (int i = 0; i < n; ++i) perm[i] = i;
-    for (int i = 0; i < n; ++i) {
-      int b = i;
-      for (int j = i + 1; j < n; ++j)
-        if (A[perm[j]][perm[j]] < A[perm[b]][perm[b]]) b = j;
-      const int t = perm[i];
-      perm[i] = perm[b];
-      perm[b] = t;
-    }
-  }
-  __syncthreads();
+  jacobi_lds(n, L);
   double* ev = evec + static_cast<long>(m) * Smax * Smax;
   for (int idx = threadIdx.x; idx < n * n; idx += 256) {
     const int r = idx / n, i = idx % n;
-    ev[i + static_cast<long>(r) * Smax] = Q[i][perm[r]];
+    ev[i + static_cast<long>(r) * Smax] = L.Q[i][L.perm[r]];
   }
-  for (int r = threadIdx.x; r < n; r += 256) eval[static_cast<long>(m) * Smax + r] = A[perm[r]][perm[r]];
+  for (int r = threadIdx.x; r < n; r += 256) eval[static_cast<long>(m) * Smax + r] = L.A[L.perm[r]][L.perm[r]];
 }
 
 // Ritz vector j of molecule m, its residual r = A x - w x and norm; for an
@@ -605,53 +533,82 @@ __global__ void __launch_bounds__(256) collapse_copy_kernel(const MolDesc* __res
   }
 }
 
-// Orthonormalise the corrections of the unconverged roots against the basis
-// (classical Gram-Schmidt, two passes) and each other, append the survivors.
-__global__ void __launch_bounds__(256) ortho_kernel(const MolDesc* __restrict__ mols, int K, int Smax,
-                                                    double* __restrict__ Vp, double* __restrict__ Wcp, int* S,
-                                                    int* knew, int* active, int* coll, const int* __restrict__ qcol,
-                                                    const int* __restrict__ unc, int* conv,
-                                                    const int* __restrict__ counters) {
+// Corrections of the unconverged roots: remove their components along the
+// basis (classical Gram-Schmidt, two passes); block (m, u) for correction u.
+// A collapsed molecule's basis is its first qcol rows.
+__global__ void __launch_bounds__(256) deflate_kernel(const MolDesc* __restrict__ mols, int K,
+                                                      const double* __restrict__ Vp, double* __restrict__ Wcp,
+                                                      const int* __restrict__ S, const int* __restrict__ knew,
+                                                      const int* __restrict__ active, const int* __restrict__ coll,
+                                                      const int* __restrict__ qcol, const int* __restrict__ unc,
+                                                      double* __restrict__ n0p) {
   __shared__ double h[kBatchMaxSub];
+  __shared__ double red[256];
+  const int m = blockIdx.x, u = blockIdx.y;
+  if (!active[m] || u >= knew[m]) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov;
+  const int nb = coll[m] ? qcol[m] : S[m];
+  const double* V = Vp + md.vbase;
+  double* w = Wcp + md.xbase + unc[m * K + u] * nov;
+  double n0 = 0.0;
+  for (long x = threadIdx.x; x < nov; x += 256) n0 += w[x] * w[x];
+  n0 = block_sum(n0, red);
+  if (threadIdx.x == 0) n0p[m * K + u] = sqrt(n0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int s = wave; s < nb; s += 4) {
+      const double* a = V + s * nov;
+      double d = 0.0;
+      for (long x = lane; x < nov; x += 64) d += a[x] * w[x];
+      d = wave_sum(d);
+      if (lane == 0) h[s] = d;
+    }
+    __syncthreads();
+    for (long x = threadIdx.x; x < nov; x += 256) {
+      double t = w[x];
+      for (int s = 0; s < nb; ++s) t -= h[s] * V[s * nov + x];
+      w[x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Orthonormalise the deflated corrections among themselves (modified
+// Gram-Schmidt, twice) and append the survivors (norm above 1e-8 of the
+// correction's norm before deflation) to the basis.
+__global__ void __launch_bounds__(256) append_kernel(const MolDesc* __restrict__ mols, int K, int Smax,
+                                                     double* __restrict__ Vp, double* __restrict__ Wcp, int* S,
+                                                     int* knew, int* active, int* coll, const int* __restrict__ qcol,
+                                                     const int* __restrict__ unc, int* conv,
+                                                     const int* __restrict__ counters,
+                                                     const double* __restrict__ n0p) {
   __shared__ double red[256];
   const int m = blockIdx.x;
   if (!active[m]) return;
   const MolDesc md = mols[m];
   const long nov = md.nov;
-  int S0 = S[m];
-  if (coll[m]) S0 = qcol[m];
+  const int S0 = coll[m] ? qcol[m] : S[m];
   const int nu = knew[m];
   double* V = Vp + md.vbase;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int acc = 0;
   for (int u = 0; u < nu; ++u) {
     if (S0 + acc >= Smax) break;
     double* w = Wcp + md.xbase + unc[m * K + u] * nov;
-    double n0 = 0.0;
-    for (long x = threadIdx.x; x < nov; x += 256) n0 += w[x] * w[x];
-    n0 = sqrt(block_sum(n0, red));
-    const int nb = S0 + acc;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int s = wave; s < nb; s += 4) {
-        const double* a = V + s * nov;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int t = 0; t < acc; ++t) {
+        const double* a = V + static_cast<long>(S0 + t) * nov;
         double d = 0.0;
-        for (long x = lane; x < nov; x += 64) d += a[x] * w[x];
-        d = wave_sum(d);
-        if (lane == 0) h[s] = d;
+        for (long x = threadIdx.x; x < nov; x += 256) d += a[x] * w[x];
+        d = block_sum(d, red);
+        for (long x = threadIdx.x; x < nov; x += 256) w[x] -= d * a[x];
+        __syncthreads();
       }
-      __syncthreads();
-      for (long x = threadIdx.x; x < nov; x += 256) {
-        double t = w[x];
-        for (int s = 0; s < nb; ++s) t -= h[s] * V[s * nov + x];
-        w[x] = t;
-      }
-      __syncthreads();
-    }
     double nw = 0.0;
     for (long x = threadIdx.x; x < nov; x += 256) nw += w[x] * w[x];
     nw = sqrt(block_sum(nw, red));
-    if (nw > 1e-8 * n0 && nw > 1e-14) {
-      double* dst = V + static_cast<long>(nb) * nov;
+    if (nw > 1e-8 * n0p[m * K + u] && nw > 1e-14) {
+      double* dst = V + static_cast<long>(S0 + acc) * nov;
       const double inv = 1.0 / nw;
       for (long x = threadIdx.x; x < nov; x += 256) dst[x] = w[x] * inv;
       ++acc;
@@ -773,6 +730,7 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
   w.eval.ensure(static_cast<size_t>(nmol) * Smax);
   w.omega.ensure(static_cast<size_t>(nmol) * K);
   w.rnorm.ensure(static_cast<size_t>(nmol) * K);
+  w.n0.ensure(static_cast<size_t>(nmol) * K);
   if (f32) w.scratch32.ensure(static_cast<size_t>(G) * scr_stride);
   else w.scratch64.ensure(static_cast<size_t>(G) * scr_stride);
 
@@ -866,8 +824,10 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
                          w.active.p, w.items.p, w.counters.p, w.nsig.p);
       launch_sigma();
       if (timed) hipLaunchKernelGGL(stamp_span_kernel, dim3(1), dim3(256), 0, st, G, w.stamps.p, w.nsig.p + 1);
-      hipLaunchKernelGGL(project_kernel, dim3(nmol), dim3(256), 0, st, w.mols.p, Smax, w.V.p, w.AV.p, w.Mp.p, w.S.p,
-                         w.knew.p, w.active.p);
+      hipLaunchKernelGGL(project_kernel, dim3(nmol, maxnew), dim3(256), 0, st, w.mols.p, Smax, w.V.p, w.AV.p, w.Mp.p,
+                         w.S.p, w.knew.p, w.active.p);
+      hipLaunchKernelGGL(advance_kernel, dim3(ceil_div(nmol, 256)), dim3(256), 0, st, nmol, w.S.p, w.knew.p,
+                         w.active.p);
       hipLaunchKernelGGL(eig_kernel, dim3(nmol), dim3(256), 0, st, Smax, w.Mp.p, w.S.p, w.active.p, w.evec.p,
                          w.eval.p);
       hipLaunchKernelGGL(ritz_kernel, dim3(nmol, K), dim3(256), 0, st, w.mols.p, K, Smax, opt.tol, w.V.p, w.AV.p,
@@ -878,8 +838,10 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
                          w.S.p, w.coll.p, w.qcol.p, w.TV.p, w.TAV.p);
       hipLaunchKernelGGL(collapse_copy_kernel, dim3(nmol, Q + 1), dim3(256), 0, st, w.mols.p, Smax, w.TV.p, w.TAV.p,
                          w.eval.p, w.S.p, w.coll.p, w.qcol.p, w.V.p, w.AV.p, w.Mp.p);
-      hipLaunchKernelGGL(ortho_kernel, dim3(nmol), dim3(256), 0, st, w.mols.p, K, Smax, w.V.p, w.Wc.p, w.S.p,
-                         w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.conv.p, w.counters.p);
+      hipLaunchKernelGGL(deflate_kernel, dim3(nmol, K), dim3(256), 0, st, w.mols.p, K, w.V.p, w.Wc.p, w.S.p,
+                         w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.n0.p);
+      hipLaunchKernelGGL(append_kernel, dim3(nmol), dim3(256), 0, st, w.mols.p, K, Smax, w.V.p, w.Wc.p, w.S.p,
+                         w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.conv.p, w.counters.p, w.n0.p);
       SEQX_LAUNCH_CHECK();
     };
     if (opt.graph) {

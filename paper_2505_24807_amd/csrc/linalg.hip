@@ -1,6 +1,7 @@
 // Small device kernels and the rocSOLVER wrapper.
 #include <rocsolver/rocsolver.h>
 
+#include "jacobi.hpp"
 #include "linalg.hpp"
 
 namespace seqx {
@@ -22,7 +23,32 @@ DenseSolver::~DenseSolver() {
   if (h_) rocblas_destroy_handle(h_);
 }
 
+namespace {
+// n <= kJacobiMax: one workgroup, Jacobi in LDS on the lower triangle (no failure mode; info = 0)
+__global__ void __launch_bounds__(256) small_eigh_kernel(int n, double* A, int lda, double* w, int* info) {
+  __shared__ JacobiLds L;
+  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+    const int i = idx / n, j = idx % n;
+    L.A[i][j] = i >= j ? A[i + static_cast<long>(j) * lda] : A[j + static_cast<long>(i) * lda];  // lower triangle
+  }
+  __syncthreads();
+  jacobi_lds(n, L);
+  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+    const int r = idx / n, i = idx % n;
+    A[i + static_cast<long>(r) * lda] = L.Q[i][L.perm[r]];
+  }
+  for (int r = threadIdx.x; r < n; r += 256) w[r] = L.A[L.perm[r]][L.perm[r]];
+  if (threadIdx.x == 0) info[0] = 0;
+}
+}  // namespace
+
 void DenseSolver::eigh(int n, double* A, int lda, double* w) {
+  if (n <= 0) return;
+  if (n <= kJacobiMax) {
+    hipLaunchKernelGGL(small_eigh_kernel, dim3(1), dim3(256), 0, st_, n, A, lda, w, info_.p);
+    SEQX_LAUNCH_CHECK();
+    return;
+  }
   work_.ensure(static_cast<size_t>(n));
   SEQX_RB(rocsolver_dsyevd(h_, rocblas_evect_original, rocblas_fill_lower, n, A, lda, w, work_.p, info_.p));
 }
