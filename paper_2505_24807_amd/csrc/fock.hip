@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(128) exchange_pair_kernel(int npairs, const in
 }
 
 template <int MODE, class TR, class TF>
-__global__ void diag_block_kernel(int natoms, int k, const int* __restrict__ slot, const int* __restrict__ ao_off,
+__global__ void diag_block_kernel(int natoms, int np, const int* __restrict__ slot, const int* __restrict__ ao_off,
                                   const int* __restrict__ pi_off, const Elem* __restrict__ elems,
                                   const double* __restrict__ J, const TR* __restrict__ R, long sR, int n,
                                   TF* __restrict__ F1, TF* __restrict__ F2, long sF, double cJ, double cK,
@@ -51,7 +51,8 @@ __global__ void diag_block_kernel(int natoms, int k, const int* __restrict__ slo
   const int I = blockIdx.y;
   if (A >= natoms) return;
   const Elem e = elems[slot[A]];
-  diag_block<MODE, TR, TF>(e, ao_off[A], pi_off[A], J + I, k, R + I * sR, n, F1 + I * sF,
+  // J is stored [k][np]: vector I's Coulomb values are contiguous
+  diag_block<MODE, TR, TF>(e, ao_off[A], pi_off[A], J + static_cast<long>(I) * np, 1, R + I * sR, n, F1 + I * sF,
                            MODE == kTwo ? F2 + I * sF : nullptr, cJ, cK, cKa);
 }
 
@@ -82,19 +83,22 @@ void build_G_any(const DeviceMolecule& m, int k, const TR* R, long sR, TF* F1, T
   hipLaunchKernelGGL(pack_kernel<TR>, dim3(ceil_div(np, 256), k), dim3(256), 0, st, k, np, n, m.pi_mu.p, m.pi_nu.p, R,
                      sR, w.r.p);
   SEQX_LAUNCH_CHECK();
-  // J[np][k] = W (np x np) * r^T ; r stored [k][np]; FP64 whatever the storage type of R and F
-  dgemm(st, false, true, np, k, np, 1.0, m.W.p, np, 0, w.r.p, np, 0, 0.0, w.J.p, k, 0, 1, nullptr);
+  // J[k][np] = r (k x np) * W (W symmetric): split-K inner products, so that a
+  // handful of vectors still spreads over hundreds of workgroups; FP64 whatever
+  // the storage type of R and F
+  w.ws.ensure(dots_workspace(k, np, np));
+  dots(st, k, w.r.p, np, np, m.W.p, np, np, w.J.p, np, w.ws.p);
   const dim3 dgrid(ceil_div(m.natoms, 64), k);
   if (mode == kTwo) {
-    hipLaunchKernelGGL((diag_block_kernel<kTwo, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p,
+    hipLaunchKernelGGL((diag_block_kernel<kTwo, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, np, m.slot.p, m.ao_off.p,
                        m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
     launch_pairs<kTwo>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
   } else if (mode == kSum) {
-    hipLaunchKernelGGL((diag_block_kernel<kSum, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p,
+    hipLaunchKernelGGL((diag_block_kernel<kSum, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, np, m.slot.p, m.ao_off.p,
                        m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
     launch_pairs<kSum>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
   } else {
-    hipLaunchKernelGGL((diag_block_kernel<kSymm, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, k, m.slot.p, m.ao_off.p,
+    hipLaunchKernelGGL((diag_block_kernel<kSymm, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, np, m.slot.p, m.ao_off.p,
                        m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
     launch_pairs<kSymm>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
   }

@@ -17,7 +17,7 @@ namespace seqx {
 // and the two-centre term on every off-diagonal block.
 
 struct GWork {
-  DBuf<double> r, J;  // packed densities [k][np] and Coulomb [np][k]
+  DBuf<double> r, J, ws;  // packed densities [k][np], Coulomb [k][np], split-K partial sums
 };
 
 void build_G(const DeviceMolecule& m, int k, const double* R, long sR, double* F1, double* F2, long sF, GMode mode,

@@ -268,7 +268,14 @@ __global__ void __launch_bounds__(256) gemm128_kernel(int M, int N, int K, doubl
   __shared__ T As[2 * BK][kBM + kPad];
   __shared__ T Bs[2 * BK][kBN + kPad];
   const long b = blockIdx.z;
-  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+  // Workgroups go to the 8 XCDs round-robin by linear id, and each XCD has its
+  // own L2.  Regroup the ids so that each XCD gets a contiguous run of tiles in
+  // row-major order: the column tiles of one row panel of A then share an L2
+  // (the ids past the largest multiple of 8 keep their place).
+  const int nbx = gridDim.x, nb = gridDim.x * gridDim.y, nfull = nb - nb % 8;
+  int bid = blockIdx.y * nbx + blockIdx.x;
+  if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
+  const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * kBN;
   if (m0 + kBM <= M && n0 + kBN <= N)
     tile128<T, To, TA, TB, EPI, false>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
                                        m0, n0, As, Bs);
@@ -356,6 +363,24 @@ __global__ void reduce_partials_kernel(int nchunks, int ns, int nt, const double
   out[static_cast<long>(s) * ldo + t] = acc;
 }
 
+// few outputs, many chunks: one workgroup per output, fixed-order tree
+__global__ void __launch_bounds__(256) reduce_partials_wide_kernel(int nchunks, int ns, int nt,
+                                                                   const double* __restrict__ part, double* out,
+                                                                   long ldo) {
+  __shared__ double red[256];
+  const int idx = blockIdx.x;
+  const long stride = static_cast<long>(ns) * nt;
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < nchunks; c += 256) acc += part[c * stride + idx];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[static_cast<long>(idx / nt) * ldo + idx % nt] = red[0];
+}
+
 // split-K chunk of the inner products: short enough that a basis of a few
 // hundred vectors still spreads over thousands of workgroups
 constexpr long kDotChunk = 1024;
@@ -404,8 +429,11 @@ void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const doubl
     dgemm(st, false, true, ns, nt, static_cast<int>(len - off), 1.0, X + off, ldx, 0, Y + off, ldy, 0, 0.0,
           ws + static_cast<long>(full) * ns * nt, nt, 0, 1, nullptr);
   }
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 256)), dim3(256), 0, st, nchunks, ns, nt, ws, out,
-                     ldo);
+  if (ns * nt < 1024 && nchunks >= 64)
+    hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
+  else
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 256)), dim3(256), 0, st, nchunks, ns, nt, ws,
+                       out, ldo);
   SEQX_LAUNCH_CHECK();
 }
 
