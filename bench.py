@@ -145,6 +145,24 @@ def summary(r, K):
     }
 
 
+def _traffic(kernel_tag, flops_per_launch):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel),
+    scaled from its k = 32 launch to this run's average launch by flops; None
+    when the GEMM source has changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, "profiles", "water330_sigma_counters.md")).read()
+        src = open(os.path.join(ROOT, "paper_2505_24807_amd", "csrc", "gemm.hip"), "rb").read()
+    except OSError:
+        return None
+    m = re.search(r"TRAFFIC (\S+) k32_bytes=(\S+) flops_k32=(\S+) gemm_src_sha1=(\w+)", text)
+    if not m or m.group(1) != kernel_tag or hashlib.sha1(src).hexdigest()[:12] != m.group(4):
+        return None
+    return float(m.group(2)) * flops_per_launch / float(m.group(3))
+
+
 def roofline_of(r, dtype):
     """Dominant sigma-build kernel: the transform phase with the most device time (HIP events per launch)."""
     from paper_2505_24807_amd import seqx
@@ -154,8 +172,10 @@ def roofline_of(r, dtype):
     avg_s = ms * 1e-3 / launches
     achieved = flops / launches / avg_s / 1e12
     ctype = "double" if dtype == "fp64" else "float"
+    traffic = _traffic("gemm128_kernel<float>:G_C_virt", flops / launches) if (dtype == "fp32" and p == 3) else None
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[dtype], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[dtype], 4), "traffic": None,
+            "frac": round(achieved / PEAK[dtype], 4),
+            "traffic": round(traffic / 1e9, 3) if traffic else None, "traffic_unit": "GB per launch",
             "kernel": f"gemm128_kernel<{ctype}> ({seqx.Stats.PHASES[p]})",
             "flops_per_launch": flops / launches, "avg_launch_ms": ms / launches}
 
