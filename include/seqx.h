@@ -70,7 +70,16 @@ typedef enum { SEQX_CIS = 0, SEQX_TDHF = 1 } seqx_theory;
  * accuracy.  SEQX_BF16 and SEQX_BF16X3 are reserved and return SEQX_E_ARG. */
 typedef enum { SEQX_FP64 = 0, SEQX_FP32 = 1, SEQX_BF16 = 2, SEQX_BF16X3 = 3 } seqx_precision;
 
-typedef enum { SEQX_GUESS_GAP = 0, SEQX_GUESS_LEARNED = 1, SEQX_GUESS_USER = 2 } seqx_guess;
+/* Starting space of the Davidson iteration:
+ *   GAP         unit vectors at the min(nocc*nvirt, 2K) smallest orbital-energy gaps;
+ *   LEARNED     unit vectors at the M pairs the context's network scores highest
+ *               (P-space guess; M = seqx_solve_opts.pspace, default 4K);
+ *   USER        the caller's vectors (molecule 0);
+ *   GAP_PSPACE  unit vectors at the M smallest gaps (the same construction as
+ *               LEARNED with the gap as the score: the baseline it is compared to).
+ * Ties are broken by the flat pair index i*nvirt + a.  The converged roots do
+ * not depend on the guess; the iteration count does. */
+typedef enum { SEQX_GUESS_GAP = 0, SEQX_GUESS_LEARNED = 1, SEQX_GUESS_USER = 2, SEQX_GUESS_GAP_PSPACE = 3 } seqx_guess;
 
 /* Parameter order of one row of seqx_set_params (eV, exponents in 1/bohr):
  *   zeta_s, zeta_p, U_ss, U_pp, beta_s, beta_p, g_ss, g_sp, g_pp, g_p2, h_sp
@@ -101,6 +110,7 @@ typedef struct {
                            persistent launch and replays one captured HIP graph.  The
                            subspace cap is min(max_subspace or 8 * nroots, 48) per molecule.
                            Molecules need at most 1536 same-atom AO pairs. */
+  int32_t pspace;       /* LEARNED / GAP_PSPACE guesses: number of pairs M; <= 0 selects 4 * nroots */
 } seqx_solve_opts;
 
 typedef struct {
@@ -219,6 +229,56 @@ seqx_status seqx_get_stats(const seqx_job* job, seqx_stats* out);
  * omega_eV may be NULL to query it). */
 seqx_status seqx_history(const seqx_job* job, int32_t mol, int32_t cap, int32_t* n_iter, double* t_s,
                          double* omega_eV);
+
+/* ---- Learned starting space -------------------------------------------------
+ * Per pair i -> a, 12 features (hartree, bohr): gap, eps_HOMO - eps_i,
+ * eps_a - eps_LUMO, sum_A q_A^2, the four largest |q_A| (q_A: transition
+ * Mulliken charge on atom A), sum_A g_A q_A^2, sum_A g_A p_A^i p_A^a (p: orbital
+ * populations, g_A = (s_A s_A|s_A s_A)), the distance of the two orbital
+ * centroids, and gap + 2 f8 - f9.  Network: standardise with (mu, sd), then
+ * 12 -> 128 -> 128 -> 1 with SiLU; weight matrices used as bfloat16 values,
+ * activations and sums in FP32.  Training target of a molecule with K solved
+ * CIS roots: w_ia = (1/K) sum_n X[n][i][a]^2; loss: mean over molecules of the
+ * softmax cross-entropy of the scores against w; optimiser: Adam. */
+#define SEQX_MLP_NFEAT 12
+#define SEQX_MLP_WIDTH 128
+/* flat FP32 parameters: W1[12][128], b1[128], W2[128][128], b2[128], w3[128], b3 */
+#define SEQX_MLP_NWEIGHTS 18305
+/* ... then the feature means mu[12] and scales sd[12] */
+#define SEQX_MLP_NPARAMS 18329
+
+typedef struct {
+  int32_t epochs;   /* passes over the training molecules; <= 0 selects 30 */
+  int32_t batch;    /* molecules per optimiser step; <= 0 selects 32 */
+  double lr;        /* Adam step size; <= 0 selects 2e-3 */
+  uint64_t seed;    /* initial weights and molecule order */
+  int32_t init;     /* nonzero: fresh weights and feature standardisation from the training set */
+} seqx_train_opts;
+
+typedef struct {
+  int32_t n_epochs;
+  double seconds;     /* wall time of the training (features, targets, epochs) */
+  double loss[256];   /* mean training loss of each epoch (first 256) */
+} seqx_train_log;
+
+/* Network parameters of the context (SEQX_MLP_NPARAMS floats, layout above). */
+seqx_status seqx_mlp_set_params(seqx_ctx* ctx, const float* params, size_t n);
+seqx_status seqx_mlp_get_params(const seqx_ctx* ctx, float* out, size_t cap, size_t* needed);
+/* Binary file: 8-byte tag "SEQXMLP1", int32 count, then the FP32 parameters. */
+seqx_status seqx_mlp_save(const seqx_ctx* ctx, const char* path);
+seqx_status seqx_mlp_load(seqx_ctx* ctx, const char* path);
+/* Train the context's network on the job's molecules, which must hold solved
+ * CIS roots (seqx_solve with theory CIS); their amplitudes are the targets. */
+seqx_status seqx_mlp_train(seqx_job* job, const seqx_train_opts* opts, seqx_train_log* log);
+/* Features of molecule `mol` (host out [nocc*nvirt][12], cap in floats). */
+seqx_status seqx_features(const seqx_job* job, int32_t mol, float* out, size_t cap);
+/* Network scores of every pair of molecule `mol` (host z [nocc*nvirt]). */
+seqx_status seqx_mlp_scores(const seqx_job* job, int32_t mol, float* z, size_t cap);
+/* Loss and weight gradient (host grad[SEQX_MLP_NWEIGHTS]) of the context's
+ * network on host features [npairs][12] and targets w[npairs], molecules given
+ * by nmol + 1 pair offsets seg (seg[0] = 0, seg[nmol] = npairs). */
+seqx_status seqx_mlp_loss_grad(seqx_ctx* ctx, int64_t npairs, const float* feats, const float* w, int32_t nmol,
+                               const int64_t* seg, double* loss, float* grad);
 
 #ifdef __cplusplus
 }

@@ -2,6 +2,8 @@
 // host validation, argument marshalling and the error model.  No exception
 // crosses the boundary; every entry point returns a status code.
 #include <chrono>
+#include <cstdio>
+#include <cstring>
 #include <cmath>
 #include <memory>
 #include <string>
@@ -12,6 +14,7 @@
 #include "davidson.hpp"
 #include "integrals.hpp"
 #include "linalg.hpp"
+#include "mlp.hpp"
 #include "model.hpp"
 #include "molecule.hpp"
 #include "scf.hpp"
@@ -28,6 +31,8 @@ struct seqx_ctx {
   DBuf<Elem> d_elems;
   std::unique_ptr<DenseSolver> ds;
   TileTuning tune;
+  Mlp mlp;
+  MlpWork mw;
 };
 
 struct seqx_job {
@@ -37,6 +42,7 @@ struct seqx_job {
   ScfWork sw;
   DavWork dw;
   BatchWork bw;
+  DBuf<double> guess_v;
   seqx_stats stats{};
   bool solved = false;
 };
@@ -398,7 +404,9 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
   return guarded(job->ctx, [&] {
     if (opts->theory != SEQX_CIS && opts->theory != SEQX_TDHF) throw Error(kEArg, "theory must be CIS or TDHF");
     check_precision(opts->precision);
-    if (opts->guess == SEQX_GUESS_LEARNED) throw Error(kEArg, "learned guess needs a loaded network");
+    if (opts->guess < SEQX_GUESS_GAP || opts->guess > SEQX_GUESS_GAP_PSPACE) throw Error(kEArg, "unknown guess");
+    if (opts->guess == SEQX_GUESS_LEARNED && !job->ctx->mlp.ready)
+      throw Error(kEState, "learned guess needs network parameters (seqx_mlp_load, _set_params or _train)");
     hipStream_t st = job->ctx->stream;
     DavOptions d;
     d.theory = opts->theory;
@@ -456,7 +464,13 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
       DeviceMolecule& m = scf_mol_of(job, static_cast<int32_t>(mi));
       const long nov = static_cast<long>(m.nocc) * m.nvirt;
       if (opts->nroots < 1 || opts->nroots > nov) throw Error(kEArg, "nroots must be in [1, nocc*nvirt]");
-      if (opts->guess == SEQX_GUESS_USER && mi == 0) {
+      if (opts->guess == SEQX_GUESS_LEARNED || opts->guess == SEQX_GUESS_GAP_PSPACE) {
+        const int M = static_cast<int>(std::min<long>(nov, opts->pspace > 0 ? opts->pspace : 4L * opts->nroots));
+        job->guess_v.ensure(static_cast<size_t>(M) * nov);
+        pspace_guess(&job->ctx->mlp, m, M, opts->guess == SEQX_GUESS_LEARNED, job->guess_v.p, job->ctx->mw, st);
+        d.guess = job->guess_v.p;
+        d.nguess = M;
+      } else if (opts->guess == SEQX_GUESS_USER && mi == 0) {
         if (!opts->user_guess || opts->n_user_guess < 1) throw Error(kEArg, "user guess missing");
         guess.alloc(static_cast<size_t>(opts->n_user_guess) * nov);
         SEQX_HIP(hipMemcpyAsync(guess.p, opts->user_guess, guess.n * sizeof(double), hipMemcpyHostToDevice, st));
@@ -556,3 +570,126 @@ seqx_status seqx_get_stats(const seqx_job* job, seqx_stats* out) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- learned starting space
+
+seqx_status seqx_mlp_set_params(seqx_ctx* ctx, const float* params, size_t n) {
+  if (!ctx) return SEQX_E_ARG;
+  return guarded(ctx, [&] {
+    if (!params || n != static_cast<size_t>(kNumParams)) throw Error(kEArg, "expected SEQX_MLP_NPARAMS floats");
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(params[i])) throw Error(kEArg, "non-finite network parameter");
+    for (int f = 0; f < kNumFeatures; ++f)
+      if (!(params[kOffSd + f] > 0.0f)) throw Error(kEArg, "feature scales must be positive");
+    ctx->mlp.set(params, ctx->stream);
+  });
+}
+
+seqx_status seqx_mlp_get_params(const seqx_ctx* ctx, float* out, size_t cap, size_t* needed) {
+  if (!ctx) return SEQX_E_ARG;
+  seqx_ctx* c = const_cast<seqx_ctx*>(ctx);
+  return guarded(c, [&] {
+    if (needed) *needed = kNumParams;
+    if (!out) return;
+    if (cap < static_cast<size_t>(kNumParams)) throw Error(kEBufSize, "parameter buffer too small");
+    c->mlp.get(out, c->stream);
+  });
+}
+
+seqx_status seqx_mlp_save(const seqx_ctx* ctx, const char* path) {
+  if (!ctx || !path) return SEQX_E_ARG;
+  seqx_ctx* c = const_cast<seqx_ctx*>(ctx);
+  return guarded(c, [&] {
+    std::vector<float> p(kNumParams);
+    c->mlp.get(p.data(), c->stream);
+    FILE* f = std::fopen(path, "wb");
+    if (!f) throw Error(kEArg, std::string("cannot write ") + path);
+    const int32_t cnt = kNumParams;
+    const bool ok = std::fwrite("SEQXMLP1", 1, 8, f) == 8 && std::fwrite(&cnt, sizeof(cnt), 1, f) == 1 &&
+                    std::fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+    std::fclose(f);
+    if (!ok) throw Error(kEArg, std::string("write failed: ") + path);
+  });
+}
+
+seqx_status seqx_mlp_load(seqx_ctx* ctx, const char* path) {
+  if (!ctx || !path) return SEQX_E_ARG;
+  return guarded(ctx, [&] {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) throw Error(kEArg, std::string("cannot read ") + path);
+    char tag[8] = {};
+    int32_t cnt = 0;
+    std::vector<float> p(kNumParams);
+    const bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, "SEQXMLP1", 8) == 0 &&
+                    std::fread(&cnt, sizeof(cnt), 1, f) == 1 && cnt == kNumParams &&
+                    std::fread(p.data(), sizeof(float), p.size(), f) == p.size();
+    std::fclose(f);
+    if (!ok) throw Error(kEArg, std::string("not a network parameter file: ") + path);
+    ctx->mlp.set(p.data(), ctx->stream);
+  });
+}
+
+seqx_status seqx_mlp_train(seqx_job* job, const seqx_train_opts* opts, seqx_train_log* log) {
+  if (!job || !opts) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    std::vector<DeviceMolecule*> ms;
+    for (size_t mi = 0; mi < job->mols.size(); ++mi) ms.push_back(&scf_mol_of(job, static_cast<int32_t>(mi)));
+    TrainOptions t;
+    t.epochs = opts->epochs > 0 ? opts->epochs : 30;
+    t.batch = opts->batch > 0 ? opts->batch : 32;
+    t.lr = opts->lr > 0 ? opts->lr : 2e-3;
+    t.seed = opts->seed;
+    t.init = opts->init != 0;
+    TrainLog tl;
+    mlp_train(job->ctx->mlp, ms, t, tl, job->ctx->mw, job->ctx->stream);
+    if (log) {
+      log->n_epochs = static_cast<int32_t>(tl.loss.size());
+      log->seconds = tl.seconds;
+      for (size_t e = 0; e < tl.loss.size() && e < 256; ++e) log->loss[e] = tl.loss[e];
+    }
+  });
+}
+
+seqx_status seqx_features(const seqx_job* job, int32_t mol, float* out, size_t cap) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = scf_mol_of(job, mol);
+    const size_t n = static_cast<size_t>(m.nocc) * m.nvirt * kNumFeatures;
+    if (!out || cap < n) throw Error(kEBufSize, "feature buffer too small");
+    DBuf<float> d(n);
+    mlp_features(m, d.p, job->ctx->mw, job->ctx->stream);
+    d2h(out, d.p, n, job->ctx->stream);
+    SEQX_HIP(hipStreamSynchronize(job->ctx->stream));
+  });
+}
+
+seqx_status seqx_mlp_scores(const seqx_job* job, int32_t mol, float* z, size_t cap) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = scf_mol_of(job, mol);
+    const long nov = static_cast<long>(m.nocc) * m.nvirt;
+    if (!z || cap < static_cast<size_t>(nov)) throw Error(kEBufSize, "score buffer too small");
+    DBuf<float> fe(static_cast<size_t>(nov) * kNumFeatures), dz(nov);
+    mlp_features(m, fe.p, job->ctx->mw, job->ctx->stream);
+    mlp_scores(job->ctx->mlp, nov, fe.p, dz.p, job->ctx->stream);
+    d2h(z, dz.p, nov, job->ctx->stream);
+    SEQX_HIP(hipStreamSynchronize(job->ctx->stream));
+  });
+}
+
+seqx_status seqx_mlp_loss_grad(seqx_ctx* ctx, int64_t npairs, const float* feats, const float* w, int32_t nmol,
+                               const int64_t* seg, double* loss, float* grad) {
+  if (!ctx) return SEQX_E_ARG;
+  return guarded(ctx, [&] {
+    if (npairs < 1 || !feats || !w || nmol < 1 || !seg || !grad) throw Error(kEArg, "bad loss arguments");
+    hipStream_t st = ctx->stream;
+    DBuf<float> df(static_cast<size_t>(npairs) * kNumFeatures), dw(npairs), dg(kNumWeights);
+    SEQX_HIP(hipMemcpyAsync(df.p, feats, df.n * sizeof(float), hipMemcpyHostToDevice, st));
+    SEQX_HIP(hipMemcpyAsync(dw.p, w, dw.n * sizeof(float), hipMemcpyHostToDevice, st));
+    std::vector<long> sg(seg, seg + nmol + 1);
+    const double L = mlp_loss_grad(ctx->mlp, npairs, df.p, dw.p, nmol, sg.data(), dg.p, ctx->mw, st);
+    d2h(grad, dg.p, kNumWeights, st);
+    SEQX_HIP(hipStreamSynchronize(st));
+    if (loss) *loss = L;
+  });
+}

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libseqx.so")
 
 CIS, TDHF = 0, 1
 FP64, FP32, BF16, BF16X3 = 0, 1, 2, 3
-GUESS_GAP, GUESS_LEARNED, GUESS_USER = 0, 1, 2
+GUESS_GAP, GUESS_LEARNED, GUESS_USER, GUESS_GAP_PSPACE = 0, 1, 2, 3
+MLP_NFEAT, MLP_NWEIGHTS, MLP_NPARAMS = 12, 18305, 18329
 NPARAM = 11
 HARTREE_EV = 27.211386245988
 
@@ -41,7 +42,16 @@ class SolveOpts(C.Structure):
     _fields_ = [("theory", C.c_int32), ("nroots", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("max_subspace", C.c_int32), ("mem_budget_bytes", C.c_size_t), ("precision", C.c_int32),
                 ("guess", C.c_int32), ("n_user_guess", C.c_int32), ("user_guess", C.POINTER(C.c_double)),
-                ("batched", C.c_int32)]
+                ("batched", C.c_int32), ("pspace", C.c_int32)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("seed", C.c_uint64),
+                ("init", C.c_int32)]
+
+
+class TrainLog(C.Structure):
+    _fields_ = [("n_epochs", C.c_int32), ("seconds", C.c_double), ("loss", C.c_double * 256)]
 
 
 class Stats(C.Structure):
@@ -61,6 +71,7 @@ class Stats(C.Structure):
 _lib = None
 
 _D = C.POINTER(C.c_double)
+_F = C.POINTER(C.c_float)
 _I = C.POINTER(C.c_int32)
 
 
@@ -92,6 +103,15 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "seqx_results": (C.c_int, [C.c_void_p, C.c_int32, _D, _D, _D, _D, _D]),
         "seqx_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
         "seqx_history": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _I, _D, _D]),
+        "seqx_mlp_set_params": (C.c_int, [C.c_void_p, _F, C.c_size_t]),
+        "seqx_mlp_get_params": (C.c_int, [C.c_void_p, _F, C.c_size_t, C.POINTER(C.c_size_t)]),
+        "seqx_mlp_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+        "seqx_mlp_load": (C.c_int, [C.c_void_p, C.c_char_p]),
+        "seqx_mlp_train": (C.c_int, [C.c_void_p, C.POINTER(TrainOpts), C.POINTER(TrainLog)]),
+        "seqx_features": (C.c_int, [C.c_void_p, C.c_int32, _F, C.c_size_t]),
+        "seqx_mlp_scores": (C.c_int, [C.c_void_p, C.c_int32, _F, C.c_size_t]),
+        "seqx_mlp_loss_grad": (C.c_int, [C.c_void_p, C.c_int64, _F, _F, C.c_int32, C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_double), _F]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -103,6 +123,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
 
 def _dptr(a):
     return None if a is None else a.ctypes.data_as(_D)
+
+
+def _fptr(a):
+    return None if a is None else a.ctypes.data_as(_F)
 
 
 def _iptr(a):
@@ -158,6 +182,31 @@ class Context:
         self._check(self.lib.seqx_prepare(self.h, len(natoms), _iptr(natoms), _iptr(Z), _dptr(xyz), C.byref(o),
                                           C.byref(h)))
         return Job(self, h, len(natoms))
+
+    def mlp_set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(self.lib.seqx_mlp_set_params(self.h, _fptr(p), p.size))
+
+    def mlp_get_params(self):
+        p = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        self._check(self.lib.seqx_mlp_get_params(self.h, _fptr(p), p.size, None))
+        return p
+
+    def mlp_save(self, path):
+        self._check(self.lib.seqx_mlp_save(self.h, os.fsencode(path)))
+
+    def mlp_load(self, path):
+        self._check(self.lib.seqx_mlp_load(self.h, os.fsencode(path)))
+
+    def mlp_loss_grad(self, feats, w, seg):
+        feats = np.ascontiguousarray(feats, dtype=np.float32)
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        seg = np.ascontiguousarray(seg, dtype=np.int64)
+        loss = C.c_double()
+        g = np.zeros(MLP_NWEIGHTS, dtype=np.float32)
+        self._check(self.lib.seqx_mlp_loss_grad(self.h, w.size, _fptr(feats), _fptr(w), len(seg) - 1,
+                                                seg.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(loss), _fptr(g)))
+        return loss.value, g
 
     def close(self):
         if getattr(self, "h", None):
@@ -221,15 +270,33 @@ class Job:
                                                C.c_void_p(out2.data_ptr()) if out2 is not None else None,
                                                precision))
 
+    def features(self, mol=0):
+        _, o, v = self.dims(mol)
+        f = np.zeros((o * v, MLP_NFEAT), dtype=np.float32)
+        self._check(self.lib.seqx_features(self.h, mol, _fptr(f), f.size))
+        return f
+
+    def mlp_scores(self, mol=0):
+        _, o, v = self.dims(mol)
+        z = np.zeros(o * v, dtype=np.float32)
+        self._check(self.lib.seqx_mlp_scores(self.h, mol, _fptr(z), z.size))
+        return z
+
+    def mlp_train(self, epochs=30, batch=32, lr=2e-3, seed=2505, init=True):
+        o = TrainOpts(epochs, batch, lr, seed, 1 if init else 0)
+        log = TrainLog()
+        self._check(self.lib.seqx_mlp_train(self.h, C.byref(o), C.byref(log)))
+        return {"loss": list(log.loss[:min(log.n_epochs, 256)]), "seconds": log.seconds}
+
     def solve(self, theory=TDHF, nroots=3, tol=1e-6, max_iter=100, max_subspace=0, mem_budget_bytes=0,
-              precision=FP64, guess=GUESS_GAP, user_guess=None, batched=False):
+              precision=FP64, guess=GUESS_GAP, user_guess=None, batched=False, pspace=0):
         ug = None
         n_ug = 0
         if user_guess is not None:
             ug = np.ascontiguousarray(user_guess, dtype=np.float64)
             n_ug = ug.shape[0]
         o = SolveOpts(theory, nroots, tol, max_iter, max_subspace, mem_budget_bytes, precision, guess, n_ug,
-                      _dptr(ug) if ug is not None else None, 1 if batched else 0)
+                      _dptr(ug) if ug is not None else None, 1 if batched else 0, pspace)
         self.nroots = 0
         self._check(self.lib.seqx_solve(self.h, C.byref(o)))
         self.nroots = nroots
