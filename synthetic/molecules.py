@@ -228,6 +228,30 @@ def workload_batch(nmol: int = 512, seed: int = 512):
     return mols
 
 
+def guess_training_molecule(seed: int) -> Molecule:
+    """Training molecule of the learned guess (seeds 0-1999): a polyene
+    C_nH_(n+2) with n even in 4..38 or a water cluster (H2O)_m with m in 4..26,
+    chosen with equal odds; 0.02 Angstrom coordinate noise on the polyenes."""
+    rng = np.random.default_rng(seed)
+    if rng.integers(2) == 0:
+        n = int(rng.choice(np.arange(4, 39, 2)))
+        return add_noise(polyene(n), 0.02, rng)
+    m = int(rng.integers(4, 27))
+    return water_cluster(m, int(rng.integers(1 << 30)))
+
+
+def guess_eval_molecule(seed: int) -> Molecule:
+    """Held-out evaluation molecule of the learned guess (seeds from 100000):
+    a polyene with n even in 100..298 or (H2O)_m with m in 67..200 (200-600
+    atoms), equal odds; 0.02 Angstrom noise on the polyenes."""
+    rng = np.random.default_rng(seed)
+    if rng.integers(2) == 0:
+        n = int(rng.choice(np.arange(100, 299, 2)))
+        return add_noise(polyene(n), 0.02, rng)
+    m = int(rng.integers(67, 201))
+    return water_cluster(m, int(rng.integers(1 << 30)))
+
+
 def concat(mols):
     """Concatenate molecules into (natoms[], Z[], xyz[]) arrays."""
     natoms = np.array([m.natoms for m in mols], dtype=np.int32)
