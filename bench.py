@@ -13,7 +13,8 @@ step; time-to-roots alongside), the roofline of the dominant sigma-build kernel
 bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--precision fp32|fp64]
-                    [--no-fp64-comparison] [--no-batched] [--no-batched-loop] [--no-cpu-baseline]
+                    [--no-fp64-comparison] [--no-batched] [--no-batched-loop] [--no-learned]
+                    [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -79,14 +80,16 @@ def cpu_baseline(mol, params_eV, k=2):
                       f"{dt:.1f} s; ERI build excluded"}
 
 
-def run_mode(ctx, mol, ref, precision, steps, warmup):
-    """Warm up, then time `steps` whole steps (integrals + SCF + Davidson) in one transform precision."""
+def run_mode(ctx, mol, ref, precision, steps, warmup, guess=0, pspace=0):
+    """Warm up, then time `steps` whole steps (integrals + SCF + Davidson) in one
+    transform precision and starting space."""
     import torch
     from paper_2505_24807_amd import seqx
 
     def step():
         job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
-        job.solve(theory=seqx.TDHF, nroots=NROOTS, tol=TOL, max_iter=400, precision=precision)
+        job.solve(theory=seqx.TDHF, nroots=NROOTS, tol=TOL, max_iter=400, precision=precision, guess=guess,
+                  pspace=pspace)
         return job
 
     for _ in range(warmup):
@@ -251,6 +254,26 @@ def sigma_only(ctx, mol, k, reps, precision):
             "sigma_vectors_per_s": round(k * reps / dt, 1), "seconds": round(dt, 4)}
 
 
+def learned_c5(ctx, nmol=3):
+    """Held-out molecules of the learned-guess evaluation (200-600 atoms), CIS,
+    10 roots, FP64: the network shipped in the package against the gap guess."""
+    from paper_2505_24807_amd import seqx
+    from paper_2505_24807_amd.train_guess import evaluate
+    ctx.mlp_load(os.path.join(ROOT, "paper_2505_24807_amd", "guess_net.bin"))
+    rows = evaluate(ctx, [100000 + s for s in range(nmol)], log=lambda *a, **k: None)
+    out = {"workload": f"{nmol} held-out molecules of the learned-guess evaluation (seeds 100000+), CIS, 10 roots, "
+                       "tol 1e-6 Eh, FP64",
+           "atoms": [r["atoms"] for r in rows]}
+    for key in ("gap", "gap_pspace", "learned_pspace"):
+        out[key] = {"iterations": [r[key]["iterations"] for r in rows],
+                    "time_to_1e-4_eV_s": [round(r[key]["time_to_1e-4_eV"], 4) for r in rows],
+                    "solve_s": [r[key]["seconds"] for r in rows]}
+    tg = sum(out["gap"]["time_to_1e-4_eV_s"])
+    tl = sum(out["learned_pspace"]["time_to_1e-4_eV_s"])
+    out["speedup_time_to_1e-4_eV_vs_gap"] = round(tg / tl, 3) if tl > 0 else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,8 +281,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
                     help="transform precision of the timed run (fp32: mixed mode finishing in FP64)")
+    ap.add_argument("--guess", choices=["learned", "gap"], default="learned",
+                    help="starting space of the timed run (learned: the packaged network's 2K best pairs)")
     ap.add_argument("--no-fp64-comparison", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-molecule batched CIS section")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess section")
     ap.add_argument("--no-batched-loop", action="store_true",
                     help="skip the per-molecule FP64 comparison loop of the batched section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -299,28 +325,47 @@ def main():
     ref = _golden()
     K = args.steps
     prec = seqx.FP32 if args.precision == "fp32" else seqx.FP64
-    main_run = run_mode(ctx, mol, ref, prec, K, args.warmup)
+    guess, pspace = (seqx.GUESS_LEARNED, 2 * NROOTS) if args.guess == "learned" else (seqx.GUESS_GAP, 0)
+    if guess == seqx.GUESS_LEARNED:
+        ctx.mlp_load(os.path.join(ROOT, "paper_2505_24807_amd", "guess_net.bin"))
+    main_run = run_mode(ctx, mol, ref, prec, K, args.warmup, guess, pspace)
     n, o, v = main_run["dims"]
     s = summary(main_run, K)
     mode = ("FP32 transforms (FP64 contraction sums, FP64 subspace), finished with FP64 products"
             if prec == seqx.FP32 else "FP64 transforms")
+    mode += (", learned starting space (the 20 best-scored pairs)" if guess == seqx.GUESS_LEARNED
+             else ", gap guess")
     out = {
         "metric": METRIC, "value": s.pop("value"), "unit": "sigma-vectors/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": s.pop("ms_per_step"), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision.replace("fp", "f"), "data": "synthetic",
         "config": {"workload": "(H2O)330 water cluster, 990 atoms, 1980 AOs (1320 occ, 660 virt), TDHF, "
-                               f"10 lowest singlet roots, residual tol 1e-5 Eh, {mode}, gap guess",
+                               f"10 lowest singlet roots, residual tol 1e-5 Eh, {mode}",
                    "seed": 330, "nov": o * v},
     }
     out.update(s)
     out["roofline"] = roofline_of(main_run, args.precision)
-    if prec != seqx.FP64 and not args.no_fp64_comparison:
+    if not args.no_fp64_comparison and (prec != seqx.FP64 or guess != seqx.GUESS_GAP):
+        # the plain FP64 Davidson (gap guess) and, for a learned run, mixed precision alone
         r64 = run_mode(ctx, mol, ref, seqx.FP64, K, args.warmup)
         s64 = summary(r64, K)
         s64["roofline"] = roofline_of(r64, "fp64")
         out["fp64_comparison"] = s64
+        out["speedup_vs_plain_fp64"] = {"time_per_step": round(s64["ms_per_step"] / out["ms_per_step"], 3),
+                                        "time_to_10_roots_at_1e-4_eV": (
+                                            round(s64["time_to_10_roots_at_1e-4_eV_s"] / out["time_to_10_roots_at_1e-4_eV_s"], 3)
+                                            if s64["time_to_10_roots_at_1e-4_eV_s"] and out["time_to_10_roots_at_1e-4_eV_s"]
+                                            else None)}
+        if prec != seqx.FP64 and guess != seqx.GUESS_GAP:
+            rm = run_mode(ctx, mol, ref, prec, K, args.warmup)
+            out["mixed_gap_guess_comparison"] = {k: v for k, v in summary(rm, K).items()
+                                                 if k in ("value", "ms_per_step", "time_to_10_roots_at_1e-4_eV_s",
+                                                          "davidson_iterations", "n_sigma_per_step",
+                                                          "parity_max_abs_eV_vs_oracle")}
     if not args.no_batched:
         out["batched_c4"] = batched_c4(ctx, K, loop=not args.no_batched_loop)
+    if not args.no_learned:
+        out["learned_c5"] = learned_c5(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mol, pr, args.cpu_vectors)
     print(json.dumps(out))
