@@ -297,7 +297,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU path is not built "
-                                   "(see the sharding notes in DESIGN.md)", "n_gpus": args.gpus}))
+                                   "(multi-GPU sharding is a design note only)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch

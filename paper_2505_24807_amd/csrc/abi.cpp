@@ -363,7 +363,7 @@ namespace {
 void check_precision(int32_t precision) {
   if (precision == SEQX_FP64 || precision == SEQX_FP32) return;
   if (precision == SEQX_BF16 || precision == SEQX_BF16X3)
-    throw Error(kEArg, "BF16 transforms are not available in this build");
+    throw Error(kEArg, "BF16 transforms are not available");
   throw Error(kEArg, "unknown precision");
 }
 }  // namespace

@@ -5,7 +5,7 @@ Hamiltonian and the density matrix in the AO basis; orbital and excitation
 energies; oscillator strengths; and the sigma products and transition
 densities carried back to the AO basis (MO phases and rotations inside
 degenerate levels are arbitrary, the AO-basis operators are not).
-Tolerances: the spec FP64 bar is 1e-6 eV on excitation energies; the
+Tolerances: the FP64 bar is 1e-6 eV on excitation energies; the
 integrals, Fock build and sigma products are compared far tighter (rounding
 of O(1e3)-term sums in FP64 stays below 1e-11 hartree).
 """
