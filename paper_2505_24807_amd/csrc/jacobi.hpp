@@ -1,5 +1,5 @@
-// Symmetric eigensolver for small matrices held in LDS by one 256-thread
-// workgroup: cyclic Jacobi with the round-robin (tournament) ordering, so each
+// Symmetric eigensolver for small matrices held in LDS by one workgroup of
+// NT threads (a power of two, at most 256): cyclic Jacobi with the round-robin (tournament) ordering, so each
 // round rotates ne/2 disjoint index pairs at once (rows, then columns), with
 // ne = n rounded up to even.  Used for the subspace problems of the batched
 // solver and for the small Gram and collapse matrices of the single-molecule
@@ -21,11 +21,12 @@ struct JacobiLds {
   double red[256];
 };
 
-// fixed-order sum over the 256 threads (result in every thread)
+// fixed-order sum over the NT threads (result in every thread)
+template <int NT>
 __device__ inline double jacobi_block_sum(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = NT / 2; h > 0; h >>= 1) {
     if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
@@ -40,8 +41,9 @@ __device__ inline double jacobi_block_sum(double v, double* red) {
 // off-diagonal sum of squares is below 1e-28 of the total (elements ~1e-14 of
 // the largest; FP64 rounding keeps the sum near n * 1e-32 of the total) or
 // after 40 sweeps.
+template <int NT>
 __device__ inline void jacobi_lds(int n, JacobiLds& L) {
-  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
     const int i = idx / n, j = idx % n;
     L.Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
@@ -49,14 +51,14 @@ __device__ inline void jacobi_lds(int n, JacobiLds& L) {
   const int ne = n + (n & 1), half = ne / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+    for (int idx = threadIdx.x; idx < n * n; idx += NT) {
       const int i = idx / n, j = idx % n;
       const double a2 = L.A[i][j] * L.A[i][j];
       tot += a2;
       if (i != j) off += a2;
     }
-    off = jacobi_block_sum(off, L.red);
-    tot = jacobi_block_sum(tot, L.red);
+    off = jacobi_block_sum<NT>(off, L.red);
+    tot = jacobi_block_sum<NT>(tot, L.red);
     if (!(off > 1e-28 * tot)) break;
     for (int r = 0; r < ne - 1; ++r) {
       if (threadIdx.x < half) {
@@ -82,7 +84,7 @@ __device__ inline void jacobi_lds(int n, JacobiLds& L) {
         L.s[k] = s;
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < half * n; idx += 256) {  // rows p, q
+      for (int idx = threadIdx.x; idx < half * n; idx += NT) {  // rows p, q
         const int k = idx / n, j = idx % n;
         const int p = L.p[k], q = L.q[k];
         if (q < 0) continue;
@@ -91,7 +93,7 @@ __device__ inline void jacobi_lds(int n, JacobiLds& L) {
         L.A[q][j] = L.s[k] * ap + L.c[k] * aq;
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < half * n; idx += 256) {  // columns p, q of A and Q
+      for (int idx = threadIdx.x; idx < half * n; idx += NT) {  // columns p, q of A and Q
         const int k = idx / n, i = idx % n;
         const int p = L.p[k], q = L.q[k];
         if (q < 0) continue;

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(256) small_eigh_kernel(int n, double* A, int l
     L.A[i][j] = i >= j ? A[i + static_cast<long>(j) * lda] : A[j + static_cast<long>(i) * lda];  // lower triangle
   }
   __syncthreads();
-  jacobi_lds(n, L);
+  jacobi_lds<256>(n, L);
   for (int idx = threadIdx.x; idx < n * n; idx += 256) {
     const int r = idx / n, i = idx % n;
     A[i + static_cast<long>(r) * lda] = L.Q[i][L.perm[r]];
