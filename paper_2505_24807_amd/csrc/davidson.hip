@@ -557,7 +557,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
         zero_upper_cm(st, S, w.Lm.p, Smax);
         dgemm_cm(st, false, false, S, S, S, 1.0, w.Mp.p, Smax, w.Lm.p, Smax, 0.0, w.Tmp.p, Smax);  // M+ L
         dgemm_cm(st, true, false, S, S, S, 1.0, w.Lm.p, Smax, w.Tmp.p, Smax, 0.0, w.Hs.p, Smax);    // L^T M+ L
-        ds.eigh(S, w.Hs.p, Smax, w.w2.p);
+        ds.eigh_lowest(S, w.Hs.p, Smax, K, w.w2.p);  // only the K lowest pairs are used
         hipLaunchKernelGGL(omega_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, w.w2.p, om, 1);
         dgemm_cm(st, false, false, S, K, S, 1.0, w.Lm.p, Smax, w.Hs.p, Smax, 0.0, tco, Smax);   // L z
         dgemm_cm(st, false, false, S, K, S, 1.0, w.Tmp.p, Smax, w.Hs.p, Smax, 0.0, uco, Smax);  // M+ L z
@@ -565,7 +565,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
         hipLaunchKernelGGL(scale_cols_kernel, dim3(K), dim3(256), 0, st, uco, Smax, S, K, om, 1.5);
       } else {
         copy(st, w.Hs.p, w.Mp.p, static_cast<long>(S) * Smax);
-        ds.eigh(S, w.Hs.p, Smax, w.w2.p);
+        ds.eigh_lowest(S, w.Hs.p, Smax, std::min(2 * K, S), w.w2.p);  // K Ritz pairs, 2K for a collapse
         hipLaunchKernelGGL(omega_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, w.w2.p, om, 0);
         copy(st, tco, w.Hs.p, static_cast<long>(K) * Smax);
       }

@@ -1,4 +1,5 @@
 // Small device kernels and the rocSOLVER wrapper.
+#include <algorithm>
 #include <rocsolver/rocsolver.h>
 
 #include "jacobi.hpp"
@@ -53,7 +54,22 @@ void DenseSolver::eigh(int n, double* A, int lda, double* w) {
   SEQX_RB(rocsolver_dsyevd(h_, rocblas_evect_original, rocblas_fill_lower, n, A, lda, w, work_.p, info_.p));
 }
 
+void DenseSolver::eigh_lowest(int n, double* A, int lda, int k, double* w) {
+  if (n <= 0 || k <= 0) return;
+  k = std::min(k, n);
+  if (n <= kJacobiMax || n > kSmallDense) {
+    eigh(n, A, lda, w);
+    return;
+  }
+  small_.ensure(small_syevx_scratch(n, k));
+  launch_small_syevx(st_, n, A, lda, k, w, small_.p, info_.p);
+}
+
 void DenseSolver::potrf(int n, double* A, int lda) {
+  if (n <= kSmallDense) {
+    launch_small_potrf(st_, n, A, lda, info_.p + 1);
+    return;
+  }
   SEQX_RB(rocsolver_dpotrf(h_, rocblas_fill_lower, n, A, lda, info_.p + 1));
 }
 

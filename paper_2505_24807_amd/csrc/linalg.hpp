@@ -8,6 +8,14 @@
 
 namespace seqx {
 
+constexpr int kSmallDense = 256;  // largest n of the one-workgroup dense kernels
+
+// one-workgroup kernels (small_dense.hip): k lowest eigenpairs (A's columns
+// 0..k-1 and w), lower Cholesky; scratch holds small_syevx_scratch(n, k) doubles
+size_t small_syevx_scratch(int n, int k);
+void launch_small_syevx(hipStream_t st, int n, double* A, int lda, int k, double* w, double* scratch, int* info);
+void launch_small_potrf(hipStream_t st, int n, double* A, int lda, int* info);
+
 // Dense symmetric eigensolver / Cholesky on the device (rocSOLVER), FP64,
 // column-major storage.  One instance per context stream.
 class DenseSolver {
@@ -18,7 +26,13 @@ class DenseSolver {
   DenseSolver& operator=(const DenseSolver&) = delete;
   // eigenvalues ascending into w[n]; eigenvectors overwrite A (columns)
   void eigh(int n, double* A, int lda, double* w);
-  // lower Cholesky factor in place; returns false when not positive definite
+  // the k lowest eigenpairs only: w[0..k), eigenvectors in columns 0..k-1 of A
+  // (the rest of A is overwritten).  n <= kSmallDense runs as one workgroup
+  // (Householder tridiagonalisation, Sturm bisection, inverse iteration,
+  // back-transformation); larger n uses eigh.  Reads the lower triangle.
+  void eigh_lowest(int n, double* A, int lda, int k, double* w);
+  // lower Cholesky factor in place (upper triangle untouched); info reports
+  // the first non-positive pivot.  n <= kSmallDense runs as one workgroup.
   void potrf(int n, double* A, int lda);
   // device info word of the last eigh / potrf calls (0 = success); synchronises
   int info_eigh();
@@ -27,7 +41,7 @@ class DenseSolver {
  private:
   rocblas_handle h_ = nullptr;
   hipStream_t st_;
-  DBuf<double> work_;
+  DBuf<double> work_, small_;
   DBuf<int> info_;
 };
 
