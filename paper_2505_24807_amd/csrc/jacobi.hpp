@@ -21,16 +21,15 @@ struct JacobiLds {
   double red[256];
 };
 
-// fixed-order sum over the NT threads (result in every thread)
+// fixed-order sum over the NT threads (result in every thread): butterfly
+// within each wavefront, then the wavefront sums in order
 template <int NT>
 __device__ inline double jacobi_block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int h = NT / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = 0.0;
+  for (int q = 0; q < NT / 64; ++q) r += red[q];
   __syncthreads();
   return r;
 }

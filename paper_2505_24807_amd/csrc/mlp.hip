@@ -383,44 +383,74 @@ __global__ void __launch_bounds__(256) feature_stats_kernel(long npairs, const f
   }
 }
 
-// M best pairs by (score descending, index ascending); learned = 0 scores by -gap.
-__global__ void __launch_bounds__(256) select_kernel(long nov, int v, int o, int M, int learned,
-                                                     const float* __restrict__ z, const double* __restrict__ eps,
-                                                     int* __restrict__ sel) {
-  __shared__ double bs[256];
-  __shared__ long bi[256];
+// M best pairs by (score descending, index ascending); learned = 0 scores by
+// -gap.  Stage 1: every workgroup keeps the M best of its contiguous chunk
+// (M rounds of a lexicographic workgroup maximum); stage 2: one workgroup
+// picks the M best of the candidates.  Both stages visit candidates in index
+// order, so ties go to the lower flat index.
+__device__ __forceinline__ bool better(double s, long i, double t, long j) { return s > t || (s == t && i < j); }
+
+__device__ void topm_block(long n0, long n1, int M, const double* cs, const long* ci, int learned_src,
+                           const float* __restrict__ z, const double* __restrict__ eps, int v, int o,
+                           double* outs, long* outi, double* bs, long* bi) {
   double ls = 1e300;
   long li = -1;
   for (int r = 0; r < M; ++r) {
     double best = -1e300;
-    long bidx = nov;
-    for (long x = threadIdx.x; x < nov; x += 256) {
-      const double s = learned ? static_cast<double>(z[x]) : -(eps[o + x % v] - eps[x / v]);
-      const bool after = s < ls || (s == ls && x > li);
-      if (after && (s > best || (s == best && x < bidx))) {
-        best = s;
-        bidx = x;
+    long bidx = 0x7fffffffffffffffL;
+    for (long x = n0 + threadIdx.x; x < n1; x += 256) {
+      double sc;
+      long id;
+      if (cs) {
+        sc = cs[x];
+        id = ci[x];
+      } else {
+        sc = learned_src ? static_cast<double>(z[x]) : -(eps[o + x % v] - eps[x / v]);
+        id = x;
+      }
+      if (id < 0) continue;
+      if (better(ls, li, sc, id) && better(sc, id, best, bidx)) {
+        best = sc;
+        bidx = id;
       }
     }
     bs[threadIdx.x] = best;
     bi[threadIdx.x] = bidx;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-      if (threadIdx.x < h) {
-        const double s2 = bs[threadIdx.x + h];
-        const long i2 = bi[threadIdx.x + h];
-        if (s2 > bs[threadIdx.x] || (s2 == bs[threadIdx.x] && i2 < bi[threadIdx.x])) {
-          bs[threadIdx.x] = s2;
-          bi[threadIdx.x] = i2;
-        }
+      if (threadIdx.x < h && better(bs[threadIdx.x + h], bi[threadIdx.x + h], bs[threadIdx.x], bi[threadIdx.x])) {
+        bs[threadIdx.x] = bs[threadIdx.x + h];
+        bi[threadIdx.x] = bi[threadIdx.x + h];
       }
       __syncthreads();
     }
     ls = bs[0];
     li = bi[0];
-    if (threadIdx.x == 0) sel[r] = static_cast<int>(li);
+    if (threadIdx.x == 0) {
+      outs[r] = ls;
+      outi[r] = li < 0x7fffffffffffffffL ? li : -1;
+    }
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(256) topm_stage1_kernel(long nov, long chunk, int v, int o, int M, int learned,
+                                                          const float* __restrict__ z, const double* __restrict__ eps,
+                                                          double* __restrict__ cs, long* __restrict__ ci) {
+  __shared__ double bs[256];
+  __shared__ long bi[256];
+  const long n0 = blockIdx.x * chunk, n1 = min(nov, n0 + chunk);
+  topm_block(n0, n1, M, nullptr, nullptr, learned, z, eps, v, o, cs + static_cast<long>(blockIdx.x) * M,
+             ci + static_cast<long>(blockIdx.x) * M, bs, bi);
+}
+
+__global__ void __launch_bounds__(256) topm_stage2_kernel(long ncand, int M, const double* __restrict__ cs,
+                                                          const long* __restrict__ ci, double* __restrict__ ws,
+                                                          long* __restrict__ wi, int* __restrict__ sel) {
+  __shared__ double bs[256];
+  __shared__ long bi[256];
+  topm_block(0, ncand, M, cs, ci, 0, nullptr, nullptr, 1, 0, ws, wi, bs, bi);
+  for (int r = threadIdx.x; r < M; r += 256) sel[r] = static_cast<int>(wi[r]);
 }
 
 __global__ void unit_rows_kernel(long nov, int M, const int* __restrict__ sel, double* __restrict__ V) {
@@ -608,8 +638,15 @@ void pspace_guess(const Mlp* net, const DeviceMolecule& m, int M, bool learned, 
     mlp_features(m, w.feats.p, w, st);
     mlp_scores(*net, nov, w.feats.p, w.z.p, st);
   }
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, st, nov, m.nvirt, m.nocc, M, learned ? 1 : 0,
-                     learned ? w.z.p : nullptr, m.eps.p, w.sel.p);
+  const long chunk = std::max<long>(1024, ceil_div(nov, 512));
+  const int nblk = static_cast<int>(ceil_div(nov, chunk));
+  w.cand.ensure(static_cast<size_t>(nblk) * M + M);
+  w.candi.ensure(static_cast<size_t>(nblk) * M + M);
+  hipLaunchKernelGGL(topm_stage1_kernel, dim3(nblk), dim3(256), 0, st, nov, chunk, m.nvirt, m.nocc, M,
+                     learned ? 1 : 0, learned ? w.z.p : nullptr, m.eps.p, w.cand.p, w.candi.p);
+  hipLaunchKernelGGL(topm_stage2_kernel, dim3(1), dim3(256), 0, st, static_cast<long>(nblk) * M, M, w.cand.p,
+                     w.candi.p, w.cand.p + static_cast<long>(nblk) * M, w.candi.p + static_cast<long>(nblk) * M,
+                     w.sel.p);
   hipLaunchKernelGGL(unit_rows_kernel, dim3(static_cast<unsigned>(ceil_div(nov, 256)), M), dim3(256), 0, st, nov, M,
                      w.sel.p, V);
   SEQX_LAUNCH_CHECK();

@@ -39,7 +39,8 @@ struct Mlp {
 
 struct MlpWork {
   DBuf<float> feats, z, dz, w, part, grad;
-  DBuf<double> pop, cent, lossm;
+  DBuf<double> pop, cent, lossm, cand;
+  DBuf<long> candi;
   DBuf<int2> tiles;
   DBuf<long> seg;
   DBuf<int> sel;

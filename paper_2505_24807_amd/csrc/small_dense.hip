@@ -22,21 +22,21 @@ namespace {
 constexpr int kNT = 1024;
 constexpr int kNW = kNT / 64;
 
-__device__ double block_sum_1024(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int h = kNT / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-
 __device__ __forceinline__ double wave_sum64(double s) {
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   return s;
+}
+
+// fixed-order sum over the 1024 threads: butterfly within each wavefront, then
+// the 16 wavefront sums in order (two barriers)
+__device__ double block_sum_1024(double v, double* red) {
+  v = wave_sum64(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int q = 0; q < kNW; ++q) r += red[q];
+  __syncthreads();
+  return r;
 }
 
 // number of eigenvalues of T (d, e2 = e^2) below x
@@ -100,9 +100,17 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
       const int g = tid >> 8, r = tid & 255;
       const int l0 = (m * g) / 4, l1 = (m * (g + 1)) / 4;
       for (int i = r; i < m; i += 256) {
-        double s = 0.0;
-        for (int l = l0; l < l1; ++l) s += W[static_cast<long>(j + 1 + l) * n + j + 1 + i] * vs[l];
-        ps[g][i] = s;
+        const double* wi = W + static_cast<long>(j + 1) * n + j + 1 + i;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;  // four independent chains keep loads in flight
+        int l = l0;
+        for (; l + 4 <= l1; l += 4) {
+          s0 += wi[static_cast<long>(l) * n] * vs[l];
+          s1 += wi[static_cast<long>(l + 1) * n] * vs[l + 1];
+          s2 += wi[static_cast<long>(l + 2) * n] * vs[l + 2];
+          s3 += wi[static_cast<long>(l + 3) * n] * vs[l + 3];
+        }
+        for (; l < l1; ++l) s0 += wi[static_cast<long>(l) * n] * vs[l];
+        ps[g][i] = (s0 + s1) + (s2 + s3);
       }
     }
     __syncthreads();
@@ -115,6 +123,7 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
     const double K = 0.5 * t * block_sum_1024(pvl, red);
     for (int i = tid; i < m; i += kNT) ws[i] = pv[i] - K * vs[i];
     __syncthreads();
+#pragma unroll 4
     for (int idx = tid; idx < m * m; idx += kNT) {
       const int i = idx % m, l = idx / m;
       W[static_cast<long>(j + 1 + l) * n + j + 1 + i] -= vs[i] * ws[l] + ws[i] * vs[l];
@@ -182,72 +191,85 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
   }
   __syncthreads();
 
-  // ---- eigenvectors of T by inverse iteration, one thread per vector
+  // ---- eigenvectors of T by inverse iteration, one thread per vector.  The
+  // per-vector arrays are interleaved by element ([i][t]), so the k threads,
+  // which step through i together, share cache lines.
   if (tid < k) {
     const int tt = tid;
-    double* u0 = per + static_cast<long>(tt) * 6 * n;
-    double* u1 = u0 + n;
-    double* u2 = u1 + n;
-    double* lm = u2 + n;
-    double* pvt = lm + n;
-    double* y = pvt + n;
+    const long kk = k;
+    double* u0 = per;  // reciprocal pivots after the factorisation
+    double* u1 = u0 + kk * n;
+    double* u2 = u1 + kk * n;
+    double* lm = u2 + kk * n;
+    double* pvt = lm + kk * n;
+    double* y = pvt + kk * n;
     const double l_t = lam[tt];
-    // factor (T - lam I) = P L U once, U with two superdiagonals
-    for (int i = 0; i < n; ++i) {
-      u0[i] = d[i] - l_t;
-      u1[i] = i + 1 < n ? e[i] : 0.0;
-      u2[i] = 0.0;
-    }
+    const double pert = 2.2e-16 * tnorm + 1e-300;
+    // factor P (T - lam I) = L U, U with two superdiagonals; row i of U is (u0, u1, u2)
+    double c0 = d[0] - l_t, c1 = n > 1 ? e[0] : 0.0, c2 = 0.0;  // current pivot row
     for (int i = 0; i + 1 < n; ++i) {
       const double sub = e[i];
-      if (fabs(sub) > fabs(u0[i])) {  // swap rows i and i+1
-        const double r0 = sub, r1 = d[i + 1] - l_t, r2 = i + 2 < n ? e[i + 1] : 0.0;
-        const double o0 = u0[i], o1 = u1[i], o2 = u2[i];
-        const double mlt = o0 / r0;
-        u0[i] = r0;
-        u1[i] = r1;
-        u2[i] = r2;
-        u0[i + 1] = o1 - mlt * r1;
-        u1[i + 1] = o2 - mlt * r2;
-        lm[i] = mlt;
-        pvt[i] = 1.0;
+      const double r1 = d[i + 1] - l_t, r2 = i + 2 < n ? e[i + 1] : 0.0;
+      double n0, n1;  // next row's entries in columns i+1, i+2
+      if (fabs(sub) > fabs(c0)) {  // swap rows i and i+1
+        const double mlt = c0 / sub;
+        u1[i * kk + tt] = r1;
+        u2[i * kk + tt] = r2;
+        n0 = c1 - mlt * r1;
+        n1 = c2 - mlt * r2;
+        lm[i * kk + tt] = mlt;
+        pvt[i * kk + tt] = 1.0;
+        c0 = sub;
       } else {
-        const double mlt = u0[i] != 0.0 ? sub / u0[i] : 0.0;
-        u0[i + 1] = u0[i + 1] - mlt * u1[i];
-        lm[i] = mlt;
-        pvt[i] = 0.0;
+        const double mlt = c0 != 0.0 ? sub / c0 : 0.0;
+        u1[i * kk + tt] = c1;
+        u2[i * kk + tt] = c2;
+        n0 = r1 - mlt * c1;
+        n1 = r2 - mlt * c2;
+        lm[i * kk + tt] = mlt;
+        pvt[i * kk + tt] = 0.0;
       }
+      if (fabs(c0) < pert) c0 = c0 < 0.0 ? -pert : pert;
+      u0[i * kk + tt] = 1.0 / c0;
+      c0 = n0;
+      c1 = n1;
+      c2 = 0.0;
     }
-    const double pert = 2.2e-16 * tnorm + 1e-300;
-    for (int i = 0; i < n; ++i)
-      if (fabs(u0[i]) < pert) u0[i] = u0[i] < 0.0 ? -pert : pert;
+    if (fabs(c0) < pert) c0 = c0 < 0.0 ? -pert : pert;
+    u0[(n - 1) * kk + tt] = 1.0 / c0;
+    u1[(n - 1) * kk + tt] = 0.0;
+    u2[(n - 1) * kk + tt] = 0.0;
     // deterministic start: a fixed pseudo-random vector per eigenvalue index
-    unsigned long long st = 0x9E3779B97F4A7C15ULL * (tt + 1);
+    unsigned long long sd = 0x9E3779B97F4A7C15ULL * (tt + 1);
     for (int i = 0; i < n; ++i) {
-      st = st * 6364136223846793005ULL + 1442695040888963407ULL;
-      y[i] = static_cast<double>(static_cast<long long>(st >> 11)) / 9007199254740992.0 - 0.5;
+      sd = sd * 6364136223846793005ULL + 1442695040888963407ULL;
+      y[i * kk + tt] = static_cast<double>(static_cast<long long>(sd >> 11)) / 9007199254740992.0 - 0.5;
     }
-    for (int it = 0; it < 3; ++it) {
-      for (int i = 0; i + 1 < n; ++i) {  // apply P L^-1
-        if (pvt[i] != 0.0) {
-          const double tmp = y[i];
-          y[i] = y[i + 1];
-          y[i + 1] = tmp;
+    for (int it = 0; it < 2; ++it) {
+      double carry = y[0 * kk + tt];  // running element i of P L^-1 y
+      for (int i = 0; i + 1 < n; ++i) {
+        double next = y[(i + 1) * kk + tt];
+        if (pvt[i * kk + tt] != 0.0) {
+          const double tmp = carry;
+          carry = next;
+          next = tmp;
         }
-        y[i + 1] -= lm[i] * y[i];
+        y[i * kk + tt] = carry;
+        carry = next - lm[i * kk + tt] * carry;
       }
-      double nrm = 0.0;
-      for (int i = n - 1; i >= 0; --i) {  // U^-1
-        double s = y[i];
-        if (i + 1 < n) s -= u1[i] * y[i + 1];
-        if (i + 2 < n) s -= u2[i] * y[i + 2];
-        y[i] = s / u0[i];
-        nrm += y[i] * y[i];
+      y[(n - 1) * kk + tt] = carry;
+      double nrm = 0.0, x1 = 0.0, x2 = 0.0;  // x1, x2: solution at rows i+1, i+2
+      for (int i = n - 1; i >= 0; --i) {
+        const double xi = (y[i * kk + tt] - u1[i * kk + tt] * x1 - u2[i * kk + tt] * x2) * u0[i * kk + tt];
+        y[i * kk + tt] = xi;
+        nrm += xi * xi;
+        x2 = x1;
+        x1 = xi;
       }
       const double inv = 1.0 / sqrt(nrm);
-      for (int i = 0; i < n; ++i) y[i] *= inv;
+      for (int i = 0; i < n; ++i) y[i * kk + tt] *= inv;
     }
-    for (int i = 0; i < n; ++i) Z[static_cast<long>(tt) * n + i] = y[i];
+    for (int i = 0; i < n; ++i) Z[static_cast<long>(tt) * n + i] = y[i * kk + tt];
   }
   __syncthreads();
   // modified Gram-Schmidt inside clusters (|lam_s - lam_t| < 1e-3 ||T||)
@@ -327,6 +349,7 @@ __global__ void __launch_bounds__(kNT) small_potrf_kernel(int n, double* __restr
     for (int i = j + 1 + tid; i < n; i += kNT) A[i + static_cast<long>(j) * lda] *= inv;
     __syncthreads();
     const int m = n - j - 1;
+#pragma unroll 4
     for (int idx = tid; idx < m * m; idx += kNT) {
       const int i = idx % m, l = idx / m;
       if (i >= l) A[(j + 1 + i) + static_cast<long>(j + 1 + l) * lda] -=
