@@ -120,14 +120,17 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, double a
 
 // ---------------------------------------------------------------- 128 x 128 tiles
 // For the dense transforms: each of the four wavefronts owns a 64 x 64
-// quadrant (4 x 4 MFMA tiles); global loads of element pairs.  The K panels
-// are double-buffered in LDS: the loads of panel k+1 are issued (and kept
-// ahead of the MFMAs by a scheduling barrier) before the MFMAs of panel k, and
-// land in the other LDS buffer afterwards, so one barrier per panel suffices.
-// Interior and edge tiles take separate code paths.  Needs even leading
-// dimensions and batch strides and pair-aligned base pointers (checked by the
-// dispatcher).  Panel depth: 16 (FP64) or 32 (FP32), which keeps the loads of
-// one panel at 16 registers per lane either way.
+// quadrant (4 x 4 MFMA tiles); loads of element pairs.  The K panels are
+// double-buffered in LDS: the loads of a later panel are issued (and kept
+// ahead of the MFMAs by a scheduling barrier) before the MFMAs of the current
+// one and land in the other LDS buffer afterwards, so one barrier per panel
+// suffices.  FP64 prefetches one panel ahead; FP32 two panels ahead with two
+// register sets, buffer loads on interior tiles and LDS operand reads issued
+// one k-step ahead of the MFMAs.  Interior and edge tiles take separate code
+// paths.  Needs even leading dimensions and batch strides and pair-aligned
+// base pointers (checked by the dispatcher).  Panel depth: 16 (FP64) or 32
+// (FP32), which keeps the loads of one panel at 16 registers per lane either
+// way.
 constexpr int kBM = 128, kBN = 128, kPad = 2;
 
 template <class T>
@@ -136,6 +139,8 @@ struct Panel {
   static constexpr int NP = kBM * BK / 2 / 256;  // element pairs per thread per operand
 };
 
+// FP64 panels: global loads of element pairs; CHECKED tests every element
+// against M, N and K (edge tiles and the K tail).
 template <class T, bool TA, bool TB, bool CHECKED>
 __device__ __forceinline__ void panel_load(const T* __restrict__ A, long lda, const T* __restrict__ B, long ldb, int M,
                                            int N, int K, int m0, int n0, int k0, int tid,
@@ -168,6 +173,80 @@ __device__ __forceinline__ void panel_load(const T* __restrict__ A, long lda, co
   }
 }
 
+// Edge tiles and the K head panel: element loads at clamped indices, so every
+// load is issued unconditionally (which keeps the wait counters exact).  Rows
+// past M and columns past N only feed outputs that are never stored, so their
+// clamped values are harmless; columns k >= K are set to zero.
+template <class T, bool TA, bool TB>
+__device__ __forceinline__ void panel_load_edge(const T* __restrict__ A, long lda, const T* __restrict__ B, long ldb,
+                                                int M, int N, int K, int m0, int n0, int k0, int tid,
+                                                typename Mfma<T>::pair_t* ra, typename Mfma<T>::pair_t* rb) {
+  constexpr int BK = Panel<T>::BK, HK = BK / 2, HM = kBM / 2, HN = kBN / 2;
+  auto ld_a = [&](int gi, int gk) {
+    const T v = TA ? A[static_cast<long>(min(gk, K - 1)) * lda + min(gi, M - 1)]
+                   : A[static_cast<long>(min(gi, M - 1)) * lda + min(gk, K - 1)];
+    return gk < K ? v : T(0);
+  };
+  auto ld_b = [&](int gj, int gk) {
+    const T v = TB ? B[static_cast<long>(min(gj, N - 1)) * ldb + min(gk, K - 1)]
+                   : B[static_cast<long>(min(gk, K - 1)) * ldb + min(gj, N - 1)];
+    return gk < K ? v : T(0);
+  };
+#pragma unroll
+  for (int j = 0; j < Panel<T>::NP; ++j) {
+    const int c = tid + 256 * j;
+    if (!TA) {
+      const int gi = m0 + c / HK, gk = k0 + (c % HK) * 2;
+      ra[j].x = ld_a(gi, gk);
+      ra[j].y = ld_a(gi, gk + 1);
+    } else {
+      const int gk = k0 + c / HM, gi = m0 + (c % HM) * 2;
+      ra[j].x = ld_a(gi, gk);
+      ra[j].y = ld_a(gi + 1, gk);
+    }
+    if (!TB) {
+      const int gk = k0 + c / HN, gj = n0 + (c % HN) * 2;
+      rb[j].x = ld_b(gj, gk);
+      rb[j].y = ld_b(gj + 1, gk);
+    } else {
+      const int gj = n0 + c / HK, gk = k0 + (c % HK) * 2;
+      rb[j].x = ld_b(gj, gk);
+      rb[j].y = ld_b(gj, gk + 1);
+    }
+  }
+}
+
+// Interior panels: buffer loads from a descriptor at the tile's corner, with
+// the panel's position as a scalar offset and a per-thread 32-bit offset fixed
+// for the whole tile, so each load needs one vector register for its address.
+// Word 3 of the descriptor (0x00020000) is the gfx9 raw-buffer format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+
+template <class T>
+__device__ __forceinline__ typename Mfma<T>::pair_t buffer_pair(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                                unsigned soff);
+template <>
+__device__ __forceinline__ f2 buffer_pair<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ d2 buffer_pair<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+template <class T>
+__device__ __forceinline__ void panel_load_fast(__amdgpu_buffer_rsrc_t ar, unsigned asoff, __amdgpu_buffer_rsrc_t br,
+                                                unsigned bsoff, const unsigned* oa, const unsigned* ob,
+                                                typename Mfma<T>::pair_t* ra, typename Mfma<T>::pair_t* rb) {
+#pragma unroll
+  for (int j = 0; j < Panel<T>::NP; ++j) {
+    ra[j] = buffer_pair<T>(ar, oa[j], asoff);
+    rb[j] = buffer_pair<T>(br, ob[j], bsoff);
+  }
+}
+
 template <class T, bool TA, bool TB>
 __device__ __forceinline__ void panel_store(T (*As)[kBM + kPad], T (*Bs)[kBN + kPad], int tid,
                                             const typename Mfma<T>::pair_t* ra, const typename Mfma<T>::pair_t* rb) {
@@ -196,20 +275,52 @@ __device__ __forceinline__ void panel_store(T (*As)[kBM + kPad], T (*Bs)[kBN + k
   }
 }
 
+// FP32: the operands of k-step s + 1 are read from LDS before the MFMAs of
+// step s are issued, so the LDS latency overlaps the matrix-core work.  FP64
+// keeps one operand set: its accumulators take twice the registers, and a
+// second set would cost a wavefront per SIMD.
 template <class T>
 __device__ __forceinline__ void panel_mfma(const T (*As)[kBM + kPad], const T (*Bs)[kBN + kPad], int lane, int wm,
                                            int wn, typename Mfma<T>::acc_t (*acc)[4]) {
+  constexpr int NS = Panel<T>::BK / 4;
+  if constexpr (sizeof(T) == 8) {  // FP64: one operand set, order left to the compiler
 #pragma unroll
-  for (int ks = 0; ks < Panel<T>::BK; ks += 4) {
-    T a[4], bb[4];
+    for (int ks = 0; ks < Panel<T>::BK; ks += 4) {
+      T a[4], bb[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = As[ks + (lane >> 4)][wm + i * 16 + (lane & 15)];
+      for (int i = 0; i < 4; ++i) a[i] = As[ks + (lane >> 4)][wm + i * 16 + (lane & 15)];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bb[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::op(a[i], bb[j], acc[i][j]);
+    }
+    return;
+  }
+  T a[2][4], bb[2][4];
+  auto read = [&](int ks, T* ar, T* br) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ar[i] = As[ks + (lane >> 4)][wm + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) br[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
+  };
+  read(0, a[0], bb[0]);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s + 1 < NS) read(4 * (s + 1), a[(s + 1) & 1], bb[(s + 1) & 1]);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::op(a[i], bb[j], acc[i][j]);
+      for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::op(a[s & 1][i], bb[s & 1][j], acc[i][j]);
+  }
+  // schedule: the LDS reads of step 0, then per step the reads of step s + 1
+  // ahead of the 16 MFMAs of step s (masks: 0x100 LDS read, 0x008 MFMA)
+  __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s + 1 < NS) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
   }
 }
 
@@ -227,25 +338,80 @@ __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
-  typename MF::pair_t ra[Panel<T>::NP], rb[Panel<T>::NP];
-  const int nfull = K / BK;  // panels without a K tail
-  const int npan = (K + BK - 1) / BK;
-  // LDS buffers 0 and 1: rows [0, BK) and [BK, 2 BK) of As / Bs
-  if (nfull > 0) panel_load<T, TA, TB, EDGE>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
-  else panel_load<T, TA, TB, true>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
-  panel_store<T, TA, TB>(As, Bs, tid, ra, rb);
-  __syncthreads();
-  for (int kt = 0; kt < npan; ++kt) {
-    const int cur = (kt & 1) * BK, nxt = BK - cur;
-    const bool more = kt + 1 < npan;
-    if (more) {
-      if (kt + 1 < nfull) panel_load<T, TA, TB, EDGE>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
-      else panel_load<T, TA, TB, true>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    panel_mfma<T>(As + cur, Bs + cur, lane, wm, wn, acc);
-    if (more) panel_store<T, TA, TB>(As + nxt, Bs + nxt, tid, ra, rb);
+  typedef typename MF::pair_t P2;
+  if constexpr (sizeof(T) == 8) {
+    // FP64 (accumulators take 128 registers): one register set for the
+    // prefetch of panel p + 1; the K tail is the last panel.
+    P2 ra[Panel<T>::NP], rb[Panel<T>::NP];
+    const int nfull = K / BK;  // panels without a K tail
+    const int npan = (K + BK - 1) / BK;
+    if (nfull > 0) panel_load<T, TA, TB, EDGE>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
+    else panel_load<T, TA, TB, true>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
+    panel_store<T, TA, TB>(As, Bs, tid, ra, rb);
     __syncthreads();
+    for (int kt = 0; kt < npan; ++kt) {
+      const int cur = (kt & 1) * BK, nxt = BK - cur;
+      const bool more = kt + 1 < npan;
+      if (more) {
+        if (kt + 1 < nfull) panel_load<T, TA, TB, EDGE>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
+        else panel_load<T, TA, TB, true>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      panel_mfma<T>(As + cur, Bs + cur, lane, wm, wn, acc);
+      if (more) panel_store<T, TA, TB>(As + nxt, Bs + nxt, tid, ra, rb);
+      __syncthreads();
+    }
+  } else {
+    // FP32: K is walked as a head panel of K % BK columns (when K is not a
+    // multiple of BK), loaded with zero fill, followed by full panels, so that
+    // the steady-state loop holds no K checks.  Two register sets for the
+    // global prefetch: the loads of panel p + 2 are issued while panel p is
+    // multiplied and have two panels of MFMA work to land before they are
+    // stored to LDS.  The loads are unconditional (past the last panel they
+    // repeat it and are not stored): a conditional load would make the wait
+    // before the LDS stores cover the newest loads as well.
+    P2 ra0[Panel<T>::NP], rb0[Panel<T>::NP], ra1[Panel<T>::NP], rb1[Panel<T>::NP];
+    const int kr = K % BK;
+    const int npan = K / BK + (kr ? 1 : 0);
+    const int kshift = kr ? kr - BK : 0;  // panel p >= 1 starts at p * BK + kshift
+    constexpr int HK = BK / 2, HM = kBM / 2, HN = kBN / 2;
+    unsigned oa[Panel<T>::NP], ob[Panel<T>::NP];  // byte offsets inside a panel (interior tiles)
+#pragma unroll
+    for (int j = 0; j < Panel<T>::NP; ++j) {
+      const int c = tid + 256 * j;
+      oa[j] = static_cast<unsigned>(TA ? (c / HM) * lda + (c % HM) * 2 : (c / HK) * lda + (c % HK) * 2) * sizeof(T);
+      ob[j] = static_cast<unsigned>(TB ? (c / HK) * ldb + (c % HK) * 2 : (c / HN) * ldb + (c % HN) * 2) * sizeof(T);
+    }
+    const __amdgpu_buffer_rsrc_t ar = buffer_rsrc(TA ? A + m0 : A + static_cast<long>(m0) * lda);
+    const __amdgpu_buffer_rsrc_t br = buffer_rsrc(TB ? B + static_cast<long>(n0) * ldb : B + n0);
+    auto load_full = [&](int p, P2* ra, P2* rb) {
+      const int k0 = p * BK + kshift;
+      if (!EDGE)
+        panel_load_fast<T>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(T), br,
+                           static_cast<unsigned>(TB ? k0 : k0 * ldb) * sizeof(T), oa, ob, ra, rb);
+      else
+        panel_load_edge<T, TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, tid, ra, rb);
+    };
+    // LDS buffers 0 and 1: rows [0, BK) and [BK, 2 BK) of As / Bs
+    if (kr) panel_load_edge<T, TA, TB>(A, lda, B, ldb, M, N, kr, m0, n0, 0, tid, ra0, rb0);
+    else load_full(0, ra0, rb0);
+    load_full(min(1, npan - 1), ra1, rb1);
+    panel_store<T, TA, TB>(As, Bs, tid, ra0, rb0);
+    __syncthreads();
+    int kt = 0;
+    for (; kt + 1 < npan; kt += 2) {
+      load_full(min(kt + 2, npan - 1), ra0, rb0);
+      __builtin_amdgcn_sched_barrier(0);
+      panel_mfma<T>(As, Bs, lane, wm, wn, acc);
+      panel_store<T, TA, TB>(As + BK, Bs + BK, tid, ra1, rb1);
+      __syncthreads();
+      load_full(min(kt + 3, npan - 1), ra1, rb1);
+      __builtin_amdgcn_sched_barrier(0);
+      panel_mfma<T>(As + BK, Bs + BK, lane, wm, wn, acc);
+      if (kt + 2 < npan) panel_store<T, TA, TB>(As, Bs, tid, ra0, rb0);
+      __syncthreads();
+    }
+    if (kt < npan) panel_mfma<T>(As, Bs, lane, wm, wn, acc);  // odd panel count: the last one is in buffer 0
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -276,7 +442,7 @@ __global__ void __launch_bounds__(256) gemm128_kernel(int M, int N, int K, doubl
   int bid = blockIdx.y * nbx + blockIdx.x;
   if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
   const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * kBN;
-  if (m0 + kBM <= M && n0 + kBN <= N)
+  if (m0 + kBM <= M && n0 + kBN <= N && (sizeof(T) == 8 || (K & 1) == 0))
     tile128<T, To, TA, TB, EPI, false>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
                                        m0, n0, As, Bs);
   else
@@ -334,7 +500,12 @@ void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   if (epi) ep = *epi;
   const bool skinny = N <= 16;
   const bool even = ((lda | ldb | sA | sB) & 1) == 0 && aligned_to(A, 2 * sizeof(T)) && aligned_to(B, 2 * sizeof(T));
-  if (even && M >= 96 && N >= 96 && K >= 16) {
+  // the 128 x 128 tiles address each operand with 32-bit byte offsets from a
+  // tile corner: rows and panel steps must stay below 2 GiB
+  const long ldmax = lda > ldb ? lda : ldb;
+  const bool small_offsets = (ldmax * (static_cast<long>(K > kBM ? K : kBM) + kBM) + K) * static_cast<long>(sizeof(T)) <
+                             (1L << 31);
+  if (even && small_offsets && M >= 96 && N >= 96 && K >= 16) {
     if (epi) launch128<T, To, true>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
     else launch128<T, To, false>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
   } else if (epi) {
