@@ -324,13 +324,17 @@ __device__ __forceinline__ void panel_mfma(const T (*As)[kBM + kPad], const T (*
   }
 }
 
-template <class T, class To, bool TA, bool TB, bool EPI, bool EDGE>
+// EM: 0 interior tile; 1 edge tile whose pair dimensions (M when A is
+// transposed, N when B is not) are even, loaded like an interior tile at
+// clamped offsets; 2 other edge tiles, element loads.
+template <class T, class To, bool TA, bool TB, bool EPI, int EM>
 __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const T* __restrict__ A, long lda,
                                         const T* __restrict__ B, long ldb, double beta, To* __restrict__ C, long ldc,
                                         long b, const SigmaEpilogue& ep, int m0, int n0, T (*As)[kBM + kPad],
                                         T (*Bs)[kBN + kPad]) {
   typedef Mfma<T> MF;
   constexpr int BK = Panel<T>::BK;
+  constexpr bool EDGE = EM != 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   typename MF::acc_t acc[4][4];
@@ -375,18 +379,26 @@ __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const
     const int npan = K / BK + (kr ? 1 : 0);
     const int kshift = kr ? kr - BK : 0;  // panel p >= 1 starts at p * BK + kshift
     constexpr int HK = BK / 2, HM = kBM / 2, HN = kBN / 2;
-    unsigned oa[Panel<T>::NP], ob[Panel<T>::NP];  // byte offsets inside a panel (interior tiles)
+    // Byte offsets inside a panel.  On edge tiles (EM == 1) rows and columns
+    // past M and N are clamped to the last ones (pair starts to the last
+    // pair): they only feed outputs that are not stored.
+    const int im = M - 1 - m0, in = N - 1 - n0;  // last valid row / column of the tile
+    unsigned oa[Panel<T>::NP], ob[Panel<T>::NP];
 #pragma unroll
     for (int j = 0; j < Panel<T>::NP; ++j) {
       const int c = tid + 256 * j;
-      oa[j] = static_cast<unsigned>(TA ? (c / HM) * lda + (c % HM) * 2 : (c / HK) * lda + (c % HK) * 2) * sizeof(T);
-      ob[j] = static_cast<unsigned>(TB ? (c / HK) * ldb + (c % HK) * 2 : (c / HN) * ldb + (c % HN) * 2) * sizeof(T);
+      int i = TA ? (c % HM) * 2 : c / HK, kk = TA ? c / HM : (c % HK) * 2;
+      if (EM == 1) i = TA ? min(i, im - 1) : min(i, im);
+      oa[j] = static_cast<unsigned>(TA ? kk * lda + i : i * lda + kk) * sizeof(T);
+      int jj = TB ? c / HK : (c % HN) * 2, kb = TB ? (c % HK) * 2 : c / HN;
+      if (EM == 1) jj = TB ? min(jj, in) : min(jj, in - 1);
+      ob[j] = static_cast<unsigned>(TB ? jj * ldb + kb : kb * ldb + jj) * sizeof(T);
     }
     const __amdgpu_buffer_rsrc_t ar = buffer_rsrc(TA ? A + m0 : A + static_cast<long>(m0) * lda);
     const __amdgpu_buffer_rsrc_t br = buffer_rsrc(TB ? B + static_cast<long>(n0) * ldb : B + n0);
     auto load_full = [&](int p, P2* ra, P2* rb) {
       const int k0 = p * BK + kshift;
-      if (!EDGE)
+      if (EM < 2)
         panel_load_fast<T>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(T), br,
                            static_cast<unsigned>(TB ? k0 : k0 * ldb) * sizeof(T), oa, ob, ra, rb);
       else
@@ -442,12 +454,21 @@ __global__ void __launch_bounds__(256) gemm128_kernel(int M, int N, int K, doubl
   int bid = blockIdx.y * nbx + blockIdx.x;
   if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
   const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * kBN;
-  if (m0 + kBM <= M && n0 + kBN <= N && (sizeof(T) == 8 || (K & 1) == 0))
-    tile128<T, To, TA, TB, EPI, false>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
-                                       m0, n0, As, Bs);
-  else
-    tile128<T, To, TA, TB, EPI, true>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
-                                      m0, n0, As, Bs);
+  const bool keven = sizeof(T) == 8 || (K & 1) == 0;  // FP32 panels start at even k
+  if (m0 + kBM <= M && n0 + kBN <= N && keven)
+    tile128<T, To, TA, TB, EPI, 0>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
+                                   n0, As, Bs);
+  else if constexpr (sizeof(T) == 4) {
+    if (keven && (!TA || (M & 1) == 0) && (TB || (N & 1) == 0))
+      tile128<T, To, TA, TB, EPI, 1>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
+                                     m0, n0, As, Bs);
+    else
+      tile128<T, To, TA, TB, EPI, 2>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
+                                     m0, n0, As, Bs);
+  } else {
+    tile128<T, To, TA, TB, EPI, 2>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
+                                   n0, As, Bs);
+  }
 }
 
 // ---------------------------------------------------------------- dispatch

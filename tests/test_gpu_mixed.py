@@ -88,6 +88,45 @@ def test_sigma_fp32_products(ctx, name):
     job.free()
 
 
+LARGE = {
+    # even o and v: interior and clamped-offset edge tiles of the 128 x 128 GEMMs
+    "H2O48": molecules.water_cluster(48, 48),
+    # odd o and v: element-load edge tiles and odd K
+    "C40H42n": molecules.add_noise(molecules.polyene(40), 0.02, np.random.default_rng(4042)),
+}
+
+
+@pytest.mark.parametrize("name", ["H2O48", "C40H42n"])
+def test_sigma_fp32_products_large_tiles(ctx, name):
+    """FP32 products on molecules whose transforms run on the 128 x 128 tiles,
+    against the oracle's matrix-free products (Eqs. 8-9), in the AO basis."""
+    mol = LARGE[name]
+    sy = model.make_system(mol.Z, mol.xyz, PR)
+    ints = integrals.build(sy)
+    res = scf.run(sy, ints)
+    print(f"[gpu] fp32 sigma {name}", flush=True)
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    _, Cl, _ = job.scf_results()
+    n, o, v = job.dims()
+    assert min(n, o, v) >= 96
+    k = 6
+    Y = np.random.default_rng(12).normal(size=(k, n, n))
+    Vl = np.stack([Cl[:, :o].T @ y @ Cl[:, o:] for y in Y])
+    Vo = np.stack([res.C[:, :o].T @ y @ res.C[:, o:] for y in Y])
+    AV, BV = excited.sigma(ints, res.eps, res.C, o, Vo)
+    de = res.eps[None, o:] - res.eps[:o, None]
+    p1, m1 = job.sigma(Vl, theory=seqx.TDHF, precision=seqx.FP32)
+    worst = 0.0
+    for lib, ref in ((p1, AV + BV), (m1, AV - BV)):
+        for j in range(k):
+            d = np.abs(_ao(Cl, o, lib[j].reshape(o, v)) - _ao(res.C, o, ref[j])).max()
+            scale = np.abs(_ao(res.C, o, ref[j] - de * Vo[j])).max()
+            worst = max(worst, d / (n * U32 * scale))
+            assert d <= 8 * n * U32 * scale, (j, d, scale)
+    print(f"[gpu] {name}: worst error / (n u max|2e part|) = {worst:.3f}", flush=True)
+    job.free()
+
+
 @pytest.mark.parametrize("name,theory,K", [("C2H4", seqx.TDHF, 3), ("C20H22n", seqx.TDHF, 5),
                                            ("C20H22n", seqx.CIS, 4), ("H2O12", seqx.TDHF, 6)])
 def test_fp32_solve_finishes_in_fp64(ctx, name, theory, K):
