@@ -21,21 +21,53 @@ namespace {
 
 constexpr int kNT = 1024;
 constexpr int kNW = kNT / 64;
+constexpr int kG = 4;  // columns per wavefront per load batch in the tridiagonalisation pass
 
+// one DPP move of both halves of a double (lanes outside ROWS read 0)
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// sum over the 64 lanes in a fixed order, returned in every lane: pairs,
+// quads, half rows and rows by DPP permutes, then rows 0+1 and (0+1)+2+3 by
+// the row broadcasts of lanes 15 and 31; the total ends in lane 63
 __device__ __forceinline__ double wave_sum64(double s) {
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  return s;
+  s += dpp_move<0xb1>(s);       // quad_perm [1,0,3,2]
+  s += dpp_move<0x4e>(s);       // quad_perm [2,3,0,1]
+  s += dpp_move<0x141>(s);      // row_half_mirror
+  s += dpp_move<0x140>(s);      // row_mirror
+  s += dpp_move<0x142, 0xa>(s);  // row_bcast:15 into rows 1, 3
+  s += dpp_move<0x143, 0xc>(s);  // row_bcast:31 into rows 2, 3
+  const long long b = __double_as_longlong(s);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), 63);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// workgroup barrier that orders LDS accesses only (global accesses that must
+// be seen by other threads need __syncthreads)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // fixed-order sum over the 1024 threads: butterfly within each wavefront, then
-// the 16 wavefront sums in order (two barriers)
+// the 16 wavefront sums in order (two barriers; LDS-only barriers when LDS)
+template <bool LDS = false>
 __device__ double block_sum_1024(double v, double* red) {
   v = wave_sum64(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
+  if (LDS) lds_barrier();
+  else __syncthreads();
   double r = 0.0;
   for (int q = 0; q < kNW; ++q) r += red[q];
-  __syncthreads();
+  if (LDS) lds_barrier();
+  else __syncthreads();
   return r;
 }
 
@@ -57,91 +89,137 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
                                                           double* __restrict__ w, double* __restrict__ scratch,
                                                           int* __restrict__ info) {
   __shared__ double d[kSmallDense], e[kSmallDense], e2[kSmallDense], tau[kSmallDense];
-  __shared__ double vs[kSmallDense], ws[kSmallDense], pv[kSmallDense];
-  __shared__ double ps[4][kSmallDense];
+  __shared__ double xs[kSmallDense], vp[kSmallDense], wp[kSmallDense], pc[kSmallDense], nextc[kSmallDense];
+  __shared__ double prw[kNW][kSmallDense];
   __shared__ double red[kNT];
   __shared__ double lam[kSmallDense];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* W = scratch;
   double* Z = scratch + static_cast<long>(n) * n;
   double* per = Z + static_cast<long>(n) * k;
-  // working copy, symmetric from the lower triangle of A
-  for (int idx = tid; idx < n * n; idx += kNT) {
-    const int i = idx % n, j = idx / n;
-    W[idx] = i >= j ? A[i + static_cast<long>(j) * lda] : A[j + static_cast<long>(i) * lda];
+  // working copy (column-major, W[l * n + i] = A(i, l)) of the lower
+  // triangle.  Element (i, l) belongs to the thread of wavefront l % 16 and
+  // lane i % 64 for the whole reduction, so the passes below touch only their
+  // own elements in global memory and their barriers order LDS alone.
+  for (int l = wave; l < n; l += kNW)
+#pragma unroll
+    for (int c = 0; c < kSmallDense / 64; ++c) {
+      const int i = lane + 64 * c;
+      if (i >= l && i < n) W[static_cast<long>(l) * n + i] = A[i + static_cast<long>(l) * lda];
+    }
+  for (int i = tid; i < n; i += kNT) {
+    vp[i] = 0.0;
+    wp[i] = 0.0;
   }
   __syncthreads();
 
-  // ---- Householder tridiagonalisation (reflector j stored in W[j+1 .., j])
+  // ---- Householder tridiagonalisation, lower triangle only (reflector j
+  // stored in W[j+1 .., j]).  The rank-2 update A -= v w^T + w v^T of step j
+  // is kept pending in (vp, wp) and applied during the pass of step j + 1
+  // that also forms p = A v, so every step reads and writes the trailing
+  // triangle once.
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;
-    double* col = W + static_cast<long>(j) * n + j + 1;
-    double xx = 0.0;
-    for (int i = tid; i < m; i += kNT) xx += col[i] * col[i];
-    xx = block_sum_1024(xx, red);
-    const double x0 = col[0];
-    if (!(xx > 0.0)) {
-      if (tid == 0) {
-        tau[j] = 0.0;
-        e[j] = 0.0;
-        d[j] = W[static_cast<long>(j) * n + j];
+    // column j with the pending update: diagonal d[j] and x = rows j+1 ..
+    double xsq = 0.0;
+    if (tid < m + 1) {
+      const int i = j + tid;
+      // column j as the previous pass left it (kept in LDS), or the input
+      const double cw = j == 0 ? W[i] : nextc[tid];
+      const double c = cw - (vp[i] * wp[j] + wp[i] * vp[j]);
+      if (tid == 0) d[j] = c;
+      else {
+        xs[i] = c;
+        xsq = c * c;
       }
-      __syncthreads();
-      continue;
     }
-    const double alpha = x0 > 0.0 ? -sqrt(xx) : sqrt(xx);
-    const double v0 = x0 - alpha;
-    const double t = 2.0 / (xx - x0 * x0 + v0 * v0);
-    for (int i = tid; i < m; i += kNT) vs[i] = i == 0 ? v0 : col[i];
-    __syncthreads();
-    if (tid == 0) col[0] = v0;
-    // p = t A22 v, the columns of A22 split over four groups of 256 threads
-    {
-      const int g = tid >> 8, r = tid & 255;
-      const int l0 = (m * g) / 4, l1 = (m * (g + 1)) / 4;
-      for (int i = r; i < m; i += 256) {
-        const double* wi = W + static_cast<long>(j + 1) * n + j + 1 + i;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;  // four independent chains keep loads in flight
-        int l = l0;
-        for (; l + 4 <= l1; l += 4) {
-          s0 += wi[static_cast<long>(l) * n] * vs[l];
-          s1 += wi[static_cast<long>(l + 1) * n] * vs[l + 1];
-          s2 += wi[static_cast<long>(l + 2) * n] * vs[l + 2];
-          s3 += wi[static_cast<long>(l + 3) * n] * vs[l + 3];
+    const double xx = block_sum_1024<true>(xsq, red);
+    const double x0 = xs[j + 1];
+    double alpha = 0.0, v0 = x0, t = 0.0;
+    if (xx > 0.0) {
+      alpha = x0 > 0.0 ? -sqrt(xx) : sqrt(xx);
+      v0 = x0 - alpha;
+      t = 2.0 / (xx - x0 * x0 + v0 * v0);
+    }
+    // the reflector, for the back-transformation (column j is never touched again)
+    if (tid < m) W[static_cast<long>(j) * n + j + 1 + tid] = tid == 0 ? v0 : xs[j + 1 + tid];
+    // fused pass over the trailing lower triangle (rows and columns j+1 ..):
+    // apply the pending update, store, and accumulate p = A22 v by rows
+    // (per lane, rows lane + 64 c) and by columns (wavefront sums).  Each
+    // wavefront takes its columns kG at a time, all loads first.  The first
+    // column (the next step's pivot column) is also kept in LDS.
+    double pr[kSmallDense / 64] = {};
+    const int lfirst = j + 1 + (((wave - (j + 1)) % kNW) + kNW) % kNW;
+    for (int l0 = lfirst; l0 < n; l0 += kNW * kG) {
+      double a[kG][kSmallDense / 64];
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const int l = l0 + kNW * g;
+        const double* col = W + static_cast<long>(l) * n;
+#pragma unroll
+        for (int c = 0; c < kSmallDense / 64; ++c) {
+          const int i = lane + 64 * c;
+          a[g][c] = (l < n && i >= l && i < n) ? col[i] : 0.0;
         }
-        for (; l < l1; ++l) s0 += wi[static_cast<long>(l) * n] * vs[l];
-        ps[g][i] = (s0 + s1) + (s2 + s3);
+      }
+      double cs[kG];
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const int l = l0 + kNW * g;
+        cs[g] = 0.0;
+        if (l >= n) continue;
+        const double vl = l == j + 1 ? v0 : xs[l], vpl = vp[l], wpl = wp[l];
+        double* col = W + static_cast<long>(l) * n;
+#pragma unroll
+        for (int c = 0; c < kSmallDense / 64; ++c) {
+          const int i = lane + 64 * c;
+          if (i >= l && i < n) {
+            const double av = a[g][c] - (vp[i] * wpl + wp[i] * vpl);
+            col[i] = av;
+            if (l == j + 1) nextc[i - j - 1] = av;
+            pr[c] += av * vl;
+            if (i > l) cs[g] += av * xs[i];
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const int l = l0 + kNW * g;
+        const double t2 = wave_sum64(cs[g]);
+        if (lane == 0 && l < n) pc[l - j - 1] = t2;
       }
     }
-    __syncthreads();
-    double pvl = 0.0;
-    for (int i = tid; i < m; i += kNT) {
-      const double p = t * (ps[0][i] + ps[1][i] + ps[2][i] + ps[3][i]);
-      pv[i] = p;
-      pvl += p * vs[i];
+#pragma unroll
+    for (int c = 0; c < kSmallDense / 64; ++c) prw[wave][lane + 64 * c] = pr[c];
+    lds_barrier();
+    double pv = 0.0, vi = 0.0;
+    if (tid < m) {
+      const int i = j + 1 + tid;
+      double ssum = pc[tid];
+      for (int q = 0; q < kNW; ++q) ssum += prw[q][i];
+      pv = t * ssum;
+      vi = tid == 0 ? v0 : xs[i];
     }
-    const double K = 0.5 * t * block_sum_1024(pvl, red);
-    for (int i = tid; i < m; i += kNT) ws[i] = pv[i] - K * vs[i];
-    __syncthreads();
-#pragma unroll 4
-    for (int idx = tid; idx < m * m; idx += kNT) {
-      const int i = idx % m, l = idx / m;
-      W[static_cast<long>(j + 1 + l) * n + j + 1 + i] -= vs[i] * ws[l] + ws[i] * vs[l];
+    const double K = 0.5 * t * block_sum_1024<true>(pv * vi, red);
+    if (tid < m) {
+      vp[j + 1 + tid] = vi;
+      wp[j + 1 + tid] = pv - K * vi;
     }
     if (tid == 0) {
       tau[j] = t;
       e[j] = alpha;
-      d[j] = W[static_cast<long>(j) * n + j];
     }
-    __syncthreads();
+    lds_barrier();
   }
-  if (tid == 0) {
+  __syncthreads();  // the last block and the reflectors are read by other threads
+  if (tid == 0) {  // the last 2 x 2 block, with the pending update
     if (n >= 2) {
-      d[n - 2] = W[static_cast<long>(n - 2) * n + n - 2];
-      e[n - 2] = W[static_cast<long>(n - 2) * n + n - 1];
-      tau[n - 2] = 0.0;
+      const int a = n - 2, b = n - 1;
+      d[a] = W[static_cast<long>(a) * n + a] - 2.0 * vp[a] * wp[a];
+      e[a] = W[static_cast<long>(a) * n + b] - (vp[b] * wp[a] + wp[b] * vp[a]);
+      tau[a] = 0.0;
     }
-    d[n - 1] = W[static_cast<long>(n - 1) * n + n - 1];
+    d[n - 1] = W[static_cast<long>(n - 1) * n + n - 1] - 2.0 * vp[n - 1] * wp[n - 1];
   }
   __syncthreads();
   for (int i = tid; i + 1 < n; i += kNT) e2[i] = e[i] * e[i];
@@ -326,35 +404,48 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
   if (tid == 0) info[0] = 0;
 }
 
-// right-looking lower Cholesky of an n x n block (n <= 256); info = first bad pivot (1-based) or 0
+// lower Cholesky of an n x n block (n <= 256), blocked by panels of kPB
+// columns: the panel is factored in LDS, then the trailing lower triangle takes
+// the panel's rank-kPB update in one pass; info = first bad pivot (1-based) or 0
+constexpr int kPB = 16;
+
 __global__ void __launch_bounds__(kNT) small_potrf_kernel(int n, double* __restrict__ A, int lda, int* info) {
-  __shared__ double piv;
+  __shared__ double P[kSmallDense][kPB + 1];
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) bad = 0;
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      const double a = A[j + static_cast<long>(j) * lda];
-      if (!(a > 0.0) || !isfinite(a)) {
-        bad = j + 1;
-      } else {
-        piv = sqrt(a);
-        A[j + static_cast<long>(j) * lda] = piv;
+  for (int j0 = 0; j0 < n; j0 += kPB) {
+    const int nb = min(kPB, n - j0), m = n - j0;  // panel: rows j0 + r, r < m; columns j0 + q, q < nb
+    for (int q = wave; q < nb; q += kNW)
+      for (int r = q + lane; r < m; r += 64) P[r][q] = A[(j0 + r) + static_cast<long>(j0 + q) * lda];
+    __syncthreads();
+    for (int q = 0; q < nb; ++q) {
+      if (tid == 0) {
+        const double a = P[q][q];
+        if (!(a > 0.0) || !isfinite(a)) bad = j0 + q + 1;
+        else P[q][q] = sqrt(a);
       }
+      __syncthreads();
+      if (bad) break;
+      const double inv = 1.0 / P[q][q];
+      for (int r = q + 1 + tid; r < m; r += kNT) P[r][q] *= inv;
+      __syncthreads();
+      for (int qq = q + 1 + wave; qq < nb; qq += kNW)
+        for (int r = qq + lane; r < m; r += 64) P[r][qq] -= P[r][q] * P[qq][q];
+      __syncthreads();
     }
-    __syncthreads();
     if (bad) break;
-    const double inv = 1.0 / piv;
-    for (int i = j + 1 + tid; i < n; i += kNT) A[i + static_cast<long>(j) * lda] *= inv;
-    __syncthreads();
-    const int m = n - j - 1;
-#pragma unroll 4
-    for (int idx = tid; idx < m * m; idx += kNT) {
-      const int i = idx % m, l = idx / m;
-      if (i >= l) A[(j + 1 + i) + static_cast<long>(j + 1 + l) * lda] -=
-          A[(j + 1 + i) + static_cast<long>(j) * lda] * A[(j + 1 + l) + static_cast<long>(j) * lda];
-    }
+    for (int q = wave; q < nb; q += kNW)
+      for (int r = q + lane; r < m; r += 64) A[(j0 + r) + static_cast<long>(j0 + q) * lda] = P[r][q];
+    for (int cl = nb + wave; cl < m; cl += kNW)
+      for (int r = cl + lane; r < m; r += 64) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPB; ++q)
+          if (q < nb) sacc += P[r][q] * P[cl][q];
+        A[(j0 + r) + static_cast<long>(j0 + cl) * lda] -= sacc;
+      }
     __syncthreads();
   }
   if (tid == 0) info[0] = bad;
