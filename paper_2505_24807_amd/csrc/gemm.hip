@@ -602,6 +602,109 @@ void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   dgemm(st, tb, ta, N, M, K, alpha, B, ldb, 0, A, lda, 0, beta, C, ldc, 0, 1, nullptr);
 }
 
+// Tall-skinny inner products on the FP64 matrix cores: partial[c][s][t] =
+// sum over k in chunk c of X[s][k] Y[t][k], for ns <= 48 rows of X and any
+// number of rows of Y (the Davidson basis).  A workgroup takes every row of X
+// and 128 rows of Y (32 per wavefront) over one chunk of kSkinnyChunk, so Y
+// is read once.  Within each block of 16 k-values lane l loads the 4
+// contiguous values 4 (l / 16) .. +3 of its rows (row l % 16 of each 16-row
+// tile) as two 16-byte loads; MFMA step q then takes value q, i.e. k-slot
+// l / 16 of step q is k = 4 (l / 16) + q.  The sum over k is the same whatever
+// slot holds which k, so no operand has to be rearranged through LDS.
+namespace {
+
+constexpr long kSkinnyChunk = 2048;
+
+template <int NX>
+__global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const double* __restrict__ X, long ldx,
+                                                          const double* __restrict__ Y, long ldy, long len,
+                                                          double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int t0 = blockIdx.x * 128 + wave * 32;
+  const long k0 = static_cast<long>(blockIdx.y) * kSkinnyChunk;
+  const long k1 = k0 + kSkinnyChunk < len ? k0 + kSkinnyChunk : len;
+  if (t0 >= nt) return;
+  // rows of this lane (clamped: rows past ns / nt feed outputs that are not stored)
+  const double* xr[NX];
+#pragma unroll
+  for (int a = 0; a < NX; ++a) xr[a] = X + static_cast<long>(min(16 * a + i, ns - 1)) * ldx;
+  const double* yr[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) yr[b] = Y + static_cast<long>(min(t0 + 16 * b + i, nt - 1)) * ldy;
+  d4 acc[NX][2];
+#pragma unroll
+  for (int a = 0; a < NX; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+  // blocks of 16 k-values; the loads of block + 1 are issued before the MFMAs
+  // of the current block (past the last full block they repeat it)
+  const long nfull = (k1 - k0) / 16;
+  auto load = [&](long blk, d2 (*xv)[2], d2 (*yv)[2]) {
+    const long kk = k0 + 16 * blk + 4 * g;
+#pragma unroll
+    for (int a = 0; a < NX; ++a) {
+      xv[a][0] = *reinterpret_cast<const d2*>(xr[a] + kk);
+      xv[a][1] = *reinterpret_cast<const d2*>(xr[a] + kk + 2);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      yv[b][0] = *reinterpret_cast<const d2*>(yr[b] + kk);
+      yv[b][1] = *reinterpret_cast<const d2*>(yr[b] + kk + 2);
+    }
+  };
+  auto mma = [&](d2 (*xv)[2], d2 (*yv)[2]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const double xa = q < 2 ? xv[a][0][q] : xv[a][1][q - 2];
+          const double yb = q < 2 ? yv[b][0][q] : yv[b][1][q - 2];
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, acc[a][b], 0, 0, 0);
+        }
+  };
+  if (nfull > 0) {
+    d2 xa0[NX][2], ya0[2][2], xa1[NX][2], ya1[2][2];
+    load(0, xa0, ya0);
+    long blk = 0;
+    for (; blk + 1 < nfull; blk += 2) {
+      load(blk + 1, xa1, ya1);
+      mma(xa0, ya0);
+      load(min(blk + 2, nfull - 1), xa0, ya0);
+      mma(xa1, ya1);
+    }
+    if (blk < nfull) mma(xa0, ya0);
+  }
+  long k = k0 + 16 * nfull;
+  if (k < k1) {  // ragged end of the last chunk: element loads, zero past len
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long kk = k + 4 * g + q;
+      const bool in = kk < k1;
+#pragma unroll
+      for (int a = 0; a < NX; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? xr[a][kk] : 0.0, in ? yr[b][kk] : 0.0, acc[a][b], 0,
+                                                           0, 0);
+    }
+  }
+  double* out = part + static_cast<long>(blockIdx.y) * ns * nt;
+#pragma unroll
+  for (int a = 0; a < NX; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = 16 * a + (lane >> 4) + 4 * r, t = t0 + 16 * b + (lane & 15);
+        if (s < ns && t < nt) out[static_cast<long>(s) * nt + t] = acc[a][b][r];
+      }
+}
+
+}  // namespace
+
 size_t dots_workspace(int ns, int nt, long len) {
   const long nchunks = (len + kDotChunk - 1) / kDotChunk;
   return static_cast<size_t>(nchunks) * ns * nt;
@@ -610,6 +713,23 @@ size_t dots_workspace(int ns, int nt, long len) {
 void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len, double* out,
           long ldo, double* ws) {
   if (ns <= 0 || nt <= 0) return;
+  if (ns <= 48 && len >= 4 * kSkinnyChunk && ((ldx | ldy) & 1) == 0 && aligned_to(X, 16) && aligned_to(Y, 16)) {
+    const int nchunks = static_cast<int>((len + kSkinnyChunk - 1) / kSkinnyChunk);
+    const dim3 grid(ceil_div(nt, 128), nchunks);
+    if (ns <= 16)
+      hipLaunchKernelGGL(skinny_dots_kernel<1>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, ws);
+    else if (ns <= 32)
+      hipLaunchKernelGGL(skinny_dots_kernel<2>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, ws);
+    else
+      hipLaunchKernelGGL(skinny_dots_kernel<3>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, ws);
+    if (ns * nt < 1024 && nchunks >= 64)
+      hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
+    else
+      hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 256)), dim3(256), 0, st, nchunks, ns, nt, ws,
+                         out, ldo);
+    SEQX_LAUNCH_CHECK();
+    return;
+  }
   const int nchunks = static_cast<int>((len + kDotChunk - 1) / kDotChunk);
   // chunk c: partial[c] (ns x nt) = X[:, chunk] * Y[:, chunk]^T ; the last chunk is ragged
   const int full = static_cast<int>(len / kDotChunk);
