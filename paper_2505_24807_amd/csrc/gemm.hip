@@ -504,6 +504,86 @@ void launch_cfg(hipStream_t st, bool ta, bool tb, int M, int N, int K, double al
 
 bool aligned_to(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
+// Tall-skinny combinations on the FP64 matrix cores: C[m][x] = alpha sum_s
+// A[m][s] B[s][x] + beta C[m][x] for M <= 48 rows and long rows x (new
+// Davidson vectors as combinations of the basis).  A wavefront owns every row
+// and 64 columns (four 16-column tiles); B is read once, in 128-byte row
+// segments per tile; the operands of the next k-step are loaded before the
+// MFMAs of the current one.
+template <int NX>
+__global__ void __launch_bounds__(256) skinny_combine_kernel(int M, long N, int K, double alpha,
+                                                             const double* __restrict__ A, long lda,
+                                                             const double* __restrict__ B, long ldb, double beta,
+                                                             double* __restrict__ C, long ldc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const long x0 = (static_cast<long>(blockIdx.x) * 4 + wave) * 64;
+  if (x0 >= N) return;
+  long xc[4];  // this lane's column in each tile (clamped; columns past N are not stored)
+#pragma unroll
+  for (int b = 0; b < 4; ++b) xc[b] = min(x0 + 16 * b + i, N - 1);
+  const double* ar[NX];
+#pragma unroll
+  for (int a = 0; a < NX; ++a) ar[a] = A + static_cast<long>(min(16 * a + i, M - 1)) * lda;
+  d4 acc[NX][4];
+#pragma unroll
+  for (int a = 0; a < NX; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
+  const int nfull = K / 4;
+  auto load = [&](int step, double* av, double* bv) {
+    const int sk = 4 * step + g;
+#pragma unroll
+    for (int a = 0; a < NX; ++a) av[a] = ar[a][sk];
+    const double* brow = B + static_cast<long>(sk) * ldb;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = brow[xc[b]];
+  };
+  auto mma = [&](const double* av, const double* bv) {
+#pragma unroll
+    for (int a = 0; a < NX; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  };
+  if (nfull > 0) {
+    double a0[NX], b0[4], a1[NX], b1[4];
+    load(0, a0, b0);
+    int st = 0;
+    for (; st + 1 < nfull; st += 2) {
+      load(st + 1, a1, b1);
+      mma(a0, b0);
+      load(min(st + 2, nfull - 1), a0, b0);
+      mma(a1, b1);
+    }
+    if (st < nfull) mma(a0, b0);
+  }
+  if (4 * nfull < K) {  // k tail: slots past K are zero
+    const int sk = 4 * nfull + g;
+    const bool in = sk < K;
+    double av[NX], bv[4];
+#pragma unroll
+    for (int a = 0; a < NX; ++a) av[a] = in ? ar[a][sk] : 0.0;
+    const double* brow = B + static_cast<long>(in ? sk : 0) * ldb;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = in ? brow[xc[b]] : 0.0;
+    mma(av, bv);
+  }
+#pragma unroll
+  for (int a = 0; a < NX; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = 16 * a + g + 4 * r;
+        const long x = x0 + 16 * b + i;
+        if (m < M && x < N) {
+          double* cp = C + static_cast<long>(m) * ldc + x;
+          const double v = alpha * acc[a][b][r];
+          *cp = beta == 0.0 ? v : v + beta * *cp;
+        }
+      }
+}
+
 template <class T, class To>
 void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const T* A, long lda, long sA,
               const T* B, long ldb, long sB, double beta, To* C, long ldc, long sC, int batch,
@@ -519,6 +599,22 @@ void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   }
   SigmaEpilogue ep;
   if (epi) ep = *epi;
+  if constexpr (sizeof(T) == 8 && sizeof(To) == 8) {
+    if (!ta && !tb && !epi && batch == 1 && M <= 48 && N >= 4096) {
+      const dim3 grid(static_cast<unsigned>((N + 255) / 256));
+      if (M <= 16)
+        hipLaunchKernelGGL(skinny_combine_kernel<1>, grid, dim3(256), 0, st, M, static_cast<long>(N), K, alpha, A, lda,
+                           B, ldb, beta, C, ldc);
+      else if (M <= 32)
+        hipLaunchKernelGGL(skinny_combine_kernel<2>, grid, dim3(256), 0, st, M, static_cast<long>(N), K, alpha, A, lda,
+                           B, ldb, beta, C, ldc);
+      else
+        hipLaunchKernelGGL(skinny_combine_kernel<3>, grid, dim3(256), 0, st, M, static_cast<long>(N), K, alpha, A, lda,
+                           B, ldb, beta, C, ldc);
+      SEQX_LAUNCH_CHECK();
+      return;
+    }
+  }
   const bool skinny = N <= 16;
   const bool even = ((lda | ldb | sA | sB) & 1) == 0 && aligned_to(A, 2 * sizeof(T)) && aligned_to(B, 2 * sizeof(T));
   // the 128 x 128 tiles address each operand with 32-bit byte offsets from a
