@@ -309,8 +309,10 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
     if args.calibrate_copy_mib > 0:
-        x = torch.ones(args.calibrate_copy_mib * 2 ** 18, device="cuda", dtype=torch.float32)
+        # random (incompressible) values: constant data reads back as far fewer fetched bytes
+        x = torch.rand(args.calibrate_copy_mib * 2 ** 18, device="cuda", dtype=torch.float32)
         y = torch.empty_like(x)
+        torch.cuda.synchronize()
         torch.neg(x, out=y)  # reads and writes calibrate_copy_mib MiB each
         torch.cuda.synchronize()
         del x, y
