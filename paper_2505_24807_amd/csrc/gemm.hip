@@ -701,25 +701,25 @@ void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
 // Tall-skinny inner products on the FP64 matrix cores: partial[c][s][t] =
 // sum over k in chunk c of X[s][k] Y[t][k], for ns <= 48 rows of X and any
 // number of rows of Y (the Davidson basis).  A workgroup takes every row of X
-// and 128 rows of Y (32 per wavefront) over one chunk of kSkinnyChunk, so Y
-// is read once.  Within each block of 16 k-values lane l loads the 4
+// and 128 rows of Y (32 per wavefront) over one chunk of k (a multiple of 16,
+// chosen so that the grid holds about a thousand workgroups), so Y is read
+// once.  Within each block of 16 k-values lane l loads the 4
 // contiguous values 4 (l / 16) .. +3 of its rows (row l % 16 of each 16-row
 // tile) as two 16-byte loads; MFMA step q then takes value q, i.e. k-slot
 // l / 16 of step q is k = 4 (l / 16) + q.  The sum over k is the same whatever
 // slot holds which k, so no operand has to be rearranged through LDS.
 namespace {
 
-constexpr long kSkinnyChunk = 2048;
 
 template <int NX>
 __global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const double* __restrict__ X, long ldx,
                                                           const double* __restrict__ Y, long ldy, long len,
-                                                          double* __restrict__ part) {
+                                                          long chunk, double* __restrict__ part) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int t0 = blockIdx.x * 128 + wave * 32;
-  const long k0 = static_cast<long>(blockIdx.y) * kSkinnyChunk;
-  const long k1 = k0 + kSkinnyChunk < len ? k0 + kSkinnyChunk : len;
+  const long k0 = static_cast<long>(blockIdx.y) * chunk;
+  const long k1 = k0 + chunk < len ? k0 + chunk : len;
   if (t0 >= nt) return;
   // rows of this lane (clamped: rows past ns / nt feed outputs that are not stored)
   const double* xr[NX];
@@ -801,23 +801,36 @@ __global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const 
 
 }  // namespace
 
+// chunk length of the tall-skinny path: about 1024 workgroups, at least 256
+long skinny_chunk(int nt, long len) {
+  const long groups = (nt + 127) / 128;
+  const long want = std::max<long>(1, 1024 / groups);
+  long chunk = (len + want - 1) / want;
+  chunk = (chunk + 15) / 16 * 16;
+  return std::max<long>(chunk, 256);
+}
+
+// Partial sums of either path.  The tall-skinny path makes at most
+// min(1024, len / 256) chunks whatever nt is, so the count is monotone in ns
+// and nt: a workspace sized for the largest shape serves every smaller one.
 size_t dots_workspace(int ns, int nt, long len) {
-  const long nchunks = (len + kDotChunk - 1) / kDotChunk;
+  const long nchunks = std::max((len + kDotChunk - 1) / kDotChunk, std::min<long>(1024, (len + 255) / 256));
   return static_cast<size_t>(nchunks) * ns * nt;
 }
 
 void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len, double* out,
           long ldo, double* ws) {
   if (ns <= 0 || nt <= 0) return;
-  if (ns <= 48 && len >= 4 * kSkinnyChunk && ((ldx | ldy) & 1) == 0 && aligned_to(X, 16) && aligned_to(Y, 16)) {
-    const int nchunks = static_cast<int>((len + kSkinnyChunk - 1) / kSkinnyChunk);
+  if (ns <= 48 && len >= 1024 && ((ldx | ldy) & 1) == 0 && aligned_to(X, 16) && aligned_to(Y, 16)) {
+    const long chunk = skinny_chunk(nt, len);
+    const int nchunks = static_cast<int>((len + chunk - 1) / chunk);
     const dim3 grid(ceil_div(nt, 128), nchunks);
     if (ns <= 16)
-      hipLaunchKernelGGL(skinny_dots_kernel<1>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, ws);
+      hipLaunchKernelGGL(skinny_dots_kernel<1>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
     else if (ns <= 32)
-      hipLaunchKernelGGL(skinny_dots_kernel<2>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, ws);
+      hipLaunchKernelGGL(skinny_dots_kernel<2>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
     else
-      hipLaunchKernelGGL(skinny_dots_kernel<3>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, ws);
+      hipLaunchKernelGGL(skinny_dots_kernel<3>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
     if (ns * nt < 1024 && nchunks >= 64)
       hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
     else
