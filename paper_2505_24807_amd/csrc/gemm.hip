@@ -504,86 +504,6 @@ void launch_cfg(hipStream_t st, bool ta, bool tb, int M, int N, int K, double al
 
 bool aligned_to(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
-// Tall-skinny combinations on the FP64 matrix cores: C[m][x] = alpha sum_s
-// A[m][s] B[s][x] + beta C[m][x] for M <= 48 rows and long rows x (new
-// Davidson vectors as combinations of the basis).  A wavefront owns every row
-// and 64 columns (four 16-column tiles); B is read once, in 128-byte row
-// segments per tile; the operands of the next k-step are loaded before the
-// MFMAs of the current one.
-template <int NX>
-__global__ void __launch_bounds__(256) skinny_combine_kernel(int M, long N, int K, double alpha,
-                                                             const double* __restrict__ A, long lda,
-                                                             const double* __restrict__ B, long ldb, double beta,
-                                                             double* __restrict__ C, long ldc) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = lane & 15, g = lane >> 4;
-  const long x0 = (static_cast<long>(blockIdx.x) * 4 + wave) * 64;
-  if (x0 >= N) return;
-  long xc[4];  // this lane's column in each tile (clamped; columns past N are not stored)
-#pragma unroll
-  for (int b = 0; b < 4; ++b) xc[b] = min(x0 + 16 * b + i, N - 1);
-  const double* ar[NX];
-#pragma unroll
-  for (int a = 0; a < NX; ++a) ar[a] = A + static_cast<long>(min(16 * a + i, M - 1)) * lda;
-  d4 acc[NX][4];
-#pragma unroll
-  for (int a = 0; a < NX; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  const int nfull = K / 4;
-  auto load = [&](int step, double* av, double* bv) {
-    const int sk = 4 * step + g;
-#pragma unroll
-    for (int a = 0; a < NX; ++a) av[a] = ar[a][sk];
-    const double* brow = B + static_cast<long>(sk) * ldb;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = brow[xc[b]];
-  };
-  auto mma = [&](const double* av, const double* bv) {
-#pragma unroll
-    for (int a = 0; a < NX; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-  };
-  if (nfull > 0) {
-    double a0[NX], b0[4], a1[NX], b1[4];
-    load(0, a0, b0);
-    int st = 0;
-    for (; st + 1 < nfull; st += 2) {
-      load(st + 1, a1, b1);
-      mma(a0, b0);
-      load(min(st + 2, nfull - 1), a0, b0);
-      mma(a1, b1);
-    }
-    if (st < nfull) mma(a0, b0);
-  }
-  if (4 * nfull < K) {  // k tail: slots past K are zero
-    const int sk = 4 * nfull + g;
-    const bool in = sk < K;
-    double av[NX], bv[4];
-#pragma unroll
-    for (int a = 0; a < NX; ++a) av[a] = in ? ar[a][sk] : 0.0;
-    const double* brow = B + static_cast<long>(in ? sk : 0) * ldb;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = in ? brow[xc[b]] : 0.0;
-    mma(av, bv);
-  }
-#pragma unroll
-  for (int a = 0; a < NX; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = 16 * a + g + 4 * r;
-        const long x = x0 + 16 * b + i;
-        if (m < M && x < N) {
-          double* cp = C + static_cast<long>(m) * ldc + x;
-          const double v = alpha * acc[a][b][r];
-          *cp = beta == 0.0 ? v : v + beta * *cp;
-        }
-      }
-}
-
 template <class T, class To>
 void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const T* A, long lda, long sA,
               const T* B, long ldb, long sB, double beta, To* C, long ldc, long sC, int batch,
@@ -601,17 +521,7 @@ void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   if (epi) ep = *epi;
   if constexpr (sizeof(T) == 8 && sizeof(To) == 8) {
     if (!ta && !tb && !epi && batch == 1 && M <= 48 && N >= 4096) {
-      const dim3 grid(static_cast<unsigned>((N + 255) / 256));
-      if (M <= 16)
-        hipLaunchKernelGGL(skinny_combine_kernel<1>, grid, dim3(256), 0, st, M, static_cast<long>(N), K, alpha, A, lda,
-                           B, ldb, beta, C, ldc);
-      else if (M <= 32)
-        hipLaunchKernelGGL(skinny_combine_kernel<2>, grid, dim3(256), 0, st, M, static_cast<long>(N), K, alpha, A, lda,
-                           B, ldb, beta, C, ldc);
-      else
-        hipLaunchKernelGGL(skinny_combine_kernel<3>, grid, dim3(256), 0, st, M, static_cast<long>(N), K, alpha, A, lda,
-                           B, ldb, beta, C, ldc);
-      SEQX_LAUNCH_CHECK();
+      skinny_combine(st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
       return;
     }
   }
@@ -641,38 +551,6 @@ void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   SEQX_LAUNCH_CHECK();
 }
 
-__global__ void reduce_partials_kernel(int nchunks, int ns, int nt, const double* __restrict__ part, double* out,
-                                       long ldo) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ns * nt) return;
-  const int s = idx / nt, t = idx % nt;
-  double acc = 0.0;
-  for (int c = 0; c < nchunks; ++c) acc += part[static_cast<long>(c) * ns * nt + idx];
-  out[static_cast<long>(s) * ldo + t] = acc;
-}
-
-// few outputs, many chunks: one workgroup per output, fixed-order tree
-__global__ void __launch_bounds__(256) reduce_partials_wide_kernel(int nchunks, int ns, int nt,
-                                                                   const double* __restrict__ part, double* out,
-                                                                   long ldo) {
-  __shared__ double red[256];
-  const int idx = blockIdx.x;
-  const long stride = static_cast<long>(ns) * nt;
-  double acc = 0.0;
-  for (int c = threadIdx.x; c < nchunks; c += 256) acc += part[c * stride + idx];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[static_cast<long>(idx / nt) * ldo + idx % nt] = red[0];
-}
-
-// split-K chunk of the inner products: short enough that a basis of a few
-// hundred vectors still spreads over thousands of workgroups
-constexpr long kDotChunk = 1024;
-
 }  // namespace
 
 void dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda, long sA,
@@ -696,166 +574,6 @@ void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
               const double* B, long ldb, double beta, double* C, long ldc) {
   // column-major C = op(A) op(B) is row-major C^T = op(B)^T op(A)^T
   dgemm(st, tb, ta, N, M, K, alpha, B, ldb, 0, A, lda, 0, beta, C, ldc, 0, 1, nullptr);
-}
-
-// Tall-skinny inner products on the FP64 matrix cores: partial[c][s][t] =
-// sum over k in chunk c of X[s][k] Y[t][k], for ns <= 48 rows of X and any
-// number of rows of Y (the Davidson basis).  A workgroup takes every row of X
-// and 128 rows of Y (32 per wavefront) over one chunk of k (a multiple of 16,
-// chosen so that the grid holds about a thousand workgroups), so Y is read
-// once.  Within each block of 16 k-values lane l loads the 4
-// contiguous values 4 (l / 16) .. +3 of its rows (row l % 16 of each 16-row
-// tile) as two 16-byte loads; MFMA step q then takes value q, i.e. k-slot
-// l / 16 of step q is k = 4 (l / 16) + q.  The sum over k is the same whatever
-// slot holds which k, so no operand has to be rearranged through LDS.
-namespace {
-
-
-template <int NX>
-__global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const double* __restrict__ X, long ldx,
-                                                          const double* __restrict__ Y, long ldy, long len,
-                                                          long chunk, double* __restrict__ part) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = lane & 15, g = lane >> 4;
-  const int t0 = blockIdx.x * 128 + wave * 32;
-  const long k0 = static_cast<long>(blockIdx.y) * chunk;
-  const long k1 = k0 + chunk < len ? k0 + chunk : len;
-  if (t0 >= nt) return;
-  // rows of this lane (clamped: rows past ns / nt feed outputs that are not stored)
-  const double* xr[NX];
-#pragma unroll
-  for (int a = 0; a < NX; ++a) xr[a] = X + static_cast<long>(min(16 * a + i, ns - 1)) * ldx;
-  const double* yr[2];
-#pragma unroll
-  for (int b = 0; b < 2; ++b) yr[b] = Y + static_cast<long>(min(t0 + 16 * b + i, nt - 1)) * ldy;
-  d4 acc[NX][2];
-#pragma unroll
-  for (int a = 0; a < NX; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  // blocks of 16 k-values; the loads of block + 1 are issued before the MFMAs
-  // of the current block (past the last full block they repeat it)
-  const long nfull = (k1 - k0) / 16;
-  auto load = [&](long blk, d2 (*xv)[2], d2 (*yv)[2]) {
-    const long kk = k0 + 16 * blk + 4 * g;
-#pragma unroll
-    for (int a = 0; a < NX; ++a) {
-      xv[a][0] = *reinterpret_cast<const d2*>(xr[a] + kk);
-      xv[a][1] = *reinterpret_cast<const d2*>(xr[a] + kk + 2);
-    }
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      yv[b][0] = *reinterpret_cast<const d2*>(yr[b] + kk);
-      yv[b][1] = *reinterpret_cast<const d2*>(yr[b] + kk + 2);
-    }
-  };
-  auto mma = [&](d2 (*xv)[2], d2 (*yv)[2]) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int a = 0; a < NX; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const double xa = q < 2 ? xv[a][0][q] : xv[a][1][q - 2];
-          const double yb = q < 2 ? yv[b][0][q] : yv[b][1][q - 2];
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, acc[a][b], 0, 0, 0);
-        }
-  };
-  if (nfull > 0) {
-    d2 xa0[NX][2], ya0[2][2], xa1[NX][2], ya1[2][2];
-    load(0, xa0, ya0);
-    long blk = 0;
-    for (; blk + 1 < nfull; blk += 2) {
-      load(blk + 1, xa1, ya1);
-      mma(xa0, ya0);
-      load(min(blk + 2, nfull - 1), xa0, ya0);
-      mma(xa1, ya1);
-    }
-    if (blk < nfull) mma(xa0, ya0);
-  }
-  long k = k0 + 16 * nfull;
-  if (k < k1) {  // ragged end of the last chunk: element loads, zero past len
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long kk = k + 4 * g + q;
-      const bool in = kk < k1;
-#pragma unroll
-      for (int a = 0; a < NX; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? xr[a][kk] : 0.0, in ? yr[b][kk] : 0.0, acc[a][b], 0,
-                                                           0, 0);
-    }
-  }
-  double* out = part + static_cast<long>(blockIdx.y) * ns * nt;
-#pragma unroll
-  for (int a = 0; a < NX; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int s = 16 * a + (lane >> 4) + 4 * r, t = t0 + 16 * b + (lane & 15);
-        if (s < ns && t < nt) out[static_cast<long>(s) * nt + t] = acc[a][b][r];
-      }
-}
-
-}  // namespace
-
-// chunk length of the tall-skinny path: about 1024 workgroups, at least 256
-long skinny_chunk(int nt, long len) {
-  const long groups = (nt + 127) / 128;
-  const long want = std::max<long>(1, 1024 / groups);
-  long chunk = (len + want - 1) / want;
-  chunk = (chunk + 15) / 16 * 16;
-  return std::max<long>(chunk, 256);
-}
-
-// Partial sums of either path.  The tall-skinny path makes at most
-// min(1024, len / 256) chunks whatever nt is, so the count is monotone in ns
-// and nt: a workspace sized for the largest shape serves every smaller one.
-size_t dots_workspace(int ns, int nt, long len) {
-  const long nchunks = std::max((len + kDotChunk - 1) / kDotChunk, std::min<long>(1024, (len + 255) / 256));
-  return static_cast<size_t>(nchunks) * ns * nt;
-}
-
-void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len, double* out,
-          long ldo, double* ws) {
-  if (ns <= 0 || nt <= 0) return;
-  if (ns <= 48 && len >= 1024 && ((ldx | ldy) & 1) == 0 && aligned_to(X, 16) && aligned_to(Y, 16)) {
-    const long chunk = skinny_chunk(nt, len);
-    const int nchunks = static_cast<int>((len + chunk - 1) / chunk);
-    const dim3 grid(ceil_div(nt, 128), nchunks);
-    if (ns <= 16)
-      hipLaunchKernelGGL(skinny_dots_kernel<1>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
-    else if (ns <= 32)
-      hipLaunchKernelGGL(skinny_dots_kernel<2>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
-    else
-      hipLaunchKernelGGL(skinny_dots_kernel<3>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
-    if (ns * nt < 1024 && nchunks >= 64)
-      hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
-    else
-      hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 256)), dim3(256), 0, st, nchunks, ns, nt, ws,
-                         out, ldo);
-    SEQX_LAUNCH_CHECK();
-    return;
-  }
-  const int nchunks = static_cast<int>((len + kDotChunk - 1) / kDotChunk);
-  // chunk c: partial[c] (ns x nt) = X[:, chunk] * Y[:, chunk]^T ; the last chunk is ragged
-  const int full = static_cast<int>(len / kDotChunk);
-  if (full > 0)
-    dgemm(st, false, true, ns, nt, static_cast<int>(kDotChunk), 1.0, X, ldx, kDotChunk, Y, ldy, kDotChunk, 0.0, ws,
-          nt, static_cast<long>(ns) * nt, full, nullptr);
-  if (full < nchunks) {
-    const long off = static_cast<long>(full) * kDotChunk;
-    dgemm(st, false, true, ns, nt, static_cast<int>(len - off), 1.0, X + off, ldx, 0, Y + off, ldy, 0, 0.0,
-          ws + static_cast<long>(full) * ns * nt, nt, 0, 1, nullptr);
-  }
-  if (ns * nt < 1024 && nchunks >= 64)
-    hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
-  else
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 256)), dim3(256), 0, st, nchunks, ns, nt, ws,
-                       out, ldo);
-  SEQX_LAUNCH_CHECK();
 }
 
 }  // namespace seqx

@@ -37,6 +37,11 @@ void sgemm_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double a
 void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,
               const double* B, long ldb, double beta, double* C, long ldc);
 
+// C[m][x] = alpha sum_s A[m][s] B[s][x] + beta C[m][x] for M <= 48 rows
+// (row-major, leading dimensions lda, ldb, ldc); beta = 0 does not read C.
+void skinny_combine(hipStream_t st, int M, long N, int K, double alpha, const double* A, long lda, const double* B,
+                    long ldb, double beta, double* C, long ldc);
+
 // Split-K inner products out[s*ldo + t] = sum_x X[s*ldx + x] * Y[t*ldy + x]
 // for s < ns, t < nt, over x < len; fixed-order reduction (deterministic).
 // ws must hold dots_workspace(ns, nt, len) doubles.
