@@ -23,6 +23,7 @@
 #include <cstdlib>
 
 #include "batch.hpp"
+#include "wave.hpp"
 #include "fock_blocks.hpp"
 #include "jacobi.hpp"
 #include "linalg.hpp"
@@ -130,15 +131,19 @@ __device__ void sigma_item(const MolDesc& md, const T* __restrict__ C, const dou
     rs[P] = (mu == nu) ? a : a + b;
   }
   __syncthreads();
-  {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int P = wave; P < np; P += 4) {
-      const double* Wr = md.W + static_cast<long>(P) * np;
-      double s = 0.0;
-      for (int Q = lane; Q < np; Q += 64) s += Wr[Q] * rs[Q];
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-      if (lane == 0) js[P] = s;
+  // J[P] = sum_Q W[Q][P] r[Q] (W symmetric): thread P walks column P, so each
+  // step reads one row of W coalesced and no cross-lane sum is needed
+  for (int P0 = 0; P0 < np; P0 += blockDim.x) {
+    const int P = P0 + threadIdx.x;
+    const double* Wc = md.W + min(P, np - 1);
+    double s0 = 0.0, s1 = 0.0;
+    int Q = 0;
+    for (; Q + 2 <= np; Q += 2) {
+      s0 += Wc[static_cast<long>(Q) * np] * rs[Q];
+      s1 += Wc[static_cast<long>(Q + 1) * np] * rs[Q + 1];
     }
+    if (Q < np) s0 += Wc[static_cast<long>(Q) * np] * rs[Q];
+    if (P < np) js[P] = s0 + s1;
   }
   __syncthreads();
   // F = 2 J(R) - K(R): atom-diagonal blocks, then every atom pair (both orders)
@@ -221,20 +226,14 @@ __global__ void __launch_bounds__(256) stamp_span_kernel(int G, const long long*
 
 // ---------------------------------------------------------------- subspace kernels
 
-__device__ __forceinline__ double wave_sum(double s) {
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  return s;
-}
+__device__ __forceinline__ double wave_sum(double s) { return wave_sum64(s); }
 
 // fixed-order block sum over 256 threads (result valid in every thread)
-__device__ double block_sum(double s, double* red) {
-  red[threadIdx.x] = s;
+__device__ double block_sum(double s, double* red) {  // 256 threads; fixed order
+  s = wave_sum64(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double r = red[0];
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
   __syncthreads();
   return r;
 }
@@ -243,7 +242,7 @@ __device__ double block_sum(double s, double* red) {
 // (ties by flat index i*v + a), found by ng rounds of lexicographic minimum.
 __global__ void __launch_bounds__(256) guess_kernel(int nmol, const MolDesc* __restrict__ mols, int K,
                                                     double* __restrict__ Vp, int* S, int* knew, int* active, int* conv,
-                                                    int* coll, int* qcol) {
+                                                    int* coll, int* qcol, int* evn) {
   __shared__ double bg[256];
   __shared__ long bi[256];
   const int m = blockIdx.x;
@@ -292,6 +291,7 @@ __global__ void __launch_bounds__(256) guess_kernel(int nmol, const MolDesc* __r
     conv[m] = 0;
     coll[m] = 0;
     qcol[m] = 0;
+    evn[m] = 0;
   }
 }
 
@@ -376,29 +376,82 @@ __global__ void advance_kernel(int nmol, int* S, const int* __restrict__ knew, c
 
 // Symmetric eigensolve of the S x S projected matrix of each molecule
 // (Jacobi in LDS, jacobi.hpp).  Eigenvalues ascending in eval, eigenvectors
-// as columns of evec (ld Smax).
+// as columns of evec (ld Smax).  Warm start: the leading evn x evn block of M
+// is unchanged since the last eigensolve, whose eigenvectors are still in
+// evec, so M is first rotated into that basis (extended by the identity for
+// the new columns) and Jacobi continues from the nearly diagonal result,
+// accumulating onto the same basis.
 constexpr int kEigThreads = 256;  // measured faster than one wavefront per molecule
 
 __global__ void __launch_bounds__(kEigThreads) eig_kernel(int Smax, const double* __restrict__ Mp,
                                                           const int* __restrict__ S, const int* __restrict__ active,
-                                                          double* __restrict__ evec, double* __restrict__ eval) {
+                                                          int* __restrict__ evn, double* __restrict__ evec,
+                                                          double* __restrict__ eval) {
   __shared__ JacobiLds L;
   const int m = blockIdx.x;
   if (!active[m]) return;
   const int n = S[m];
+  const int p = min(evn[m], n);
   const double* M = Mp + static_cast<long>(m) * Smax * Smax;
+  double* ev = evec + static_cast<long>(m) * Smax * Smax;
+  constexpr int kPer = (kJacobiMax * kJacobiMax + kEigThreads - 1) / kEigThreads;
   for (int idx = threadIdx.x; idx < n * n; idx += kEigThreads) {
     const int i = idx / n, j = idx % n;
     L.A[i][j] = M[i + static_cast<long>(j) * Smax];
+    L.Q[i][j] = (i < p && j < p) ? ev[i + static_cast<long>(j) * Smax] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  jacobi_lds<kEigThreads>(n, L);
-  double* ev = evec + static_cast<long>(m) * Smax * Smax;
+  if (p > 0) {
+    // T = M Q (only the first p columns change), then A = Q^T T (only the first p rows change)
+    double t[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = threadIdx.x + kEigThreads * e;
+      t[e] = 0.0;
+      if (idx < n * n) {
+        const int i = idx / n, j = idx % n;
+        if (j < p) {
+          for (int k = 0; k < p; ++k) t[e] += L.A[i][k] * L.Q[k][j];
+        } else {
+          t[e] = L.A[i][j];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = threadIdx.x + kEigThreads * e;
+      if (idx < n * n) L.A[idx / n][idx % n] = t[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = threadIdx.x + kEigThreads * e;
+      t[e] = 0.0;
+      if (idx < n * n) {
+        const int i = idx / n, j = idx % n;
+        if (i < p) {
+          for (int k = 0; k < p; ++k) t[e] += L.Q[k][i] * L.A[k][j];
+        } else {
+          t[e] = L.A[i][j];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = threadIdx.x + kEigThreads * e;
+      if (idx < n * n) L.A[idx / n][idx % n] = t[e];
+    }
+    __syncthreads();
+  }
+  jacobi_lds<kEigThreads>(n, L, true);
   for (int idx = threadIdx.x; idx < n * n; idx += kEigThreads) {
     const int r = idx / n, i = idx % n;
     ev[i + static_cast<long>(r) * Smax] = L.Q[i][L.perm[r]];
   }
   for (int r = threadIdx.x; r < n; r += kEigThreads) eval[static_cast<long>(m) * Smax + r] = L.A[L.perm[r]][L.perm[r]];
+  if (threadIdx.x == 0) evn[m] = n;
 }
 
 // Ritz vector j of molecule m, its residual r = A x - w x and norm; for an
@@ -514,7 +567,8 @@ __global__ void __launch_bounds__(256) collapse_copy_kernel(const MolDesc* __res
                                                             const double* __restrict__ TAVp,
                                                             const double* __restrict__ eval, int* S, int* coll,
                                                             const int* __restrict__ qcol, double* __restrict__ Vp,
-                                                            double* __restrict__ AVp, double* __restrict__ Mp) {
+                                                            double* __restrict__ AVp, double* __restrict__ Mp,
+                                                            int* __restrict__ evn) {
   const int m = blockIdx.x, s = blockIdx.y;
   if (!coll[m]) return;
   const int q = qcol[m];
@@ -526,7 +580,8 @@ __global__ void __launch_bounds__(256) collapse_copy_kernel(const MolDesc* __res
       Vp[md.vbase + s * nov + x] = TVp[md.tbase + s * nov + x];
       AVp[md.vbase + s * nov + x] = TAVp[md.tbase + s * nov + x];
     }
-  } else {  // block s == q: the projected matrix
+  } else {  // block s == q: the projected matrix (diagonal: no previous eigenvectors to start from)
+    if (threadIdx.x == 0) evn[m] = 0;
     double* M = Mp + static_cast<long>(m) * Smax * Smax;
     for (int idx = threadIdx.x; idx < q * q; idx += 256) {
       const int i = idx / q, j = idx % q;
@@ -715,7 +770,7 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
 
   w.mols.ensure(nmol);
   w.order.ensure(nmol);
-  for (DBuf<int>* b : {&w.S, &w.knew, &w.active, &w.coll, &w.qcol, &w.conv}) b->ensure(nmol);
+  for (DBuf<int>* b : {&w.S, &w.knew, &w.active, &w.coll, &w.qcol, &w.conv, &w.evn}) b->ensure(nmol);
   w.unc.ensure(static_cast<size_t>(nmol) * K);
   w.counters.ensure(4);
   w.nsig.ensure(3);
@@ -774,7 +829,7 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
     for (int m = 0; m < nmol; ++m) bucket[m] = bucket_of(h[m].n);
     upload_desc();
     hipLaunchKernelGGL(guess_kernel, dim3(nmol), dim3(256), 0, st, nmol, w.mols.p, K, w.V.p, w.S.p, w.knew.p,
-                       w.active.p, w.conv.p, w.coll.p, w.qcol.p);
+                       w.active.p, w.conv.p, w.coll.p, w.qcol.p, w.evn.p);
     SEQX_LAUNCH_CHECK();
     const auto ta0 = std::chrono::steady_clock::now();
     for (int b = 0; b < kNumSizeBuckets; ++b) {
@@ -831,7 +886,7 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
       hipLaunchKernelGGL(advance_kernel, dim3(ceil_div(nmol, 256)), dim3(256), 0, st, nmol, w.S.p, w.knew.p,
                          w.active.p);
       hipLaunchKernelGGL(eig_kernel, dim3(nmol), dim3(kEigThreads), 0, st, Smax, w.Mp.p, w.S.p, w.active.p,
-                         w.evec.p, w.eval.p);
+                         w.evn.p, w.evec.p, w.eval.p);
       hipLaunchKernelGGL(ritz_kernel, dim3(nmol, K), dim3(256), 0, st, w.mols.p, K, Smax, opt.tol, w.V.p, w.AV.p,
                          w.evec.p, w.eval.p, w.S.p, w.active.p, w.X.p, w.Wc.p, w.omega.p, w.rnorm.p);
       hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, st, nmol, K, Smax, opt.tol, w.rnorm.p, w.S.p,
@@ -839,7 +894,7 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
       hipLaunchKernelGGL(collapse_kernel, dim3(nmol, Q), dim3(256), 0, st, w.mols.p, Smax, w.V.p, w.AV.p, w.evec.p,
                          w.S.p, w.coll.p, w.qcol.p, w.TV.p, w.TAV.p);
       hipLaunchKernelGGL(collapse_copy_kernel, dim3(nmol, Q + 1), dim3(256), 0, st, w.mols.p, Smax, w.TV.p, w.TAV.p,
-                         w.eval.p, w.S.p, w.coll.p, w.qcol.p, w.V.p, w.AV.p, w.Mp.p);
+                         w.eval.p, w.S.p, w.coll.p, w.qcol.p, w.V.p, w.AV.p, w.Mp.p, w.evn.p);
       hipLaunchKernelGGL(deflate_kernel, dim3(nmol, K), dim3(256), 0, st, w.mols.p, K, w.V.p, w.Wc.p, w.S.p,
                          w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.n0.p);
       hipLaunchKernelGGL(append_kernel, dim3(nmol), dim3(256), 0, st, w.mols.p, K, Smax, w.V.p, w.Wc.p, w.S.p,

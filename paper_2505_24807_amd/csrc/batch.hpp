@@ -74,6 +74,7 @@ struct BatchResult {
 struct BatchWork {
   DBuf<MolDesc> mols;
   DBuf<int> order, S, knew, active, coll, qcol, unc, conv, counters;
+  DBuf<int> evn;           // leading block of each molecule's M whose eigenvectors are in evec (0: none)
   DBuf<int2> items;
   DBuf<long long> nsig;    // [0] sigma vectors, [1] wall-clock ticks inside sigma launches, [2] flops
   DBuf<long long> stamps;  // start / end tick of each workgroup of the last sigma launch

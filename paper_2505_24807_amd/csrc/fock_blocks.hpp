@@ -100,11 +100,17 @@ __device__ __forceinline__ void diag_block(const Elem& e, int o, int po, const d
                                            const TR* __restrict__ Rv, int n, TF* __restrict__ f1,
                                            TF* __restrict__ f2, double cJ, double cK, double cKa) {
   const int na = e.nao;
-  double X[4][4];
-  for (int i = 0; i < na; ++i)
-    for (int j = 0; j < na; ++j) X[i][j] = static_cast<double>(Rv[static_cast<long>(o + i) * n + o + j]);
-  for (int m = 0; m < na; ++m)
-    for (int nn = 0; nn < na; ++nn) {
+  double X[4][4];  // statically indexed (unrolled, predicated) so that it stays in registers
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      X[i][j] = (i < na && j < na) ? static_cast<double>(Rv[static_cast<long>(o + i) * n + o + j]) : 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int nn = 0; nn < 4; ++nn) {
+      if (m >= na || nn >= na) continue;
       const double S = 0.5 * (X[m][nn] + X[nn][m]), Dv = 0.5 * (X[m][nn] - X[nn][m]);
       double kS, kD;
       if (na == 1) {
@@ -112,6 +118,7 @@ __device__ __forceinline__ void diag_block(const Elem& e, int o, int po, const d
         kD = 0.0;
       } else if (m == nn) {
         kS = g1(e, m, m) * X[m][m];
+#pragma unroll
         for (int l = 0; l < 4; ++l)
           if (l != m) kS += h1(e, m, l) * X[l][l];
         kD = 0.0;

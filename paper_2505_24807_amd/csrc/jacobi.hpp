@@ -7,6 +7,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "wave.hpp"
 
 namespace seqx {
 
@@ -18,14 +19,15 @@ struct JacobiLds {
   double c[kJacobiMax / 2], s[kJacobiMax / 2];
   int p[kJacobiMax / 2], q[kJacobiMax / 2];
   int perm[kJacobiMax];
+  int nact;  // stamp of the last round that rotated a pair
   double red[256];
 };
 
-// fixed-order sum over the NT threads (result in every thread): butterfly
+// fixed-order sum over the NT threads (result in every thread): DPP sum
 // within each wavefront, then the wavefront sums in order
 template <int NT>
 __device__ inline double jacobi_block_sum(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  v = wave_sum64(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double r = 0.0;
@@ -34,48 +36,56 @@ __device__ inline double jacobi_block_sum(double v, double* red) {
   return r;
 }
 
-// On entry L.A holds the symmetric n x n matrix (n <= kJacobiMax).  On exit
-// L.Q holds the eigenvectors as columns, diag(L.A) the eigenvalues, and
+// On entry L.A holds the symmetric n x n matrix (n <= kJacobiMax) and, with
+// q_given, L.Q an orthogonal matrix that the rotations accumulate onto
+// (otherwise the identity).  On exit L.Q holds the eigenvectors as columns, diag(L.A) the eigenvalues, and
 // L.perm the ascending order of the eigenvalues.  Sweeps stop when the
 // off-diagonal sum of squares is below 1e-28 of the total (elements ~1e-14 of
 // the largest; FP64 rounding keeps the sum near n * 1e-32 of the total) or
 // after 40 sweeps.
 template <int NT>
-__device__ inline void jacobi_lds(int n, JacobiLds& L) {
-  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
-    const int i = idx / n, j = idx % n;
-    L.Q[i][j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int ne = n + (n & 1), half = ne / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, tot = 0.0;
+__device__ inline void jacobi_lds(int n, JacobiLds& L, bool q_given = false) {
+  if (!q_given) {
     for (int idx = threadIdx.x; idx < n * n; idx += NT) {
       const int i = idx / n, j = idx % n;
-      const double a2 = L.A[i][j] * L.A[i][j];
-      tot += a2;
-      if (i != j) off += a2;
+      L.Q[i][j] = (i == j) ? 1.0 : 0.0;
     }
+    __syncthreads();
+  }
+  const int ne = n + (n & 1), half = ne / 2;
+  if (threadIdx.x == 0) L.nact = 0;  // seen by all after the first barrier of the sweep
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane < n)
+      for (int i = wv; i < n; i += NT / 64) {
+        const double a2 = L.A[i][lane] * L.A[i][lane];
+        tot += a2;
+        if (i != lane) off += a2;
+      }
     off = jacobi_block_sum<NT>(off, L.red);
     tot = jacobi_block_sum<NT>(tot, L.red);
     if (!(off > 1e-28 * tot)) break;
+    // pairs whose element is below this are left alone: together they stay
+    // two orders under the stopping bar (threshold Jacobi)
+    const double skip2 = 1e-30 * tot / (static_cast<double>(n) * n);
     for (int r = 0; r < ne - 1; ++r) {
+      const int stamp = sweep * ne + r + 1;  // unique per round: no reset needed
       if (threadIdx.x < half) {
         const int k = threadIdx.x;
         int p = k == 0 ? r % (ne - 1) : (r + k) % (ne - 1);
         int q = k == 0 ? ne - 1 : (r - k + ne - 1) % (ne - 1);
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
-        if (q < n) {
+        if (q < n && L.A[p][q] * L.A[p][q] > skip2) {
           const double apq = L.A[p][q];
-          if (apq != 0.0) {
-            const double th = (L.A[q][q] - L.A[p][p]) / (2.0 * apq);
-            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-          }
+          const double th = (L.A[q][q] - L.A[p][p]) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+          L.nact = stamp;  // benign race: every writer stores the same value
         } else {
-          q = -1;
+          q = p;  // identity rotation of row / column p onto itself (p is in no other pair)
         }
         L.p[k] = p;
         L.q[k] = q;
@@ -83,25 +93,54 @@ __device__ inline void jacobi_lds(int n, JacobiLds& L) {
         L.s[k] = s;
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < half * n; idx += NT) {  // rows p, q
-        const int k = idx / n, j = idx % n;
-        const int p = L.p[k], q = L.q[k];
-        if (q < 0) continue;
-        const double ap = L.A[p][j], aq = L.A[q][j];
-        L.A[p][j] = L.c[k] * ap - L.s[k] * aq;
-        L.A[q][j] = L.s[k] * ap + L.c[k] * aq;
+      if (L.nact != stamp) continue;  // uniform: nothing to rotate in this round
+      // The pairs of a round are disjoint, so each wavefront first reads the
+      // pair indices, rotations and operands of all its pairs, then writes:
+      // no read waits on an earlier write, and no access is predicated (a
+      // slot without a pair works on the spare LDS row kJacobiMax - 1, which
+      // exists only when n < kJacobiMax - 1, with the identity rotation).
+      constexpr int KW = (kJacobiMax / 2 + NT / 64 - 1) / (NT / 64);  // pairs per wavefront
+      int pk[KW], qk[KW];
+      double ck[KW], sk[KW];
+#pragma unroll
+      for (int j = 0; j < KW; ++j) {
+        const int k = wv + (NT / 64) * j;
+        const bool has = k < half;
+        pk[j] = has ? L.p[k] : kJacobiMax - 1;
+        qk[j] = has ? L.q[k] : kJacobiMax - 1;
+        ck[j] = has ? L.c[k] : 1.0;
+        sk[j] = has ? L.s[k] : 0.0;
+      }
+      if (lane < n) {  // rows p, q: lane = column
+        double ap[KW], aq[KW];
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+          ap[j] = L.A[pk[j]][lane];
+          aq[j] = L.A[qk[j]][lane];
+        }
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+          L.A[pk[j]][lane] = ck[j] * ap[j] - sk[j] * aq[j];
+          L.A[qk[j]][lane] = sk[j] * ap[j] + ck[j] * aq[j];
+        }
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < half * n; idx += NT) {  // columns p, q of A and Q
-        const int k = idx / n, i = idx % n;
-        const int p = L.p[k], q = L.q[k];
-        if (q < 0) continue;
-        const double ap = L.A[i][p], aq = L.A[i][q];
-        L.A[i][p] = L.c[k] * ap - L.s[k] * aq;
-        L.A[i][q] = L.s[k] * ap + L.c[k] * aq;
-        const double vp = L.Q[i][p], vq = L.Q[i][q];
-        L.Q[i][p] = L.c[k] * vp - L.s[k] * vq;
-        L.Q[i][q] = L.s[k] * vp + L.c[k] * vq;
+      if (lane < n) {  // columns p, q of A and Q: lane = row
+        double ap[KW], aq[KW], vp[KW], vq[KW];
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+          ap[j] = L.A[lane][pk[j]];
+          aq[j] = L.A[lane][qk[j]];
+          vp[j] = L.Q[lane][pk[j]];
+          vq[j] = L.Q[lane][qk[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < KW; ++j) {
+          L.A[lane][pk[j]] = ck[j] * ap[j] - sk[j] * aq[j];
+          L.A[lane][qk[j]] = sk[j] * ap[j] + ck[j] * aq[j];
+          L.Q[lane][pk[j]] = ck[j] * vp[j] - sk[j] * vq[j];
+          L.Q[lane][qk[j]] = sk[j] * vp[j] + ck[j] * vq[j];
+        }
       }
       __syncthreads();
     }

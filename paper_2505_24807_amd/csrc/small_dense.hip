@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "linalg.hpp"
+#include "wave.hpp"
 
 namespace seqx {
 
@@ -22,31 +23,6 @@ namespace {
 constexpr int kNT = 1024;
 constexpr int kNW = kNT / 64;
 constexpr int kG = 4;  // columns per wavefront per load batch in the tridiagonalisation pass
-
-// one DPP move of both halves of a double (lanes outside ROWS read 0)
-template <int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ double dpp_move(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xf, false);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-
-// sum over the 64 lanes in a fixed order, returned in every lane: pairs,
-// quads, half rows and rows by DPP permutes, then rows 0+1 and (0+1)+2+3 by
-// the row broadcasts of lanes 15 and 31; the total ends in lane 63
-__device__ __forceinline__ double wave_sum64(double s) {
-  s += dpp_move<0xb1>(s);       // quad_perm [1,0,3,2]
-  s += dpp_move<0x4e>(s);       // quad_perm [2,3,0,1]
-  s += dpp_move<0x141>(s);      // row_half_mirror
-  s += dpp_move<0x140>(s);      // row_mirror
-  s += dpp_move<0x142, 0xa>(s);  // row_bcast:15 into rows 1, 3
-  s += dpp_move<0x143, 0xc>(s);  // row_bcast:31 into rows 2, 3
-  const long long b = __double_as_longlong(s);
-  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), 63);
-  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
 
 // workgroup barrier that orders LDS accesses only (global accesses that must
 // be seen by other threads need __syncthreads)
