@@ -341,6 +341,24 @@ __global__ void __launch_bounds__(256) items_kernel(int nmol, const MolDesc* __r
   }
 }
 
+// Inner products of b with the rows s0 + 4 i (i < 4, rows < ns) of V, one
+// wavefront: four independent load streams over b and the rows.
+__device__ __forceinline__ void wave_dots4(const double* __restrict__ V, long nov, int s0, int ns,
+                                           const double* __restrict__ b, double* d) {
+  const int lane = threadIdx.x & 63;
+  const double* a[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) a[i] = V + static_cast<long>(min(s0 + 4 * i, ns - 1)) * nov;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long x = lane; x < nov; x += 64) {
+    const double bx = b[x];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += a[i][x] * bx;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) d[i] = wave_sum(acc[i]);
+}
+
 // New columns of M = V^T A V (column-major, ld Smax), both triangles: block
 // (m, j) forms column S_m + j against rows s <= S_m + j.  S is advanced by
 // advance_kernel afterwards.
@@ -357,14 +375,16 @@ __global__ void __launch_bounds__(256) project_kernel(const MolDesc* __restrict_
   const double* b = AVp + md.vbase + j * nov;
   double* M = Mp + static_cast<long>(m) * Smax * Smax;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int s = wave; s <= j; s += 4) {
-    const double* a = V + s * nov;
-    double acc = 0.0;
-    for (long x = lane; x < nov; x += 64) acc += a[x] * b[x];
-    acc = wave_sum(acc);
-    if (lane == 0) {
-      M[s + static_cast<long>(j) * Smax] = acc;
-      M[j + static_cast<long>(s) * Smax] = acc;
+  for (int s0 = wave; s0 <= j; s0 += 16) {  // rows s0, s0 + 4, s0 + 8, s0 + 12
+    double d[4];
+    wave_dots4(V, nov, s0, j + 1, b, d);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int s = s0 + 4 * i;
+      if (lane == 0 && s <= j) {
+        M[s + static_cast<long>(j) * Smax] = d[i];
+        M[j + static_cast<long>(s) * Smax] = d[i];
+      }
     }
   }
 }
@@ -614,12 +634,12 @@ __global__ void __launch_bounds__(256) deflate_kernel(const MolDesc* __restrict_
   if (threadIdx.x == 0) n0p[m * K + u] = sqrt(n0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int s = wave; s < nb; s += 4) {
-      const double* a = V + s * nov;
-      double d = 0.0;
-      for (long x = lane; x < nov; x += 64) d += a[x] * w[x];
-      d = wave_sum(d);
-      if (lane == 0) h[s] = d;
+    for (int s0 = wave; s0 < nb; s0 += 16) {  // rows s0, s0 + 4, s0 + 8, s0 + 12
+      double d[4];
+      wave_dots4(V, nov, s0, nb, w, d);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (lane == 0 && s0 + 4 * i < nb) h[s0 + 4 * i] = d[i];
     }
     __syncthreads();
     for (long x = threadIdx.x; x < nov; x += 256) {
