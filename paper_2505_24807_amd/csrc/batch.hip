@@ -68,7 +68,8 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const TA* __restric
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, k4 = lane >> 4;
   const int tm = (M + 16 * TM - 1) / (16 * TM), tn = (N + 16 * TN - 1) / (16 * TN);
-  for (int t = wave; t < tm * tn; t += 4) {
+  const int nwave = blockDim.x >> 6;
+  for (int t = wave; t < tm * tn; t += nwave) {
     const int i0 = (t / tn) * 16 * TM, j0 = (t % tn) * 16 * TN;
     typename MF::acc_t acc[TM][TN];
 #pragma unroll
@@ -105,6 +106,8 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const TA* __restric
         }
   }
 }
+
+constexpr int kSigThreads = 256;  // threads per work item (512 measured slower: the phases are latency-bound)
 
 // One CIS product A V for one trial vector of one molecule (whole workgroup).
 // scr: n*n (R) + n*n (F) + n*v (T, then Z) elements of T; rs, js: LDS [np].
@@ -175,7 +178,7 @@ __device__ void sigma_item(const MolDesc& md, const T* __restrict__ C, const dou
 
 // counters: [0] number of items, [1] active molecules, [2] iteration
 template <class T>
-__global__ void __launch_bounds__(256) sigma_items_kernel(const MolDesc* __restrict__ mols,
+__global__ void __launch_bounds__(kSigThreads) sigma_items_kernel(const MolDesc* __restrict__ mols,
                                                           const int2* __restrict__ items, const int* __restrict__ counters,
                                                           const double* __restrict__ Vp, double* __restrict__ AVp,
                                                           T* __restrict__ scratch, long scratch_stride,
@@ -782,9 +785,9 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
   SEQX_HIP(hipGetDevice(&dev));
   SEQX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   if (f32)
-    SEQX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sigma_items_kernel<float>, 256, 0));
+    SEQX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sigma_items_kernel<float>, kSigThreads, 0));
   else
-    SEQX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sigma_items_kernel<double>, 256, 0));
+    SEQX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sigma_items_kernel<double>, kSigThreads, 0));
   const int G = std::max(1, ncu * std::max(1, occ));
   const long scr_stride = (scr + 63) / 64 * 64;
 
@@ -835,10 +838,10 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
     };
     auto launch_sigma = [&] {
       if (f32)
-        hipLaunchKernelGGL(sigma_items_kernel<float>, dim3(G), dim3(256), 0, st, w.mols.p, w.items.p, w.counters.p,
+        hipLaunchKernelGGL(sigma_items_kernel<float>, dim3(G), dim3(kSigThreads), 0, st, w.mols.p, w.items.p, w.counters.p,
                            w.V.p, w.AV.p, w.scratch32.p, scr_stride, w.stamps.p);
       else
-        hipLaunchKernelGGL(sigma_items_kernel<double>, dim3(G), dim3(256), 0, st, w.mols.p, w.items.p, w.counters.p,
+        hipLaunchKernelGGL(sigma_items_kernel<double>, dim3(G), dim3(kSigThreads), 0, st, w.mols.p, w.items.p, w.counters.p,
                            w.V.p, w.AV.p, w.scratch64.p, scr_stride, w.stamps.p);
       SEQX_LAUNCH_CHECK();
     };
