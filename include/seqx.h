@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SEQX_ABI_VERSION 2
+#define SEQX_ABI_VERSION 3
 #define SEQX_NPARAM 11 /* per-element parameters, order below */
 
 typedef struct seqx_ctx seqx_ctx; /* one device + one stream */
@@ -167,6 +167,8 @@ seqx_status seqx_validate(int32_t nmol, const int32_t* natoms, const int32_t* Z,
  * all work on (e.g. torch's current stream) or NULL for the null stream.
  * Returns SEQX_E_DEVICE when no GPU is usable. */
 seqx_status seqx_create(int device, void* hip_stream, seqx_ctx** out);
+/* Frees the context's device memory (through the allocators it was made with).
+ * Free the context's jobs first: a job uses its context until it is freed. */
 void seqx_destroy(seqx_ctx* ctx);
 /* Text of the last error on this context (owned by ctx, valid until the next call). */
 const char* seqx_last_error(const seqx_ctx* ctx);
@@ -175,6 +177,30 @@ const char* seqx_last_error(const seqx_ctx* ctx);
  * The paper runs AM1 for every result; any NDDO parameter set of this form may
  * be given.  Derived multipole lengths and additive terms are computed here. */
 seqx_status seqx_set_params(seqx_ctx* ctx, int32_t nelem, const int32_t* Z, const double* values);
+
+/* Parameter sets by method.  SEQX_PARAMS_FILE reads a JSON file
+ *   {"elements": {"<Z>": {"zeta_s": .., "zeta_p": .., "U_ss": .., "U_pp": ..,
+ *                          "beta_s": .., "beta_p": .., "g_ss": .., "g_sp": ..,
+ *                          "g_pp": .., "g_p2": .., "h_sp": ..}, ...}, ...}
+ * (eV, exponents in 1/bohr; absent entries, e.g. the p terms of H, are 0) and
+ * applies it as seqx_set_params would.  The published MNDO / AM1 / PM3 tables
+ * (the paper's AM1 runs, "Theory and implementation") are not bundled: those
+ * methods return SEQX_E_ARG.  Errors: SEQX_E_ARG for an unreadable or malformed
+ * file, SEQX_E_ELEMENT for an unsupported Z. */
+typedef enum { SEQX_MNDO = 0, SEQX_AM1 = 1, SEQX_PM3 = 2, SEQX_PARAMS_FILE = 3 } seqx_method;
+seqx_status seqx_load_params(seqx_ctx* ctx, seqx_method method, const char* json_path);
+
+/* Device memory of everything this context and its jobs allocate from now on
+ * comes from alloc(bytes, user) and goes back through release(ptr, user)
+ * (e.g. a framework's caching allocator), instead of hipMalloc / hipFree.
+ * alloc must return device memory of the context's GPU, or NULL (the call then
+ * fails with SEQX_E_NOMEM).  Buffers keep the allocator that made them; the
+ * device is synchronised before a buffer is handed back, so a stream-ordered
+ * allocator may reuse it at once.  Both NULL: back to hipMalloc / hipFree for
+ * new buffers.  Exactly one NULL: SEQX_E_ARG.  Jobs must be freed before their
+ * context is destroyed. */
+seqx_status seqx_set_allocator(seqx_ctx* ctx, void* (*alloc)(size_t bytes, void* user),
+                               void (*release)(void* ptr, void* user), void* user);
 
 /* Integrals + RHF SCF for nmol molecules given as concatenated arrays:
  * natoms[nmol], Z[sum natoms], xyz_angstrom[sum natoms][3].  opts may be NULL.

@@ -1,11 +1,17 @@
 // C ABI of libseqx (declared in include/seqx.h): context and job lifecycle,
 // host validation, argument marshalling and the error model.  No exception
 // crosses the boundary; every entry point returns a status code.
+#include <cctype>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <cmath>
+#include <deque>
+#include <fstream>
+#include <map>
 #include <memory>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -20,9 +26,18 @@
 #include "scf.hpp"
 #include "sigma.hpp"
 
+namespace seqx {
+thread_local const DeviceAllocator* g_device_allocator = nullptr;
+}  // namespace seqx
+
 using namespace seqx;
 
 struct seqx_ctx {
+  // caller allocators, never modified once added (buffers keep a pointer to
+  // theirs).  Declared first so that they are destroyed last, after every
+  // buffer of the context has been handed back.
+  std::deque<DeviceAllocator> allocators;
+  const DeviceAllocator* allocator = nullptr;  // current one; nullptr: hipMalloc / hipFree
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
@@ -51,8 +66,18 @@ namespace {
 
 thread_local std::string g_noctx_err;
 
+// makes the context's allocator current for the duration of one ABI call
+struct AllocatorScope {
+  const DeviceAllocator* saved;
+  explicit AllocatorScope(const seqx_ctx* ctx) : saved(g_device_allocator) {
+    g_device_allocator = ctx ? ctx->allocator : nullptr;
+  }
+  ~AllocatorScope() { g_device_allocator = saved; }
+};
+
 template <class F>
 seqx_status guarded(seqx_ctx* ctx, F&& f) {
+  AllocatorScope scope(ctx);
   try {
     if (ctx) SEQX_HIP(hipSetDevice(ctx->device));
     f();
@@ -208,9 +233,104 @@ void seqx_destroy(seqx_ctx* ctx) {
 
 const char* seqx_last_error(const seqx_ctx* ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
 
-seqx_status seqx_set_params(seqx_ctx* ctx, int32_t nelem, const int32_t* Z, const double* values) {
-  if (!ctx) return SEQX_E_ARG;
-  return guarded(ctx, [&] {
+namespace {
+
+// Minimal JSON reader for parameter files: objects, arrays, strings, numbers,
+// true / false / null.  Parse errors raise SEQX_E_ARG.
+struct Json {
+  enum Kind { kNull, kNum, kStr, kObj, kArr, kBool } kind = kNull;
+  double num = 0.0;
+  std::string str;
+  std::map<std::string, Json> obj;
+  std::vector<Json> arr;
+};
+
+struct JsonParser {
+  const std::string& t;
+  size_t i = 0;
+  explicit JsonParser(const std::string& text) : t(text) {}
+  [[noreturn]] void fail(const char* what) {
+    throw Error(kEArg, std::string("parameter file: ") + what + " at offset " + std::to_string(i));
+  }
+  void ws() { while (i < t.size() && std::isspace(static_cast<unsigned char>(t[i]))) ++i; }
+  std::string string() {
+    if (t[i] != '"') fail("string expected");
+    std::string out;
+    for (++i; i < t.size() && t[i] != '"'; ++i) {
+      if (t[i] == '\\') {
+        if (++i >= t.size()) fail("bad escape");
+        const char c = t[i];
+        out += c == 'n' ? '\n' : c == 't' ? '\t' : c;
+      } else {
+        out += t[i];
+      }
+    }
+    if (i >= t.size()) fail("unterminated string");
+    ++i;
+    return out;
+  }
+  Json value() {
+    ws();
+    if (i >= t.size()) fail("value expected");
+    Json v;
+    const char c = t[i];
+    if (c == '{') {
+      v.kind = Json::kObj;
+      ++i;
+      ws();
+      if (i < t.size() && t[i] == '}') { ++i; return v; }
+      for (;;) {
+        ws();
+        const std::string key = string();
+        ws();
+        if (i >= t.size() || t[i] != ':') fail("':' expected");
+        ++i;
+        v.obj[key] = value();
+        ws();
+        if (i < t.size() && t[i] == ',') { ++i; continue; }
+        if (i < t.size() && t[i] == '}') { ++i; return v; }
+        fail("',' or '}' expected");
+      }
+    }
+    if (c == '[') {
+      v.kind = Json::kArr;
+      ++i;
+      ws();
+      if (i < t.size() && t[i] == ']') { ++i; return v; }
+      for (;;) {
+        v.arr.push_back(value());
+        ws();
+        if (i < t.size() && t[i] == ',') { ++i; continue; }
+        if (i < t.size() && t[i] == ']') { ++i; return v; }
+        fail("',' or ']' expected");
+      }
+    }
+    if (c == '"') {
+      v.kind = Json::kStr;
+      v.str = string();
+      return v;
+    }
+    if (t.compare(i, 4, "true") == 0 || t.compare(i, 5, "false") == 0) {
+      v.kind = Json::kBool;
+      v.num = t[i] == 't' ? 1.0 : 0.0;
+      i += t[i] == 't' ? 4 : 5;
+      return v;
+    }
+    if (t.compare(i, 4, "null") == 0) {
+      i += 4;
+      return v;
+    }
+    const char* b = t.c_str() + i;
+    char* e = nullptr;
+    v.num = std::strtod(b, &e);
+    if (e == b) fail("number expected");
+    v.kind = Json::kNum;
+    i += static_cast<size_t>(e - b);
+    return v;
+  }
+};
+
+void set_params_impl(seqx_ctx* ctx, int32_t nelem, const int32_t* Z, const double* values) {
     if (nelem <= 0 || !Z || !values) throw Error(kEArg, "nelem must be > 0 and arrays non-null");
     for (int i = 0; i < nelem; ++i) {
       const int s = element_slot(Z[i]);
@@ -227,6 +347,67 @@ seqx_status seqx_set_params(seqx_ctx* ctx, int32_t nelem, const int32_t* Z, cons
     }
     SEQX_HIP(hipMemcpyAsync(ctx->d_elems.p, ctx->elems, sizeof(ctx->elems), hipMemcpyHostToDevice, ctx->stream));
     SEQX_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+}  // namespace
+
+seqx_status seqx_set_params(seqx_ctx* ctx, int32_t nelem, const int32_t* Z, const double* values) {
+  if (!ctx) return SEQX_E_ARG;
+  return guarded(ctx, [&] { set_params_impl(ctx, nelem, Z, values); });
+}
+
+seqx_status seqx_load_params(seqx_ctx* ctx, seqx_method method, const char* path) {
+  if (!ctx) return SEQX_E_ARG;
+  return guarded(ctx, [&] {
+    if (method != SEQX_PARAMS_FILE)
+      throw Error(kEArg, "published MNDO/AM1/PM3 tables are not bundled; load a parameter file (SEQX_PARAMS_FILE)");
+    if (!path) throw Error(kEArg, "parameter file path is null");
+    std::ifstream f(path);
+    if (!f) throw Error(kEArg, std::string("cannot read ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string text = ss.str();
+    JsonParser jp(text);
+    const Json doc = jp.value();
+    auto it = doc.obj.find("elements");
+    if (doc.kind != Json::kObj || it == doc.obj.end() || it->second.kind != Json::kObj)
+      throw Error(kEArg, "parameter file has no \"elements\" object");
+    static const char* const names[SEQX_NPARAM] = {"zeta_s", "zeta_p", "U_ss", "U_pp", "beta_s", "beta_p",
+                                                   "g_ss", "g_sp", "g_pp", "g_p2", "h_sp"};
+    std::vector<int32_t> zs;
+    std::vector<double> vals;
+    for (const auto& kv : it->second.obj) {
+      char* e = nullptr;
+      const long z = std::strtol(kv.first.c_str(), &e, 10);
+      if (e == kv.first.c_str() || *e != '\0') throw Error(kEArg, "element key is not an atomic number: " + kv.first);
+      if (kv.second.kind != Json::kObj) throw Error(kEArg, "element entry is not an object: " + kv.first);
+      zs.push_back(static_cast<int32_t>(z));
+      for (const char* nm : names) {
+        auto p = kv.second.obj.find(nm);
+        if (p != kv.second.obj.end() && p->second.kind != Json::kNum)
+          throw Error(kEArg, std::string("parameter ") + nm + " of Z=" + kv.first + " is not a number");
+        vals.push_back(p == kv.second.obj.end() ? 0.0 : p->second.num);  // absent (p terms of H): 0
+      }
+    }
+    set_params_impl(ctx, static_cast<int32_t>(zs.size()), zs.data(), vals.data());
+  });
+}
+
+seqx_status seqx_set_allocator(seqx_ctx* ctx, void* (*alloc)(size_t bytes, void* user),
+                               void (*release)(void* ptr, void* user), void* user) {
+  if (!ctx) return SEQX_E_ARG;
+  return guarded(ctx, [&] {
+    if (!alloc != !release) throw Error(kEArg, "alloc and release must both be set or both be null");
+    if (!alloc) {
+      ctx->allocator = nullptr;
+      return;
+    }
+    DeviceAllocator a;
+    a.alloc = alloc;
+    a.release = release;
+    a.user = user;
+    ctx->allocators.push_back(a);
+    ctx->allocator = &ctx->allocators.back();
   });
 }
 

@@ -37,33 +37,61 @@ struct Error : std::runtime_error {
 
 #define SEQX_LAUNCH_CHECK() SEQX_HIP(hipGetLastError())
 
-// Owning device buffer (hipMalloc / hipFree), move-only.
+// Caller-provided device allocator (seqx_set_allocator).  The ABI entry
+// points make the allocator of their context current for the call; buffers
+// remember the allocator that made them and hand their memory back to it.
+struct DeviceAllocator {
+  void* (*alloc)(size_t bytes, void* user) = nullptr;
+  void (*release)(void* ptr, void* user) = nullptr;
+  void* user = nullptr;
+};
+extern thread_local const DeviceAllocator* g_device_allocator;  // nullptr: hipMalloc / hipFree
+
+// Owning device buffer, move-only: hipMalloc / hipFree, or the current
+// caller-provided allocator.  Before memory goes back to a caller's allocator
+// the device is synchronised, so that a stream-ordered allocator cannot give
+// it to other work while kernels of this library may still use it.
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  const DeviceAllocator* a = nullptr;
   DBuf() = default;
   explicit DBuf(size_t count) { alloc(count); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), a(o.a) { o.p = nullptr; o.n = 0; o.a = nullptr; }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; a = o.a; o.p = nullptr; o.n = 0; o.a = nullptr; }
     return *this;
   }
   ~DBuf() { release(); }
   void alloc(size_t count) {
     release();
     if (count == 0) return;
-    SEQX_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+    a = g_device_allocator;
+    if (a) {
+      p = static_cast<T*>(a->alloc(count * sizeof(T), a->user));
+      if (!p) throw Error(kENoMem, "caller allocator returned null for " + std::to_string(count * sizeof(T)) + " bytes");
+    } else {
+      SEQX_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+    }
     n = count;
   }
   // grow-only reallocation; contents are not preserved
   void ensure(size_t count) { if (count > n) alloc(count); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (a) {
+        (void)hipDeviceSynchronize();
+        a->release(p, a->user);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
     n = 0;
+    a = nullptr;
   }
   operator T*() const { return p; }
   T* get() const { return p; }

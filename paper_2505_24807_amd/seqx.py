@@ -7,8 +7,11 @@ missing or no GPU is usable, calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import traceback
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -70,6 +73,12 @@ class Stats(C.Structure):
 
 _lib = None
 
+# device allocator callbacks of seqx_set_allocator: alloc(bytes, user) -> ptr, release(ptr, user)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+MNDO, AM1, PM3, PARAMS_FILE = 0, 1, 2, 3
+
 _D = C.POINTER(C.c_double)
 _F = C.POINTER(C.c_float)
 _I = C.POINTER(C.c_int32)
@@ -82,6 +91,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libseqx.so not found at {path}; build it with `python -m paper_2505_24807_amd.build`")
+    # A process holds one HIP runtime.  PyTorch ships its own copy under the
+    # same soname: when PyTorch is installed it is loaded first, so that this
+    # library binds to that runtime and PyTorch's streams and device memory are
+    # valid here (a library loaded first would leave PyTorch without a GPU).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     sig = {
         "seqx_abi_version": (C.c_int, []),
@@ -90,6 +107,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "seqx_destroy": (None, [C.c_void_p]),
         "seqx_last_error": (C.c_char_p, [C.c_void_p]),
         "seqx_set_params": (C.c_int, [C.c_void_p, C.c_int32, _I, _D]),
+        "seqx_load_params": (C.c_int, [C.c_void_p, C.c_int, C.c_char_p]),
+        "seqx_set_allocator": (C.c_int, [C.c_void_p, ALLOC_FN, RELEASE_FN, C.c_void_p]),
         "seqx_prepare": (C.c_int, [C.c_void_p, C.c_int32, _I, _I, _D, C.POINTER(ScfOpts), C.POINTER(C.c_void_p)]),
         "seqx_job_free": (None, [C.c_void_p]),
         "seqx_dims": (C.c_int, [C.c_void_p, C.c_int32, _I, _I, _I]),
@@ -158,6 +177,9 @@ class Context:
 
     def __init__(self, device: int = 0, stream: int | None = None):
         self.lib = load_library()
+        self._callbacks = []
+        self._jobs = weakref.WeakSet()
+        self._exit_hook = False
         h = C.c_void_p()
         s = self.lib.seqx_create(device, C.c_void_p(stream) if stream else None, C.byref(h))
         if s != 0:
@@ -172,6 +194,48 @@ class Context:
         Zs = np.ascontiguousarray(Zs, dtype=np.int32)
         values = np.ascontiguousarray(values, dtype=np.float64).reshape(len(Zs), NPARAM)
         self._check(self.lib.seqx_set_params(self.h, len(Zs), _iptr(Zs), _dptr(values)))
+
+    def load_params(self, path: str, method: int = PARAMS_FILE):
+        """seqx_load_params: a JSON parameter file (or a named method, which is not bundled)."""
+        self._check(self.lib.seqx_load_params(self.h, method, path.encode() if path is not None else None))
+
+    def set_allocator(self, alloc, release):
+        """seqx_set_allocator with Python callables alloc(nbytes) -> device pointer (int) and
+        release(pointer); None, None restores hipMalloc / hipFree.  The callbacks are kept
+        alive by the context."""
+        if alloc is None and release is None:
+            self._check(self.lib.seqx_set_allocator(self.h, ALLOC_FN(), RELEASE_FN(), None))
+            return
+        def _alloc(n, user):
+            try:
+                return alloc(int(n)) or None
+            except Exception:  # reported as a failed allocation (SEQX_E_NOMEM)
+                traceback.print_exc()
+                return None
+
+        def _release(ptr, user):
+            try:
+                release(int(ptr))
+            except Exception:
+                traceback.print_exc()
+
+        cbs = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+        if not self._exit_hook:
+            # memory must go back through Python callables while the interpreter
+            # (and the framework that owns the memory) is still whole
+            atexit.register(_close_at_exit, weakref.ref(self))
+            self._exit_hook = True
+        # buffers made earlier still hand their memory back through the callbacks they
+        # were made with, so every pair stays alive as long as the context
+        self._callbacks.append(cbs)
+        self._check(self.lib.seqx_set_allocator(self.h, cbs[0], cbs[1], None))
+
+    def use_torch_allocator(self, device: int = 0):
+        """Route the library's device memory through torch's caching allocator (on the
+        current torch stream of `device`)."""
+        import torch
+        self.set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, device),
+                           lambda p: torch.cuda.caching_allocator_delete(p))
 
     def prepare(self, natoms, Z, xyz, tol=None, max_iter=None, ndiis=None, integrals_only=False) -> "Job":
         natoms = np.ascontiguousarray(np.atleast_1d(natoms), dtype=np.int32)
@@ -209,7 +273,10 @@ class Context:
         return loss.value, g
 
     def close(self):
+        """Free the context's jobs, then the context (seqx_destroy)."""
         if getattr(self, "h", None):
+            for job in list(self._jobs):
+                job.free()
             self.lib.seqx_destroy(self.h)
             self.h = None
 
@@ -220,10 +287,17 @@ class Context:
             pass
 
 
+def _close_at_exit(ref):
+    ctx = ref()
+    if ctx is not None:
+        ctx.close()
+
+
 class Job:
     def __init__(self, ctx: Context, h, nmol: int):
         self.ctx, self.h, self.nmol = ctx, h, nmol
         self.lib = ctx.lib
+        ctx._jobs.add(self)
 
     def _check(self, s):
         self.ctx._check(s)
