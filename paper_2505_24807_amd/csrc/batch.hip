@@ -76,24 +76,30 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, const TA* __restric
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
-#pragma unroll 4
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + k4;
-      T a[TM], b[TN];
+    // four k-steps per pass, all loads first (the loads past K read zero, so
+    // no remainder loop is needed)
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      T a[4][TM], b[4][TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int row = i0 + i * 16 + r16;
-        a[i] = (row < M && k < K) ? static_cast<T>(A[row * sai + k * sak]) : T(0);
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 4 * q + k4;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int row = i0 + i * 16 + r16;
+          a[q][i] = (row < M && k < K) ? static_cast<T>(A[row * sai + k * sak]) : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int col = j0 + j * 16 + r16;
+          b[q][j] = (col < N && k < K) ? static_cast<T>(B[k * sbk + col * sbj]) : T(0);
+        }
       }
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int col = j0 + j * 16 + r16;
-        b[j] = (col < N && k < K) ? static_cast<T>(B[k * sbk + col * sbj]) : T(0);
-      }
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[q][i], b[q][j], acc[i][j]);
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)

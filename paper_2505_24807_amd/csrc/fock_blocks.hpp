@@ -110,32 +110,33 @@ __device__ __forceinline__ void diag_block(const Elem& e, int o, int po, const d
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int nn = 0; nn < 4; ++nn) {
-      if (m >= na || nn >= na) continue;
-      const double S = 0.5 * (X[m][nn] + X[nn][m]), Dv = 0.5 * (X[m][nn] - X[nn][m]);
-      double kS, kD;
-      if (na == 1) {
-        kS = e.gss * S;
-        kD = 0.0;
-      } else if (m == nn) {
-        kS = g1(e, m, m) * X[m][m];
+      if (m < na && nn < na) {
+        const double S = 0.5 * (X[m][nn] + X[nn][m]), Dv = 0.5 * (X[m][nn] - X[nn][m]);
+        double kS, kD;
+        if (na == 1) {
+          kS = e.gss * S;
+          kD = 0.0;
+        } else if (m == nn) {
+          kS = g1(e, m, m) * X[m][m];
 #pragma unroll
-        for (int l = 0; l < 4; ++l)
-          if (l != m) kS += h1(e, m, l) * X[l][l];
-        kD = 0.0;
-      } else {
-        // K1(S) and K1(D) for the symmetric / antisymmetric parts
-        kS = (g1(e, m, nn) + h1(e, m, nn)) * S;
-        kD = (g1(e, m, nn) - h1(e, m, nn)) * Dv;
-      }
-      const double jv = J[static_cast<long>(po + (na == 1 ? 0 : pair_index(m, nn))) * jstride];
-      const long idx = static_cast<long>(o + m) * n + o + nn;
-      if (MODE == kTwo) {
-        f1[idx] = static_cast<TF>(cJ * jv + cK * kS);
-        f2[idx] = static_cast<TF>(cKa * kD);
-      } else if (MODE == kSum) {
-        f1[idx] = static_cast<TF>(cJ * jv + cK * kS + cKa * kD);
-      } else {
-        f1[idx] = static_cast<TF>(cJ * jv + cK * kS);
+          for (int l = 0; l < 4; ++l)
+            if (l != m) kS += h1(e, m, l) * X[l][l];
+          kD = 0.0;
+        } else {
+          // K1(S) and K1(D) for the symmetric / antisymmetric parts
+          kS = (g1(e, m, nn) + h1(e, m, nn)) * S;
+          kD = (g1(e, m, nn) - h1(e, m, nn)) * Dv;
+        }
+        const double jv = J[static_cast<long>(po + (na == 1 ? 0 : pair_index(m, nn))) * jstride];
+        const long idx = static_cast<long>(o + m) * n + o + nn;
+        if (MODE == kTwo) {
+          f1[idx] = static_cast<TF>(cJ * jv + cK * kS);
+          f2[idx] = static_cast<TF>(cKa * kD);
+        } else if (MODE == kSum) {
+          f1[idx] = static_cast<TF>(cJ * jv + cK * kS + cKa * kD);
+        } else {
+          f1[idx] = static_cast<TF>(cJ * jv + cK * kS);
+        }
       }
     }
 }
