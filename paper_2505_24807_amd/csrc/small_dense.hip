@@ -2,8 +2,8 @@
 // iteration (n <= 256): the k lowest eigenpairs of a symmetric matrix and a
 // Cholesky factorisation.  A library divide-and-conquer eigensolver spends
 // most of its time in hundreds of small launches at these sizes; here each
-// problem is one launch of 1024 threads with the matrix in global memory
-// (L2-resident) and the vectors in LDS.
+// problem is one workgroup: the reduction keeps the matrix in registers, the
+// later phases keep the tridiagonal matrix and the eigenvalues in LDS.
 //
 // Eigenpairs: Householder reduction to tridiagonal form T = Q^T A Q; the k
 // lowest eigenvalues of T by Sturm-count multisection (each wavefront narrows
@@ -22,7 +22,8 @@ namespace {
 
 constexpr int kNT = 1024;
 constexpr int kNW = kNT / 64;
-constexpr int kG = 4;  // columns per wavefront per load batch in the tridiagonalisation pass
+constexpr int kIB = 4;   // rows per block of the triangular solves of inverse iteration
+constexpr int kBT = 16;  // reflectors per LDS chunk of the back-transformation
 
 // workgroup barrier that orders LDS accesses only (global accesses that must
 // be seen by other threads need __syncthreads)
@@ -48,11 +49,27 @@ __device__ double block_sum_1024(double v, double* red) {
 }
 
 // number of eigenvalues of T (d, e2 = e^2) below x
+// (the LDS operands of 8 steps are read ahead of their dependent chain)
 __device__ int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
   int c = 0;
   double q = d[0] - x;
   if (q < 0.0) ++c;
-  for (int i = 1; i < n; ++i) {
+  int i = 1;
+  for (; i + 8 <= n; i += 8) {
+    double dx[8], f[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dx[u] = d[i + u] - x;
+      f[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (fabs(q) < pivmin) q = -pivmin;
+      q = dx[u] - f[u] / q;
+      if (q < 0.0) ++c;
+    }
+  }
+  for (; i < n; ++i) {
     if (fabs(q) < pivmin) q = -pivmin;
     q = d[i] - x - e2[i - 1] / q;
     if (q < 0.0) ++c;
@@ -60,142 +77,197 @@ __device__ int sturm_count(int n, const double* d, const double* e2, double x, d
   return c;
 }
 
-// scratch layout (doubles): W [n * n] working copy, Z [n * k], then per vector t: u0, u1, u2, l, piv, y [n each]
-__global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restrict__ A, int lda, int k,
-                                                          double* __restrict__ w, double* __restrict__ scratch,
-                                                          int* __restrict__ info) {
-  __shared__ double d[kSmallDense], e[kSmallDense], e2[kSmallDense], tau[kSmallDense];
-  __shared__ double xs[kSmallDense], vp[kSmallDense], wp[kSmallDense], pc[kSmallDense], nextc[kSmallDense];
-  __shared__ double prw[kNW][kSmallDense];
-  __shared__ double red[kNT];
-  __shared__ double lam[kSmallDense];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* W = scratch;
-  double* Z = scratch + static_cast<long>(n) * n;
-  double* per = Z + static_cast<long>(n) * k;
-  // working copy (column-major, W[l * n + i] = A(i, l)) of the lower
-  // triangle.  Element (i, l) belongs to the thread of wavefront l % 16 and
-  // lane i % 64 for the whole reduction, so the passes below touch only their
-  // own elements in global memory and their barriers order LDS alone.
-  for (int l = wave; l < n; l += kNW)
-#pragma unroll
-    for (int c = 0; c < kSmallDense / 64; ++c) {
-      const int i = lane + 64 * c;
-      if (i >= l && i < n) W[static_cast<long>(l) * n + i] = A[i + static_cast<long>(l) * lda];
-    }
-  for (int i = tid; i < n; i += kNT) {
-    vp[i] = 0.0;
-    wp[i] = 0.0;
-  }
-  __syncthreads();
+// ---- Householder tridiagonalisation T = Q^T A Q, one workgroup of kTT
+// threads with the matrix in registers.  Column l belongs to wavefront l % kTW
+// (l = wavefront + kTW g) and row i to lane i % 64 (i = lane + 64 c); a thread
+// keeps a[g][c] for the row blocks c >= l / 64 only (80 of the 128 slots), so
+// it stores the block lower triangle: whole 64 x 64 blocks on the diagonal
+// (both triangles, each element twice) and below.  Then no element needs a
+// per-lane test: an element of a diagonal block adds to its row of p = A v, an
+// element below adds to its row and (through a wavefront sum) to its column.
+// Rows and columns past n, and rows <= j at step j, hold or meet zeros.
+// Step j forms the reflector of column j (kept, updated, in LDS), p = tau A22 v,
+// v^T A22 v from the same products, w = p - (tau v^T p / 2) v, and applies
+// A22 -= v w^T + w v^T to the registers.  Three LDS barriers a step; global
+// memory is only read at the start.
+constexpr int kTT = 512;
+constexpr int kTW = kTT / 64;
+constexpr int kTG = kSmallDense / kTW;  // columns per wavefront
+constexpr int kTC = kSmallDense / 64;   // row blocks per lane
 
-  // ---- Householder tridiagonalisation, lower triangle only (reflector j
-  // stored in W[j+1 .., j]).  The rank-2 update A -= v w^T + w v^T of step j
-  // is kept pending in (vp, wp) and applied during the pass of step j + 1
-  // that also forms p = A v, so every step reads and writes the trailing
-  // triangle once.
-  for (int j = 0; j + 2 < n; ++j) {
-    const int m = n - j - 1;
-    // column j with the pending update: diagonal d[j] and x = rows j+1 ..
-    double xsq = 0.0;
-    if (tid < m + 1) {
-      const int i = j + tid;
-      // column j as the previous pass left it (kept in LDS), or the input
-      const double cw = j == 0 ? W[i] : nextc[tid];
-      const double c = cw - (vp[i] * wp[j] + wp[i] * vp[j]);
-      if (tid == 0) d[j] = c;
-      else {
-        xs[i] = c;
-        xsq = c * c;
-      }
+// outputs: reflector j in W[j * n + i] (i > j), then d, e, tau [n each] in dte
+__global__ void __launch_bounds__(kTT) small_tridiag_kernel(int n, const double* __restrict__ A, int lda,
+                                                            double* __restrict__ W, double* __restrict__ dte) {
+  __shared__ double colj[2][kSmallDense];  // column j (rows >= j) after the updates of steps < j
+  __shared__ double wv[kSmallDense];
+  __shared__ double prw[kTW][kSmallDense];
+  __shared__ double pc[kSmallDense];
+  __shared__ double vav[kTW];
+  // the wavefront index, read from lane 0 so that the compiler knows it is uniform
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* dd = dte;
+  double* ee = dte + n;
+  double* tt = dte + 2 * n;
+  double a[kTG][kTC];
+#pragma unroll
+  for (int g = 0; g < kTG; ++g)
+#pragma unroll
+    for (int c = g / kTW; c < kTC; ++c) {
+      const int l = wave + kTW * g, i = lane + 64 * c;
+      const int r = i > l ? i : l, s = i > l ? l : i;  // read the lower triangle
+      a[g][c] = (l < n && i < n) ? A[r + static_cast<long>(s) * lda] : 0.0;
     }
-    const double xx = block_sum_1024<true>(xsq, red);
-    const double x0 = xs[j + 1];
+  if (wave == 0)
+#pragma unroll
+    for (int c = 0; c < kTC; ++c) colj[0][lane + 64 * c] = a[0][c];
+  lds_barrier();
+  for (int j = 0; j + 2 < n; ++j) {
+    const double* cj = colj[j & 1];
+    double* cn = colj[(j + 1) & 1];
+    // reflector H = I - t v v^T with H x = alpha e_1, x = column j below the diagonal
+    double xsq = 0.0;
+#pragma unroll
+    for (int c = 0; c < kTC; ++c) {
+      const int i = lane + 64 * c;
+      const double x = (i > j && i < n) ? cj[i] : 0.0;
+      xsq += x * x;
+    }
+    const double xx = wave_sum64(xsq);  // the same value in every wavefront
+    const double x0 = cj[j + 1];
     double alpha = 0.0, v0 = x0, t = 0.0;
     if (xx > 0.0) {
       alpha = x0 > 0.0 ? -sqrt(xx) : sqrt(xx);
       v0 = x0 - alpha;
       t = 2.0 / (xx - x0 * x0 + v0 * v0);
     }
-    // the reflector, for the back-transformation (column j is never touched again)
-    if (tid < m) W[static_cast<long>(j) * n + j + 1 + tid] = tid == 0 ? v0 : xs[j + 1 + tid];
-    // fused pass over the trailing lower triangle (rows and columns j+1 ..):
-    // apply the pending update, store, and accumulate p = A22 v by rows
-    // (per lane, rows lane + 64 c) and by columns (wavefront sums).  Each
-    // wavefront takes its columns kG at a time, all loads first.  The first
-    // column (the next step's pivot column) is also kept in LDS.
-    double pr[kSmallDense / 64] = {};
-    const int lfirst = j + 1 + (((wave - (j + 1)) % kNW) + kNW) % kNW;
-    for (int l0 = lfirst; l0 < n; l0 += kNW * kG) {
-      double a[kG][kSmallDense / 64];
+    double vi[kTC];  // v by rows: zero at rows <= j and >= n
 #pragma unroll
-      for (int g = 0; g < kG; ++g) {
-        const int l = l0 + kNW * g;
-        const double* col = W + static_cast<long>(l) * n;
+    for (int c = 0; c < kTC; ++c) {
+      const int i = lane + 64 * c;
+      vi[c] = i == j + 1 ? v0 : ((i > j + 1 && i < n) ? cj[i] : 0.0);
+    }
+    if (wave == 0) {
 #pragma unroll
-        for (int c = 0; c < kSmallDense / 64; ++c) {
-          const int i = lane + 64 * c;
-          a[g][c] = (l < n && i >= l && i < n) ? col[i] : 0.0;
-        }
+      for (int c = 0; c < kTC; ++c) {
+        const int i = lane + 64 * c;
+        if (i > j && i < n) W[static_cast<long>(j) * n + i] = vi[c];
       }
-      double cs[kG];
+      if (lane == 0) {
+        dd[j] = cj[j];
+        ee[j] = alpha;
+        tt[j] = t;
+      }
+    }
+    // A22 v by rows (pr) and, for the blocks below the diagonal, by columns
+    // (pc); v^T A22 v counts an element below the diagonal blocks twice.
+    // Columns go in chunks of 8 (l = wavefront + kTW (8 q + u)), which share
+    // the diagonal block q; their column sums are reduced together.
+    double pr[kTC] = {};
+    double svav = 0.0;
 #pragma unroll
-      for (int g = 0; g < kG; ++g) {
-        const int l = l0 + kNW * g;
-        cs[g] = 0.0;
-        if (l >= n) continue;
-        const double vl = l == j + 1 ? v0 : xs[l], vpl = vp[l], wpl = wp[l];
-        double* col = W + static_cast<long>(l) * n;
+    for (int q = 0; q < kTG / 8; ++q) {
+      const int lf = wave + kTW * 8 * q, ll = lf + kTW * 7;
+      if (ll > j && lf < n) {  // uniform: a column of the chunk is active
+        double cs[8];
 #pragma unroll
-        for (int c = 0; c < kSmallDense / 64; ++c) {
-          const int i = lane + 64 * c;
-          if (i >= l && i < n) {
-            const double av = a[g][c] - (vp[i] * wpl + wp[i] * vpl);
-            col[i] = av;
-            if (l == j + 1) nextc[i - j - 1] = av;
-            pr[c] += av * vl;
-            if (i > l) cs[g] += av * xs[i];
+        for (int u = 0; u < 8; ++u) {
+          const int g = 8 * q + u, l = wave + kTW * g;
+          cs[u] = 0.0;
+          if (l > j && l < n) {
+            const double vl = lane_value(vi[q], l & 63);  // v_l from the lane that holds row l
+            pr[q] += a[g][q] * vl;
+            const double sd = a[g][q] * vi[q];
+#pragma unroll
+            for (int c = q + 1; c < kTC; ++c) {
+              pr[c] += a[g][c] * vl;
+              cs[u] += a[g][c] * vi[c];
+            }
+            svav += vl * (2.0 * cs[u] + sd);
           }
         }
-      }
-#pragma unroll
-      for (int g = 0; g < kG; ++g) {
-        const int l = l0 + kNW * g;
-        const double t2 = wave_sum64(cs[g]);
-        if (lane == 0 && l < n) pc[l - j - 1] = t2;
+        const double cl = wave_sum8x64(cs);  // column u = (lane >> 3) & 7 of the chunk
+        if ((lane & 7) == 0) {
+          const int l = wave + kTW * (8 * q + (lane >> 3));
+          if (l > j && l < n) pc[l] = cl;
+        }
       }
     }
 #pragma unroll
-    for (int c = 0; c < kSmallDense / 64; ++c) prw[wave][lane + 64 * c] = pr[c];
+    for (int c = 0; c < kTC; ++c) prw[wave][lane + 64 * c] = pr[c];
+    const double sw = wave_sum64(svav);
+    if (lane == 0) vav[wave] = sw;
     lds_barrier();
-    double pv = 0.0, vi = 0.0;
-    if (tid < m) {
+    double vav_all = 0.0;
+#pragma unroll
+    for (int q = 0; q < kTW; ++q) vav_all += vav[q];
+    const double K = 0.5 * t * t * vav_all;  // tau v^T p / 2 with p = tau A22 v
+    if (tid < n - j - 1) {
       const int i = j + 1 + tid;
-      double ssum = pc[tid];
-      for (int q = 0; q < kNW; ++q) ssum += prw[q][i];
-      pv = t * ssum;
-      vi = tid == 0 ? v0 : xs[i];
+      double s = pc[i];
+#pragma unroll
+      for (int q = 0; q < kTW; ++q) s += prw[q][i];
+      wv[i] = t * s - K * (i == j + 1 ? v0 : cj[i]);
     }
-    const double K = 0.5 * t * block_sum_1024<true>(pv * vi, red);
-    if (tid < m) {
-      vp[j + 1 + tid] = vi;
-      wp[j + 1 + tid] = pv - K * vi;
+    lds_barrier();
+    // A22 -= v w^T + w v^T; the owner of column j + 1 hands it to the next step
+    double wi[kTC];
+#pragma unroll
+    for (int c = 0; c < kTC; ++c) {
+      const int i = lane + 64 * c;
+      wi[c] = (i > j && i < n) ? wv[i] : 0.0;
     }
-    if (tid == 0) {
-      tau[j] = t;
-      e[j] = alpha;
+#pragma unroll
+    for (int g = 0; g < kTG; ++g) {
+      const int l = wave + kTW * g;
+      if (l > j && l < n) {
+        // v_l and w_l from the lane that holds row l (row block g / kTW)
+        const double vl = lane_value(vi[g / kTW], l & 63), wl = lane_value(wi[g / kTW], l & 63);
+#pragma unroll
+        for (int c = g / kTW; c < kTC; ++c) a[g][c] = fma(-wi[c], vl, fma(-vi[c], wl, a[g][c]));
+        if (l == j + 1)
+#pragma unroll
+          for (int c = g / kTW; c < kTC; ++c) cn[lane + 64 * c] = a[g][c];
+      }
     }
     lds_barrier();
   }
-  __syncthreads();  // the last block and the reflectors are read by other threads
-  if (tid == 0) {  // the last 2 x 2 block, with the pending update
+  // the last 2 x 2 block: column n - 2 is in LDS, element (n-1, n-1) in its register
+  const int jl = n >= 2 ? n - 2 : 0;
+  if (tid == 0) {
     if (n >= 2) {
-      const int a = n - 2, b = n - 1;
-      d[a] = W[static_cast<long>(a) * n + a] - 2.0 * vp[a] * wp[a];
-      e[a] = W[static_cast<long>(a) * n + b] - (vp[b] * wp[a] + wp[b] * vp[a]);
-      tau[a] = 0.0;
+      dd[n - 2] = colj[jl & 1][n - 2];
+      ee[n - 2] = colj[jl & 1][n - 1];
+      tt[n - 2] = 0.0;
     }
-    d[n - 1] = W[static_cast<long>(n - 1) * n + n - 1] - 2.0 * vp[n - 1] * wp[n - 1];
+    ee[n - 1] = 0.0;
+    tt[n - 1] = 0.0;
+  }
+#pragma unroll
+  for (int g = 0; g < kTG; ++g)
+#pragma unroll
+    for (int c = g / kTW; c < kTC; ++c)
+      if (wave + kTW * g == n - 1 && lane + 64 * c == n - 1) dd[n - 1] = a[g][c];
+}
+
+// scratch layout (doubles): W [n * n] reflectors, Z [n * k], d, e, tau [n each], then per vector t: u0, u1, u2, l,
+// piv, y [n each].  Runs after small_tridiag_kernel on the same scratch.
+__global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restrict__ A, int lda, int k,
+                                                          double* __restrict__ w, double* __restrict__ scratch,
+                                                          int* __restrict__ info) {
+  __shared__ double d[kSmallDense], e[kSmallDense], e2[kSmallDense], tau[kSmallDense];
+  __shared__ double red[kNT];
+  __shared__ double lam[kSmallDense];
+  __shared__ double Vs[kBT][kSmallDense];
+  // the wavefront index, read from lane 0 so that the compiler knows it is uniform
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* W = scratch;
+  double* Z = scratch + static_cast<long>(n) * n;
+  const double* dte = Z + static_cast<long>(n) * k;
+  double* per = Z + static_cast<long>(n) * k + 3L * n;
+  for (int i = tid; i < n; i += kNT) {
+    d[i] = dte[i];
+    e[i] = dte[n + i];
+    tau[i] = dte[2 * n + i];
   }
   __syncthreads();
   for (int i = tid; i + 1 < n; i += kNT) e2[i] = e[i] * e[i];
@@ -299,9 +371,33 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
       sd = sd * 6364136223846793005ULL + 1442695040888963407ULL;
       y[i * kk + tt] = static_cast<double>(static_cast<long long>(sd >> 11)) / 9007199254740992.0 - 0.5;
     }
+    // The two triangular solves run in blocks of kIB rows whose operands are
+    // all loaded before the dependent chain goes through them, so a block
+    // waits for memory once.
     for (int it = 0; it < 2; ++it) {
       double carry = y[0 * kk + tt];  // running element i of P L^-1 y
-      for (int i = 0; i + 1 < n; ++i) {
+      int i = 0;
+      for (; i + kIB < n; i += kIB) {
+        double yn[kIB], pv[kIB], lv[kIB];
+#pragma unroll
+        for (int u = 0; u < kIB; ++u) {
+          yn[u] = y[(i + 1 + u) * kk + tt];
+          pv[u] = pvt[(i + u) * kk + tt];
+          lv[u] = lm[(i + u) * kk + tt];
+        }
+#pragma unroll
+        for (int u = 0; u < kIB; ++u) {
+          double next = yn[u];
+          if (pv[u] != 0.0) {
+            const double tmp = carry;
+            carry = next;
+            next = tmp;
+          }
+          y[(i + u) * kk + tt] = carry;
+          carry = next - lv[u] * carry;
+        }
+      }
+      for (; i + 1 < n; ++i) {
         double next = y[(i + 1) * kk + tt];
         if (pvt[i * kk + tt] != 0.0) {
           const double tmp = carry;
@@ -313,7 +409,27 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
       }
       y[(n - 1) * kk + tt] = carry;
       double nrm = 0.0, x1 = 0.0, x2 = 0.0;  // x1, x2: solution at rows i+1, i+2
-      for (int i = n - 1; i >= 0; --i) {
+      i = n - 1;
+      for (; i + 1 >= kIB; i -= kIB) {  // rows i, i - 1, ..., i - kIB + 1
+        double yv[kIB], a0[kIB], a1[kIB], a2[kIB];
+#pragma unroll
+        for (int u = 0; u < kIB; ++u) {
+          const long r = static_cast<long>(i - u) * kk + tt;
+          yv[u] = y[r];
+          a0[u] = u0[r];
+          a1[u] = u1[r];
+          a2[u] = u2[r];
+        }
+#pragma unroll
+        for (int u = 0; u < kIB; ++u) {
+          const double xi = (yv[u] - a1[u] * x1 - a2[u] * x2) * a0[u];
+          y[static_cast<long>(i - u) * kk + tt] = xi;
+          nrm += xi * xi;
+          x2 = x1;
+          x1 = xi;
+        }
+      }
+      for (; i >= 0; --i) {
         const double xi = (y[i * kk + tt] - u1[i * kk + tt] * x1 - u2[i * kk + tt] * x2) * u0[i * kk + tt];
         y[i * kk + tt] = xi;
         nrm += xi * xi;
@@ -344,38 +460,55 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
     }
   }
 
-  // ---- back-transformation y = H_0 H_1 ... H_{n-3} z, one wavefront per
-  // vector, the vector held in registers (element lane + 64 q in zr[q])
-  for (int tt = wave; tt < k; tt += kNW) {
+  // ---- back-transformation y = H_0 H_1 ... H_{n-3} z.  The reflectors pass
+  // through LDS in chunks of kBT, loaded by the whole workgroup; each
+  // wavefront applies them, in order, to one vector held in registers
+  // (element lane + 64 q in zr[q]).
+  for (int t0 = 0; t0 < k; t0 += kNW) {
+    const int tt = t0 + wave;
+    const bool act = tt < k;  // uniform within the wavefront
     double zr[kSmallDense / 64];
 #pragma unroll
     for (int q = 0; q < kSmallDense / 64; ++q) {
       const int i = lane + 64 * q;
-      zr[q] = i < n ? Z[static_cast<long>(tt) * n + i] : 0.0;
+      zr[q] = (act && i < n) ? Z[static_cast<long>(tt) * n + i] : 0.0;
     }
-    for (int j = n - 3; j >= 0; --j) {
-      const double t = tau[j];
-      if (t == 0.0) continue;
-      const double* v = W + static_cast<long>(j) * n;  // v[i] for rows i > j
-      double s = 0.0;
+    for (int j1 = n - 3; j1 >= 0; j1 -= kBT) {
+      __syncthreads();  // the previous chunk is no longer read
+      for (int idx = tid; idx < kBT * kSmallDense; idx += kNT) {
+        const int q = idx / kSmallDense, i = idx % kSmallDense, j = j1 - q;
+        if (j >= 0 && i > j && i < n) Vs[q][i] = W[static_cast<long>(j) * n + i];
+      }
+      __syncthreads();
+      if (act) {
+        const int nq = min(kBT, j1 + 1);
+        for (int q = 0; q < nq; ++q) {
+          const int j = j1 - q;
+          const double t = tau[j];
+          if (t == 0.0) continue;
+          double s = 0.0;
+#pragma unroll
+          for (int c = 0; c < kSmallDense / 64; ++c) {
+            const int i = lane + 64 * c;
+            if (i > j && i < n) s += Vs[q][i] * zr[c];
+          }
+          s = t * wave_sum64(s);
+#pragma unroll
+          for (int c = 0; c < kSmallDense / 64; ++c) {
+            const int i = lane + 64 * c;
+            if (i > j && i < n) zr[c] -= s * Vs[q][i];
+          }
+        }
+      }
+    }
+    if (act) {
 #pragma unroll
       for (int q = 0; q < kSmallDense / 64; ++q) {
         const int i = lane + 64 * q;
-        if (i > j && i < n) s += v[i] * zr[q];
+        if (i < n) A[static_cast<long>(tt) * lda + i] = zr[q];
       }
-      s = t * wave_sum64(s);
-#pragma unroll
-      for (int q = 0; q < kSmallDense / 64; ++q) {
-        const int i = lane + 64 * q;
-        if (i > j && i < n) zr[q] -= s * v[i];
-      }
+      if (lane == 0) w[tt] = lam[tt];
     }
-#pragma unroll
-    for (int q = 0; q < kSmallDense / 64; ++q) {
-      const int i = lane + 64 * q;
-      if (i < n) A[static_cast<long>(tt) * lda + i] = zr[q];
-    }
-    if (lane == 0) w[tt] = lam[tt];
   }
   if (tid == 0) info[0] = 0;
 }
@@ -429,9 +562,13 @@ __global__ void __launch_bounds__(kNT) small_potrf_kernel(int n, double* __restr
 
 }  // namespace
 
-size_t small_syevx_scratch(int n, int k) { return static_cast<size_t>(n) * n + 7 * static_cast<size_t>(n) * k; }
+size_t small_syevx_scratch(int n, int k) {
+  return static_cast<size_t>(n) * n + 7 * static_cast<size_t>(n) * k + 3 * static_cast<size_t>(n);
+}
 
 void launch_small_syevx(hipStream_t st, int n, double* A, int lda, int k, double* w, double* scratch, int* info) {
+  double* dte = scratch + static_cast<long>(n) * n + static_cast<long>(n) * k;
+  hipLaunchKernelGGL(small_tridiag_kernel, dim3(1), dim3(kTT), 0, st, n, A, lda, scratch, dte);
   hipLaunchKernelGGL(small_syevx_kernel, dim3(1), dim3(kNT), 0, st, n, A, lda, k, w, scratch, info);
   SEQX_LAUNCH_CHECK();
 }

@@ -31,4 +31,56 @@ __device__ __forceinline__ double wave_sum64(double s) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
+// the value of x in lane src (src uniform across the wavefront)
+__device__ __forceinline__ double lane_value(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// the value of lane ^ M (ds_swizzle in bit mode for M < 32, which stays
+// within 32-lane halves; ds_bpermute for M = 32)
+template <int M>
+__device__ __forceinline__ double xor_shuffle(double x) {
+  const long long b = __double_as_longlong(x);
+  int lo = static_cast<int>(b), hi = static_cast<int>(b >> 32);
+  if constexpr (M < 32) {
+    constexpr int pattern = (M << 10) | 0x1f;  // and-mask 31, or-mask 0, xor-mask M
+    lo = __builtin_amdgcn_ds_swizzle(lo, pattern);
+    hi = __builtin_amdgcn_ds_swizzle(hi, pattern);
+  } else {
+    const int addr = ((threadIdx.x & 63) ^ 32) << 2;
+    lo = __builtin_amdgcn_ds_bpermute(addr, lo);
+    hi = __builtin_amdgcn_ds_bpermute(addr, hi);
+  }
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// one butterfly level: lanes paired by bit M keep H of their 2H values (the
+// upper lane the upper half) and add the partner's copy of them
+template <int M, int H>
+__device__ __forceinline__ void butterfly_level(double* x) {
+  const bool up = (threadIdx.x & M) != 0;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const double send = up ? x[k] : x[k + H];
+    const double keep = up ? x[k + H] : x[k];
+    x[k] = keep + xor_shuffle<M>(send);
+  }
+}
+
+// sums of 8 values per lane over the 64 lanes, in a fixed order: returns in
+// lane L the total of x[(L >> 3) & 7] (10 exchanges instead of 8 x 6)
+__device__ __forceinline__ double wave_sum8x64(double (&x)[8]) {
+  butterfly_level<32, 4>(x);
+  butterfly_level<16, 2>(x);
+  butterfly_level<8, 1>(x);
+  double s = x[0];
+  s += xor_shuffle<4>(s);
+  s += xor_shuffle<2>(s);
+  s += xor_shuffle<1>(s);
+  return s;
+}
+
 }  // namespace seqx
