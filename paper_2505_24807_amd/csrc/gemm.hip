@@ -49,7 +49,7 @@ __device__ __forceinline__ void store_elem(To* __restrict__ C, long ldc, long b,
   To* cp = C + static_cast<long>(row) * ldc + col;
   if (beta != 0.0) v += beta * static_cast<double>(*cp);
   if (EPI) {
-    const double* Vb = ep.V + (b % ep.kv) * ep.strideV;
+    const double* Vb = ep.V + ((b / ep.vdiv) % ep.kv) * ep.strideV;
     v += (ep.eps[ep.nocc + col] - ep.eps[row]) * Vb[static_cast<long>(row) * ldc + col];
   }
   *cp = static_cast<To>(v);

@@ -12,6 +12,7 @@ struct SigmaEpilogue {
   const double* V = nullptr;
   long strideV = 0;
   int kv = 1;
+  int vdiv = 1;  // batch b adds the diagonal term of V[(b / vdiv) % kv]
 };
 
 // Row-major semantics:  C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]

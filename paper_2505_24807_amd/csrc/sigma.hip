@@ -89,6 +89,14 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
     ep.V = Vc;
     ep.strideV = ov;
     ep.kv = kc;
+    // Outputs interleaved by vector ((A+B)V_I and (A-B)V_I half a row stride
+    // apart, as the Davidson basis keeps them): F+ and F- are built
+    // interleaved too, so the last product is one launch over all 2 kc
+    // matrices (twice the workgroups of a launch per half).
+    const bool merged = tdhf && os % 2 == 0 && out2 == out1 + os / 2;
+    const long sF = merged ? 2 * nn : nn;
+    const long f2off = merged ? nn : kc * nn;
+    if (merged) ep.vdiv = 2;
     if (!f32) {
       // T1_I (n x v) = C[:, :o] V_I
       dgemm(st, false, false, n, v, o, 1.0, m.C.p, n, 0, Vc, v, ov, 0.0, w.T1.p, v, nv, kc);
@@ -97,7 +105,7 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
       dgemm(st, false, true, kc * n, n, v, 1.0, w.T1.p, v, 0, m.C.p + o, n, 0, 0.0, w.R.p, n, 0, 1);
       SEQX_HIP(hipEventRecord(ev[2], st));
       if (tdhf)
-        build_G(m, kc, w.R.p, nn, w.F.p, w.F.p + kc * nn, nn, kTwo, 4.0, -2.0, -2.0, w.g, st);
+        build_G(m, kc, w.R.p, nn, w.F.p, w.F.p + f2off, sF, kTwo, 4.0, -2.0, -2.0, w.g, st);
       else
         build_G(m, kc, w.R.p, nn, w.F.p, static_cast<double*>(nullptr), nn, kSum, 2.0, -1.0, -1.0, w.g, st);
       SEQX_HIP(hipEventRecord(ev[3], st));
@@ -105,10 +113,14 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
       dgemm(st, false, false, nb * n, v, n, 1.0, w.F.p, n, 0, m.C.p + o, n, 0, 0.0, w.Z.p, v, 0, 1);
       SEQX_HIP(hipEventRecord(ev[4], st));
       // out_b (o x v) = C[:, :o]^T * Z_b + de o V_b
-      dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p, v, nv, 0.0, out1 + c0 * os, v, os, kc, &ep);
-      if (tdhf)
-        dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p + kc * nv, v, nv, 0.0, out2 + c0 * os, v, os, kc,
-              &ep);
+      if (merged) {
+        dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p, v, nv, 0.0, out1 + c0 * os, v, os / 2, nb, &ep);
+      } else {
+        dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p, v, nv, 0.0, out1 + c0 * os, v, os, kc, &ep);
+        if (tdhf)
+          dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, w.Z.p + kc * nv, v, nv, 0.0, out2 + c0 * os, v, os, kc,
+                &ep);
+      }
     } else {
       const float* C32 = m.C32.p;
       to_float(st, kc * ov, Vc, w.V32.p);
@@ -117,16 +129,20 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
       sgemm(st, false, true, kc * n, n, v, 1.0, w.T1s.p, v, 0, C32 + o, n, 0, 0.0, w.Rs.p, n, 0, 1);
       SEQX_HIP(hipEventRecord(ev[2], st));
       if (tdhf)
-        build_G(m, kc, w.Rs.p, nn, w.Fs.p, w.Fs.p + kc * nn, nn, kTwo, 4.0, -2.0, -2.0, w.g, st);
+        build_G(m, kc, w.Rs.p, nn, w.Fs.p, w.Fs.p + f2off, sF, kTwo, 4.0, -2.0, -2.0, w.g, st);
       else
         build_G(m, kc, w.Rs.p, nn, w.Fs.p, static_cast<float*>(nullptr), nn, kSum, 2.0, -1.0, -1.0, w.g, st);
       SEQX_HIP(hipEventRecord(ev[3], st));
       sgemm(st, false, false, nb * n, v, n, 1.0, w.Fs.p, n, 0, C32 + o, n, 0, 0.0, w.Zs.p, v, 0, 1);
       SEQX_HIP(hipEventRecord(ev[4], st));
-      sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, w.Zs.p, v, nv, 0.0, out1 + c0 * os, v, os, kc, &ep);
-      if (tdhf)
-        sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, w.Zs.p + kc * nv, v, nv, 0.0, out2 + c0 * os, v, os,
-                    kc, &ep);
+      if (merged) {
+        sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, w.Zs.p, v, nv, 0.0, out1 + c0 * os, v, os / 2, nb, &ep);
+      } else {
+        sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, w.Zs.p, v, nv, 0.0, out1 + c0 * os, v, os, kc, &ep);
+        if (tdhf)
+          sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, w.Zs.p + kc * nv, v, nv, 0.0, out2 + c0 * os, v,
+                      os, kc, &ep);
+      }
     }
     SEQX_HIP(hipEventRecord(ev[5], st));
     // algorithmic work of this chunk; d = bytes per stored element of the transforms
@@ -149,7 +165,7 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
     la[kPhaseFwd2] = 1;
     la[kPhaseG] = 1;
     la[kPhaseBwd1] = 1;
-    la[kPhaseBwd2] = tdhf ? 2 : 1;
+    la[kPhaseBwd2] = tdhf && !merged ? 2 : 1;
     w.timer.pending.push_back(ev);
     w.timer.pending_flops.push_back(fl);
     w.timer.pending_bytes.push_back(by);
