@@ -93,14 +93,14 @@ __global__ void sp2_init_kernel(int n, const double* __restrict__ F, const doubl
   X[idx] = ((i == j ? hi : 0.0) - F[idx]) / (hi - lo);
 }
 
-// out[0] = tr X, out[1] = tr X2 (single block, fixed order)
-__global__ void traces_kernel(int n, const double* __restrict__ X, const double* __restrict__ X2,
-                              double* __restrict__ out) {
+// out[0] = tr X, out[1] = tr X2 (single block, fixed order, FP64 sums)
+template <class T>
+__global__ void traces_kernel(int n, const T* __restrict__ X, const T* __restrict__ X2, double* __restrict__ out) {
   __shared__ double a[256], b[256];
   double s = 0.0, t = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
-    s += X[static_cast<long>(i) * n + i];
-    t += X2[static_cast<long>(i) * n + i];
+    s += static_cast<double>(X[static_cast<long>(i) * n + i]);
+    t += static_cast<double>(X2[static_cast<long>(i) * n + i]);
   }
   a[threadIdx.x] = s;
   b[threadIdx.x] = t;
@@ -118,12 +118,33 @@ __global__ void traces_kernel(int n, const double* __restrict__ X, const double*
   }
 }
 
+__global__ void axpby_f32_kernel(long n, float a, const float* __restrict__ x, float b, float* __restrict__ y) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void to_double_kernel(long n, const float* __restrict__ x, double* __restrict__ y) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i < n) y[i] = static_cast<double>(x[i]);
+}
+
+// FP32 purification steps stop once sum lambda (1 - lambda) is below this;
+// the FP64 steps that follow converge quadratically from there
+constexpr double kSp2Switch = 1e-2;
+// FP32 steps are used for n >= kSp2MixedMinN (where the products dominate)
+// while max |F P - P F| > kSp2MixedMaxErr, far above the ~1e-7 they leave
+constexpr int kSp2MixedMinN = 512;
+constexpr double kSp2MixedMaxErr = 1e-5;
+
 // Second-order spectral projection (SP2, Niklasson): starting from F mapped into
 // [0, 1], repeatedly apply X^2 or 2X - X^2, whichever keeps the trace closer to
 // the number of occupied orbitals, until X is idempotent.  P = 2 X is the
 // aufbau density of F (lowest `nocc` levels), the same as diagonalising F and
-// occupying its lowest orbitals, without the eigensolver.
-void sp2_density(hipStream_t st, int n, int nocc, const double* F, double* P, ScfWork& w) {
+// occupying its lowest orbitals, without the eigensolver.  With fp32_first the
+// steps run in FP32 (FP32 matrix-core products) until X is close to
+// idempotent and finish in FP64; the result then carries FP32 rounding
+// (about 1e-7 relative), which only the early SCF cycles can afford.
+void sp2_density(hipStream_t st, int n, int nocc, const double* F, double* P, ScfWork& w, bool fp32_first) {
   const long nn = static_cast<long>(n) * n;
   w.X2.ensure(nn);
   double* X = w.FP.p;  // free during purification
@@ -132,10 +153,32 @@ void sp2_density(hipStream_t st, int n, int nocc, const double* F, double* P, Sc
   hipLaunchKernelGGL(bounds_reduce_kernel, dim3(1), dim3(256), 0, st, n, w.red.p, w.scal.p);
   hipLaunchKernelGGL(sp2_init_kernel, dim3(ceil_div(nn, 256)), dim3(256), 0, st, n, F, w.scal.p, X);
   SEQX_LAUNCH_CHECK();
+  if (fp32_first) {
+    w.X32.ensure(nn);
+    w.X2_32.ensure(nn);
+    float* Xs = w.X32.p;
+    float* X2s = w.X2_32.p;
+    to_float(st, nn, X, Xs);
+    for (int it = 0; it < 200; ++it) {
+      sgemm(st, false, false, n, n, n, 1.0, Xs, n, 0, Xs, n, 0, 0.0, X2s, n, 0, 1);
+      hipLaunchKernelGGL(traces_kernel<float>, dim3(1), dim3(256), 0, st, n, Xs, X2s, w.scal.p + 2);
+      double tr[2];
+      SEQX_HIP(hipMemcpyAsync(tr, w.scal.p + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      SEQX_HIP(hipStreamSynchronize(st));
+      if (tr[0] - tr[1] < kSp2Switch) break;
+      if (std::fabs(tr[1] - nocc) < std::fabs(2.0 * tr[0] - tr[1] - nocc)) {
+        std::swap(Xs, X2s);  // X <- X^2
+      } else {
+        hipLaunchKernelGGL(axpby_f32_kernel, dim3(ceil_div(nn, 256)), dim3(256), 0, st, nn, -1.0f, X2s, 2.0f, Xs);
+      }
+    }
+    hipLaunchKernelGGL(to_double_kernel, dim3(ceil_div(nn, 256)), dim3(256), 0, st, nn, Xs, X);
+    SEQX_LAUNCH_CHECK();
+  }
   double e_prev[2] = {1e300, 1e300};
   for (int it = 0; it < 200; ++it) {
     dgemm(st, false, false, n, n, n, 1.0, X, n, 0, X, n, 0, 0.0, X2, n, 0, 1, nullptr);
-    hipLaunchKernelGGL(traces_kernel, dim3(1), dim3(256), 0, st, n, X, X2, w.scal.p + 2);
+    hipLaunchKernelGGL(traces_kernel<double>, dim3(1), dim3(256), 0, st, n, X, X2, w.scal.p + 2);
     double tr[2];
     SEQX_HIP(hipMemcpyAsync(tr, w.scal.p + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     SEQX_HIP(hipStreamSynchronize(st));
@@ -179,7 +222,7 @@ void run_scf(DeviceMolecule& m, const ScfOptions& opt, DenseSolver& ds, GWork& g
   guess_density(st, n, m.atom_of_ao.p, m.slot.p, m.elems, m.P.p);
   fock(m, m.P.p, w.G.p, w.F.p, gw, st);
   if (opt.purify) {
-    sp2_density(st, n, o, w.F.p, m.P.p, w);
+    sp2_density(st, n, o, w.F.p, m.P.p, w, n >= kSp2MixedMinN);
   } else {
     copy(st, w.CT.p, w.F.p, nn);
     ds.eigh(n, w.CT.p, n, m.eps.p);
@@ -214,7 +257,8 @@ void run_scf(DeviceMolecule& m, const ScfOptions& opt, DenseSolver& ds, GWork& g
       }
     }
     if (opt.purify) {
-      sp2_density(st, n, o, Fx, m.P.p, w);
+      // FP32 purification steps while the commutator is far above their rounding
+      sp2_density(st, n, o, Fx, m.P.p, w, n >= kSp2MixedMinN && err > kSp2MixedMaxErr);
     } else {
       copy(st, w.CT.p, Fx, nn);
       ds.eigh(n, w.CT.p, n, m.eps.p);

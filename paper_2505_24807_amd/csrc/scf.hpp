@@ -16,6 +16,7 @@ struct ScfOptions {
 
 struct ScfWork {
   DBuf<double> G, F, FP, E, CT, Fhist, Ehist, B, c, scal, red, X2;
+  DBuf<float> X32, X2_32;  // FP32 purification steps
 };
 
 // Fills m.C (row-major [mu][p]), m.eps, m.P; throws Error(kEScfNoConv) on failure.
