@@ -23,19 +23,6 @@ struct JacobiLds {
   double red[256];
 };
 
-// fixed-order sum over the NT threads (result in every thread): DPP sum
-// within each wavefront, then the wavefront sums in order
-template <int NT>
-__device__ inline double jacobi_block_sum(double v, double* red) {
-  v = wave_sum64(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = 0.0;
-  for (int q = 0; q < NT / 64; ++q) r += red[q];
-  __syncthreads();
-  return r;
-}
-
 // On entry L.A holds the symmetric n x n matrix (n <= kJacobiMax) and, with
 // q_given, L.Q an orthogonal matrix that the rotations accumulate onto
 // (otherwise the identity).  On exit L.Q holds the eigenvectors as columns, diag(L.A) the eigenvalues, and
@@ -63,8 +50,22 @@ __device__ inline void jacobi_lds(int n, JacobiLds& L, bool q_given = false) {
         tot += a2;
         if (i != lane) off += a2;
       }
-    off = jacobi_block_sum<NT>(off, L.red);
-    tot = jacobi_block_sum<NT>(tot, L.red);
+    {  // both sums in one pass: wavefront sums, then the wavefronts in order
+      off = wave_sum64(off);
+      tot = wave_sum64(tot);
+      if (lane == 0) {
+        L.red[2 * wv] = off;
+        L.red[2 * wv + 1] = tot;
+      }
+      __syncthreads();
+      off = 0.0;
+      tot = 0.0;
+      for (int q = 0; q < NT / 64; ++q) {
+        off += L.red[2 * q];
+        tot += L.red[2 * q + 1];
+      }
+      __syncthreads();
+    }
     if (!(off > 1e-28 * tot)) break;
     // pairs whose element is below this are left alone: together they stay
     // two orders under the stopping bar (threshold Jacobi)
@@ -145,16 +146,19 @@ __device__ inline void jacobi_lds(int n, JacobiLds& L, bool q_given = false) {
       __syncthreads();
     }
   }
-  if (threadIdx.x == 0) {  // ascending order (stable selection)
-    for (int i = 0; i < n; ++i) L.perm[i] = i;
-    for (int i = 0; i < n; ++i) {
-      int b = i;
-      for (int j = i + 1; j < n; ++j)
-        if (L.A[L.perm[j]][L.perm[j]] < L.A[L.perm[b]][L.perm[b]]) b = j;
-      const int t = L.perm[i];
-      L.perm[i] = L.perm[b];
-      L.perm[b] = t;
+  // ascending order, stable: eigenvalue i goes to the place given by how many
+  // eigenvalues lie below it (ties by index), all ranks at once.  perm starts
+  // as the identity, so it only ever holds valid indices (NaNs would collide).
+  for (int i = threadIdx.x; i < n; i += NT) L.perm[i] = i;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double li = L.A[i][i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = L.A[j][j];
+      r += (lj < li || (lj == li && j < i)) ? 1 : 0;
     }
+    if (r < n) L.perm[r] = i;
   }
   __syncthreads();
 }
