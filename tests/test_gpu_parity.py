@@ -42,6 +42,7 @@ MOLS = {
     "C20H22n": molecules.add_noise(molecules.polyene(20), 0.02, np.random.default_rng(20)),
     "C5H12": molecules.alkane(5),
     "H2": molecules.h2(0.74),
+    "H2O86": molecules.water_cluster(86, 7),  # n = 516: the SCF's first cycles purify with FP32 products
 }
 
 
@@ -103,6 +104,21 @@ def test_scf_ground_state(ctx, name):
     assert np.abs(res.F @ Cm - Cm * (eps / HA)[None, :]).max() < 1e-8
     st = job.stats()
     assert st.commutator <= 1e-10
+    job.free()
+
+
+def test_scf_fp32_purification_steps(ctx):
+    """(H2O)86, n = 516 >= 512: while the commutator is above 1e-5 the library's
+    SP2 purification squares in FP32 before finishing in FP64.  The converged
+    orbital energies and density must still be the oracle's FP64 SCF."""
+    sy, ints, res = oracle_of("H2O86")
+    job = job_of(ctx, "H2O86")
+    eps, Cm, P = job.scf_results()
+    n, o, v = job.dims()
+    assert (n, o) == (sy.nao, res.nocc) and n >= 512
+    assert np.abs(eps - res.eps * HA).max() < 1e-8
+    assert np.abs(P - res.P).max() < 1e-8
+    assert job.stats().commutator <= 1e-10
     job.free()
 
 
