@@ -128,6 +128,60 @@ __global__ void to_double_kernel(long n, const float* __restrict__ x, double* __
   if (i < n) y[i] = static_cast<double>(x[i]);
 }
 
+// SP2 with the decisions on the device (small n, where a host round trip per
+// step costs more than the step): one block forms tr X and tr X^2 and takes
+// the step's decision, exactly as the host loop below does; state[0] = done,
+// state[1] = branch (0: X <- X^2, 1: X <- 2X - X^2), state[2..3] = the
+// previous two values of sum lambda (1 - lambda).  Once done, the decision and
+// update kernels leave X alone, so steps launched past convergence are no-ops.
+__global__ void sp2_state_init_kernel(double* __restrict__ state) {
+  state[0] = 0.0;
+  state[1] = 0.0;
+  state[2] = 1e300;
+  state[3] = 1e300;
+}
+
+__global__ void sp2_decide_kernel(int n, int nocc, const double* __restrict__ X, const double* __restrict__ X2,
+                                  double* __restrict__ state) {
+  __shared__ double a[256], b[256];
+  double s = 0.0, t = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    s += X[static_cast<long>(i) * n + i];
+    t += X2[static_cast<long>(i) * n + i];
+  }
+  a[threadIdx.x] = s;
+  b[threadIdx.x] = t;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      a[threadIdx.x] += a[threadIdx.x + h];
+      b[threadIdx.x] += b[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0 || state[0] != 0.0) return;
+  const double tx = a[0], tx2 = b[0], e = tx - tx2;
+  if (e <= 1e-13 * n || (e < 1e-6 && e >= state[2])) {
+    state[0] = 1.0;
+    return;
+  }
+  state[2] = state[3];
+  state[3] = e;
+  state[1] = fabs(tx2 - nocc) < fabs(2.0 * tx - tx2 - nocc) ? 0.0 : 1.0;
+}
+
+__global__ void sp2_update_kernel(long nn, double* __restrict__ X, const double* __restrict__ X2,
+                                  const double* __restrict__ state) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i >= nn || state[0] != 0.0) return;
+  X[i] = state[1] == 0.0 ? X2[i] : -X2[i] + 2.0 * X[i];
+}
+
+// below this size the SP2 decisions stay on the device and the host checks
+// for convergence once every kSp2Group steps
+constexpr int kSp2DeviceMaxN = 512;
+constexpr int kSp2Group = 4;
+
 // FP32 purification steps stop once sum lambda (1 - lambda) is below this;
 // the FP64 steps that follow converge quadratically from there
 constexpr double kSp2Switch = 1e-2;
@@ -175,6 +229,25 @@ void sp2_density(hipStream_t st, int n, int nocc, const double* F, double* P, Sc
     hipLaunchKernelGGL(to_double_kernel, dim3(ceil_div(nn, 256)), dim3(256), 0, st, nn, Xs, X);
     SEQX_LAUNCH_CHECK();
   }
+  if (!fp32_first && n < kSp2DeviceMaxN) {
+    double* state = w.scal.p + 4;
+    hipLaunchKernelGGL(sp2_state_init_kernel, dim3(1), dim3(1), 0, st, state);
+    for (int it = 0; it < 200; it += kSp2Group) {
+      for (int g = 0; g < kSp2Group; ++g) {
+        dgemm(st, false, false, n, n, n, 1.0, X, n, 0, X, n, 0, 0.0, X2, n, 0, 1, nullptr);
+        hipLaunchKernelGGL(sp2_decide_kernel, dim3(1), dim3(256), 0, st, n, nocc, X, X2, state);
+        hipLaunchKernelGGL(sp2_update_kernel, dim3(ceil_div(nn, 256)), dim3(256), 0, st, nn, X, X2, state);
+      }
+      SEQX_LAUNCH_CHECK();
+      double done = 0.0;
+      SEQX_HIP(hipMemcpyAsync(&done, state, sizeof(double), hipMemcpyDeviceToHost, st));
+      SEQX_HIP(hipStreamSynchronize(st));
+      if (done != 0.0) break;
+    }
+    copy(st, P, X, nn);
+    axpby(st, nn, 0.0, X, 2.0, P);
+    return;
+  }
   double e_prev[2] = {1e300, 1e300};
   for (int it = 0; it < 200; ++it) {
     dgemm(st, false, false, n, n, n, 1.0, X, n, 0, X, n, 0, 0.0, X2, n, 0, 1, nullptr);
@@ -212,7 +285,7 @@ void run_scf(DeviceMolecule& m, const ScfOptions& opt, DenseSolver& ds, GWork& g
   w.Ehist.ensure(nd * nn);
   w.B.ensure(nd * nd);
   w.c.ensure(nd);
-  w.scal.ensure(4);
+  w.scal.ensure(8);
   w.red.ensure(std::max<size_t>(std::max<size_t>(1024, 2 * static_cast<size_t>(n)), dots_workspace(nd, nd, nn)));
   m.C.ensure(nn);
   m.P.ensure(nn);
