@@ -167,47 +167,62 @@ __global__ void guess_density_kernel(int nao, const int* __restrict__ atom_of_ao
 
 // Pulay DIIS: minimise |sum c_i e_i| subject to sum c_i = 1.  Gaussian
 // elimination with partial pivoting on the bordered (m+1) system.
+// Gauss-Jordan with partial pivoting on the bordered DIIS system, one row per
+// thread in LDS (each element sees the same operations, in the same order, as
+// a serial elimination would apply)
 __global__ void diis_kernel(int m, const double* __restrict__ B, int ldb, double* __restrict__ c) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double a[17][18];
+  __shared__ double a[17][19];
+  __shared__ double sc_s;
+  __shared__ int piv_s;
+  const int t = threadIdx.x;
   const int n = m + 1;
-  for (int i = 0; i < m; ++i) {
-    for (int j = 0; j < m; ++j) a[i][j] = B[i * ldb + j];
-    a[i][m] = -1.0;
-    a[i][n] = 0.0;
+  if (t < m) {
+    for (int j = 0; j < m; ++j) a[t][j] = B[t * ldb + j];
+    a[t][m] = -1.0;
+    a[t][n] = 0.0;
+  } else if (t == m) {
+    for (int j = 0; j < m; ++j) a[m][j] = -1.0;
+    a[m][m] = 0.0;
+    a[m][n] = -1.0;
   }
-  for (int j = 0; j < m; ++j) a[m][j] = -1.0;
-  a[m][m] = 0.0;
-  a[m][n] = -1.0;
+  __syncthreads();
   // scale the error block for conditioning
-  double sc = 0.0;
-  for (int i = 0; i < m; ++i) sc = fmax(sc, fabs(a[i][i]));
-  if (sc > 0)
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) a[i][j] /= sc;
+  if (t == 0) {
+    double sc = 0.0;
+    for (int i = 0; i < m; ++i) sc = fmax(sc, fabs(a[i][i]));
+    sc_s = sc;
+  }
+  __syncthreads();
+  if (sc_s > 0 && t < m)
+    for (int j = 0; j < m; ++j) a[t][j] /= sc_s;
+  __syncthreads();
   for (int col = 0; col < n; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < n; ++r)
-      if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
-    if (piv != col)
-      for (int j = 0; j <= n; ++j) {
-        const double t = a[col][j];
-        a[col][j] = a[piv][j];
-        a[piv][j] = t;
-      }
+    if (t == 0) {
+      int piv = col;
+      for (int r = col + 1; r < n; ++r)
+        if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+      piv_s = piv;
+    }
+    __syncthreads();
+    const int piv = piv_s;
+    if (piv != col && t <= n) {  // column t of the two rows
+      const double tmp = a[col][t];
+      a[col][t] = a[piv][t];
+      a[piv][t] = tmp;
+    }
+    __syncthreads();
     const double d = a[col][col];
-    if (d == 0.0) {
-      // singular: fall back to the newest matrix only
-      for (int i = 0; i < m; ++i) c[i] = (i == m - 1) ? 1.0 : 0.0;
+    if (d == 0.0) {  // singular (the same in every thread): fall back to the newest matrix only
+      if (t < m) c[t] = (t == m - 1) ? 1.0 : 0.0;
       return;
     }
-    for (int r = 0; r < n; ++r) {
-      if (r == col) continue;
-      const double f = a[r][col] / d;
-      for (int j = col; j <= n; ++j) a[r][j] -= f * a[col][j];
+    if (t < n && t != col) {
+      const double f = a[t][col] / d;
+      for (int j = col; j <= n; ++j) a[t][j] -= f * a[col][j];
     }
+    __syncthreads();
   }
-  for (int i = 0; i < m; ++i) c[i] = a[i][n] / a[i][i];
+  if (t < m) c[t] = a[t][n] / a[t][t];
 }
 
 }  // namespace
