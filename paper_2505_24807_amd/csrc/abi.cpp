@@ -10,6 +10,9 @@
 #include <deque>
 #include <fstream>
 #include <map>
+#include <atomic>
+#include <exception>
+#include <thread>
 #include <memory>
 #include <sstream>
 #include <string>
@@ -118,8 +121,8 @@ DeviceMolecule& scf_mol_of(const seqx_job* job, int32_t mol) {
   return m;
 }
 
-void setup_molecule(seqx_ctx* ctx, DeviceMolecule& m, int natoms, const int32_t* Z, const double* xyz) {
-  hipStream_t st = ctx->stream;
+void setup_molecule(seqx_ctx* ctx, DeviceMolecule& m, int natoms, const int32_t* Z, const double* xyz,
+                    hipStream_t st) {
   m.L = make_layout(natoms, Z, xyz, ctx->elems);
   const Layout& L = m.L;
   m.natoms = L.natoms;
@@ -174,6 +177,86 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   SEQX_HIP(hipEventElapsedTime(&ms, a, b));
   return ms;
+}
+
+// Molecules of a batch are independent.  One molecule's launches are small and
+// its SCF waits on the host every few purification steps, so a single stream
+// leaves the GPU mostly idle: from kPrepareParallelMin molecules on, a few
+// host threads, each with its own stream, dense solver and work buffers, take
+// molecules in turn.  Every molecule gets exactly the computation of the
+// sequential path.  Buffers come from hipMalloc here (with a caller allocator
+// the sequential path runs, so its callbacks are only entered from the calling
+// thread).  Times are summed over molecules.
+constexpr int kPrepareParallelMin = 4;
+constexpr int kPrepareThreads = 8;
+
+void prepare_parallel(seqx_ctx* ctx, seqx_job* job, int nmol, const int32_t* natoms, const int32_t* Z,
+                      const double* xyz, const ScfOptions& so, bool integrals_only) {
+  std::vector<size_t> offs(nmol, 0);
+  for (int m = 1; m < nmol; ++m) offs[m] = offs[m - 1] + natoms[m - 1];
+  std::vector<std::unique_ptr<DeviceMolecule>> mols(nmol);
+  std::vector<double> t_int(nmol, 0.0), t_scf(nmol, 0.0);
+  std::atomic<int> next{0};
+  const int nw = std::min(nmol, kPrepareThreads);
+  std::vector<std::exception_ptr> errs(nw);
+  SEQX_HIP(hipStreamSynchronize(ctx->stream));  // element data uploaded on the context stream
+  std::vector<std::thread> pool;
+  for (int wk = 0; wk < nw; ++wk)
+    pool.emplace_back([&, wk] {
+      try {
+        SEQX_HIP(hipSetDevice(ctx->device));
+        hipStream_t ws = nullptr;
+        SEQX_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+        struct StreamGuard {
+          hipStream_t s;
+          ~StreamGuard() {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+          }
+        } guard{ws};
+        hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+        struct EventGuard {
+          hipEvent_t* e;
+          ~EventGuard() {
+            for (int i = 0; i < 3; ++i)
+              if (e[i]) (void)hipEventDestroy(e[i]);
+          }
+        } eguard{e};
+        for (auto& ev : e) SEQX_HIP(hipEventCreate(&ev));
+        DenseSolver ds(ws);
+        GWork gw;
+        ScfWork sw;
+        for (int m = next.fetch_add(1); m < nmol; m = next.fetch_add(1)) {
+          std::unique_ptr<DeviceMolecule> dm(new DeviceMolecule());
+          setup_molecule(ctx, *dm, natoms[m], Z + offs[m], xyz + 3 * offs[m], ws);
+          SEQX_HIP(hipEventRecord(e[0], ws));
+          build_integrals(*dm, ws);
+          SEQX_HIP(hipEventRecord(e[1], ws));
+          if (!integrals_only) run_scf(*dm, so, ds, gw, sw, ws);
+          dm->scf_done = !integrals_only;
+          SEQX_HIP(hipEventRecord(e[2], ws));
+          SEQX_HIP(hipStreamSynchronize(ws));
+          t_int[m] = elapsed_ms(e[0], e[1]);
+          t_scf[m] = elapsed_ms(e[1], e[2]);
+          mols[m] = std::move(dm);
+        }
+      } catch (...) {
+        errs[wk] = std::current_exception();
+      }
+    });
+  for (auto& t : pool) t.join();
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+  double ti = 0.0, ts = 0.0;
+  for (int m = 0; m < nmol; ++m) {
+    ti += t_int[m];
+    ts += t_scf[m];
+    job->stats.scf_iterations += mols[m]->scf_iterations;
+    job->stats.commutator = std::max(job->stats.commutator, mols[m]->commutator);
+    job->mols.push_back(std::move(mols[m]));
+  }
+  job->stats.t_integrals_s = ti * 1e-3;
+  job->stats.t_scf_s = ts * 1e-3;
 }
 
 }  // namespace
@@ -435,6 +518,10 @@ seqx_status seqx_prepare(seqx_ctx* ctx, int32_t nmol, const int32_t* natoms, con
       integrals_only = opts->integrals_only != 0;
     }
     hipStream_t st = ctx->stream;
+    if (nmol >= kPrepareParallelMin && !ctx->allocator) {
+      prepare_parallel(ctx, job.get(), nmol, natoms, Z, xyz, so, integrals_only);
+      return;
+    }
     hipEvent_t e[3];
     for (auto& ev : e) SEQX_HIP(hipEventCreate(&ev));
     off = 0;
@@ -442,7 +529,7 @@ seqx_status seqx_prepare(seqx_ctx* ctx, int32_t nmol, const int32_t* natoms, con
     try {
       for (int m = 0; m < nmol; ++m) {
         std::unique_ptr<DeviceMolecule> dm(new DeviceMolecule());
-        setup_molecule(ctx, *dm, natoms[m], Z + off, xyz + 3 * off);
+        setup_molecule(ctx, *dm, natoms[m], Z + off, xyz + 3 * off, st);
         SEQX_HIP(hipEventRecord(e[0], st));
         build_integrals(*dm, st);
         SEQX_HIP(hipEventRecord(e[1], st));

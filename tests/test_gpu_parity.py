@@ -216,13 +216,25 @@ def test_small_subspace_collapse_path(ctx):
     job.free()
 
 
-def test_batched_prepare_equals_individual(ctx):
-    names = ["C2H4", "H2O3", "C10H12n"]
+@pytest.mark.parametrize("names", [["C2H4", "H2O3", "C10H12n"],
+                                   # five molecules: prepared concurrently on worker streams
+                                   ["C2H4", "H2O3", "C10H12n", "C5H12", "H2"]])
+def test_batched_prepare_equals_individual(ctx, names):
     mols = [MOLS[n] for n in names]
     natoms, Z, xyz = molecules.concat(mols)
     job = ctx.prepare(natoms, Z, xyz)
-    job.solve(theory=seqx.TDHF, nroots=3, tol=1e-7)
     for i, name in enumerate(names):
+        single = job_of(ctx, name)
+        # the same computation for each molecule, whichever path prepared it
+        for x, y in zip(job.scf_results(i), single.scf_results()):
+            assert np.array_equal(x, y)
+        single.free()
+    job.free()
+    # and the excitation energies of a batch equal the single-molecule ones
+    na3 = int(sum(natoms[:3]))
+    job = ctx.prepare(natoms[:3], Z[:na3], xyz[:na3])
+    job.solve(theory=seqx.TDHF, nroots=3, tol=1e-7)
+    for i, name in enumerate(names[:3]):
         single = job_of(ctx, name)
         single.solve(theory=seqx.TDHF, nroots=3, tol=1e-7)
         a, b = job.results(i), single.results()
