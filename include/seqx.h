@@ -204,7 +204,10 @@ seqx_status seqx_set_allocator(seqx_ctx* ctx, void* (*alloc)(size_t bytes, void*
 
 /* Integrals + RHF SCF for nmol molecules given as concatenated arrays:
  * natoms[nmol], Z[sum natoms], xyz_angstrom[sum natoms][3].  opts may be NULL.
- * The job keeps C, eps, the ERI tables and the core Hamiltonian on the device. */
+ * The job keeps C, eps, the ERI tables and the core Hamiltonian on the device.
+ * From four molecules on (and no caller allocator set) the molecules are
+ * prepared concurrently by library threads on internal streams, after the
+ * context's stream has drained; the call returns once all of them are done. */
 seqx_status seqx_prepare(seqx_ctx* ctx, int32_t nmol, const int32_t* natoms, const int32_t* Z,
                          const double* xyz_angstrom, const seqx_scf_opts* opts, seqx_job** out);
 void seqx_job_free(seqx_job* job);
