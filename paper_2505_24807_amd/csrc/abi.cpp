@@ -242,6 +242,7 @@ void prepare_parallel(seqx_ctx* ctx, seqx_job* job, int nmol, const int32_t* nat
         }
       } catch (...) {
         errs[wk] = std::current_exception();
+        next.store(nmol);  // the others stop after their current molecule
       }
     });
   for (auto& t : pool) t.join();

@@ -258,6 +258,13 @@ def test_error_paths(ctx):
         m = MOLS["C10H12n"]
         ctx.prepare([m.natoms], m.Z, m.xyz, max_iter=1, tol=1e-14)
     assert e.value.name == "E_SCF_NOCONV"
+    # the same failure inside a batch prepared by worker threads
+    natoms, Z, xyz = molecules.concat([MOLS[n] for n in ["C2H4", "H2O3", "C10H12n", "C5H12"]])
+    with pytest.raises(seqx.SeqxError) as e:
+        ctx.prepare(natoms, Z, xyz, max_iter=1, tol=1e-14)
+    assert e.value.name == "E_SCF_NOCONV"
+    ok = ctx.prepare(natoms, Z, xyz)  # the context stays usable
+    ok.free()
     fresh = seqx.Context(0)
     with pytest.raises(seqx.SeqxError) as e:
         fresh.prepare([2], [1, 1], [[0, 0, 0], [0, 0, 0.7]])
