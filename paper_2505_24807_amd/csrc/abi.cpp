@@ -201,6 +201,18 @@ void prepare_parallel(seqx_ctx* ctx, seqx_job* job, int nmol, const int32_t* nat
   std::vector<std::exception_ptr> errs(nw);
   SEQX_HIP(hipStreamSynchronize(ctx->stream));  // element data uploaded on the context stream
   std::vector<std::thread> pool;
+  // joins the started workers however this function is left (a thread that
+  // cannot be started stops the others after their current molecule)
+  struct Joiner {
+    std::vector<std::thread>& p;
+    std::atomic<int>& next;
+    int nmol;
+    ~Joiner() {
+      if (std::uncaught_exceptions() > 0) next.store(nmol);
+      for (auto& t : p)
+        if (t.joinable()) t.join();
+    }
+  } joiner{pool, next, nmol};
   for (int wk = 0; wk < nw; ++wk)
     pool.emplace_back([&, wk] {
       try {
