@@ -588,13 +588,15 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       itimer.mark(kDavCheck);
       d2h(h_rn.data(), w.rn.p, K, st);
       d2h(h_om.data(), om, K, st);
+      int h_info[2] = {0, 0};  // eigh, potrf
+      ds.info_async(h_info);
       SEQX_HIP(hipStreamSynchronize(st));
       float ms = 0.f;
       SEQX_HIP(hipEventElapsedTime(&ms, e0, e1));
       res.t_sigma_ms += ms;
-      if (tdhf && ds.info_potrf() != 0)
+      if (tdhf && h_info[1] != 0)
         throw Error(kEUnstable, "A-B projected matrix not positive definite (unstable reference)");
-      if (ds.info_eigh() != 0) throw Error(kEDevice, "subspace eigensolver failed");
+      if (h_info[0] != 0) throw Error(kEDevice, "subspace eigensolver failed");
       res.t_iter.push_back(now_s() - t0);
       res.omega_iter.push_back(h_om);
       if (log_enabled()) {

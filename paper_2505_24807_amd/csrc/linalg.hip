@@ -80,6 +80,10 @@ int DenseSolver::info_eigh() {
   return v;
 }
 
+void DenseSolver::info_async(int* host2) {
+  SEQX_HIP(hipMemcpyAsync(host2, info_.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
+}
+
 int DenseSolver::info_potrf() {
   int v = 0;
   SEQX_HIP(hipMemcpyAsync(&v, info_.p + 1, sizeof(int), hipMemcpyDeviceToHost, st_));

@@ -37,6 +37,9 @@ class DenseSolver {
   // device info word of the last eigh / potrf calls (0 = success); synchronises
   int info_eigh();
   int info_potrf();
+  // enqueue the copy of both info words (eigh, potrf) to host memory on the
+  // solver's stream, for a caller that synchronises the stream anyway
+  void info_async(int* host2);
 
  private:
   rocblas_handle h_ = nullptr;
