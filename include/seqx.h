@@ -240,6 +240,27 @@ seqx_status seqx_sigma(seqx_job* job, int32_t mol, int32_t theory, int32_t k, co
 seqx_status seqx_sigma_device(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* dV,
                               double* dout1, double* dout2, int32_t precision);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the products
+ * of seqx_sigma_device with every intermediate (AO matrices, transform
+ * intermediates, contraction work arrays) taken from one fixed workspace of
+ * SEQX_SIGMA_SCRATCH_BYTES per GPU, a device array of the library that each
+ * GPU it runs on holds until the process ends.  No allocator is called (no
+ * hipMalloc / hipFree, no caller allocator, no events); the vectors are
+ * processed in passes of as many as fit.  The caller passes device inputs and
+ * outputs as for seqx_sigma_device, ordered on the context stream.
+ * Limit: one vector's intermediates must fit the workspace: for n AOs,
+ * v virtual MOs and np same-atom AO pairs about 8 (3 n^2 + 3 n v) + 24 np
+ * bytes for TDHF in FP64 (CIS: 8 (2 n^2 + 2 n v) + 24 np) and half of the
+ * matrix terms in FP32, so a 1980-AO molecule still runs one vector per pass
+ * in FP64.  Beyond it the call returns SEQX_E_BUFSIZE and writes nothing.  Every call on one GPU shares that GPU's
+ * workspace, which keeps the last call's contents (every element is written
+ * before it is read): calls that overlap in time on one GPU, from any
+ * context or stream, race and must be ordered by the caller. */
+#define SEQX_SIGMA_SCRATCH_BYTES (128u << 20)
+seqx_status seqx_sigma_device_noalloc(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* dV,
+                                      double* dout1, double* dout2, int32_t precision);
+
 /* Davidson for every molecule of the job (seqx_solve_opts above). */
 seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts);
 

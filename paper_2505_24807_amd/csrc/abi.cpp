@@ -31,6 +31,7 @@
 
 namespace seqx {
 thread_local const DeviceAllocator* g_device_allocator = nullptr;
+static_assert(SEQX_SIGMA_SCRATCH_BYTES == kSigmaScratchBytes, "workspace size of the header and the library differ");
 }  // namespace seqx
 
 using namespace seqx;
@@ -311,6 +312,8 @@ seqx_status seqx_create(int device, void* hip_stream, seqx_ctx** out) {
   const seqx_status s = guarded(ctx.get(), [&] {
     ctx->d_elems.alloc(kNumSlots);
     ctx->ds.reset(new DenseSolver(ctx->stream));
+    // device address of this GPU's fixed sigma workspace (no-allocation entry point)
+    sigma_scratch_setup(device);
   });
   if (s != SEQX_OK) {
     g_noctx_err = ctx->err;
@@ -658,6 +661,18 @@ seqx_status seqx_sigma_device(seqx_job* job, int32_t mol, int32_t theory, int32_
     if (k <= 0 || !dV || !dout1 || (theory == SEQX_TDHF && !dout2)) throw Error(kEArg, "bad sigma arguments");
     check_precision(precision);
     sigma_build(m, theory, k, dV, dout1, dout2, job->dw.sig, job->ctx->stream, 32, 0, precision);
+  });
+}
+
+seqx_status seqx_sigma_device_noalloc(seqx_job* job, int32_t mol, int32_t theory, int32_t k, const double* dV,
+                                      double* dout1, double* dout2, int32_t precision) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    DeviceMolecule& m = scf_mol_of(job, mol);
+    if (theory != SEQX_CIS && theory != SEQX_TDHF) throw Error(kEArg, "theory must be CIS or TDHF");
+    if (k <= 0 || !dV || !dout1 || (theory == SEQX_TDHF && !dout2)) throw Error(kEArg, "bad sigma arguments");
+    check_precision(precision);
+    sigma_build_noalloc(m, theory, k, dV, dout1, dout2, job->ctx->stream, precision);
   });
 }
 

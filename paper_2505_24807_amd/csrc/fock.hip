@@ -213,46 +213,66 @@ void launch_pairs(const DeviceMolecule& m, int k, const TR* R, long sR, TF* F1, 
 
 template <class TR, class TF>
 void build_G_any(const DeviceMolecule& m, int k, const TR* R, long sR, TF* F1, TF* F2, long sF, GMode mode, double cJ,
-                 double cK, double cKa, GWork& w, hipStream_t st) {
+                 double cK, double cKa, double* r, double* J, double* ws, hipStream_t st) {
   const int np = m.np, n = m.nao;
   if (k <= 0) return;
-  w.r.ensure(static_cast<size_t>(k) * np);
-  w.J.ensure(static_cast<size_t>(k) * np);
   hipLaunchKernelGGL(pack_kernel<TR>, dim3(ceil_div(np, 256), k), dim3(256), 0, st, k, np, n, m.pi_mu.p, m.pi_nu.p, R,
-                     sR, w.r.p);
+                     sR, r);
   SEQX_LAUNCH_CHECK();
   // J[k][np] = r (k x np) * W (W symmetric): split-K inner products, so that a
   // handful of vectors still spreads over hundreds of workgroups; FP64 whatever
   // the storage type of R and F
-  w.ws.ensure(dots_workspace(k, np, np));
-  dots(st, k, w.r.p, np, np, m.W.p, np, np, w.J.p, np, w.ws.p);
+  dots(st, k, r, np, np, m.W.p, np, np, J, np, ws);
   const dim3 dgrid(ceil_div(m.natoms, 64), k);
   if (mode == kTwo) {
     hipLaunchKernelGGL((diag_block_kernel<kTwo, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, np, m.slot.p, m.ao_off.p,
-                       m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
+                       m.pi_off.p, m.elems, J, R, sR, n, F1, F2, sF, cJ, cK, cKa);
     launch_pairs<kTwo>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
   } else if (mode == kSum) {
     hipLaunchKernelGGL((diag_block_kernel<kSum, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, np, m.slot.p, m.ao_off.p,
-                       m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
+                       m.pi_off.p, m.elems, J, R, sR, n, F1, F2, sF, cJ, cK, cKa);
     launch_pairs<kSum>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
   } else {
     hipLaunchKernelGGL((diag_block_kernel<kSymm, TR, TF>), dgrid, dim3(64), 0, st, m.natoms, np, m.slot.p, m.ao_off.p,
-                       m.pi_off.p, m.elems, w.J.p, R, sR, n, F1, F2, sF, cJ, cK, cKa);
+                       m.pi_off.p, m.elems, J, R, sR, n, F1, F2, sF, cJ, cK, cKa);
     launch_pairs<kSymm>(m, k, R, sR, F1, F2, sF, cK, cKa, st);
   }
   SEQX_LAUNCH_CHECK();
 }
 
+template <class TR, class TF>
+void build_G_owned(const DeviceMolecule& m, int k, const TR* R, long sR, TF* F1, TF* F2, long sF, GMode mode,
+                   double cJ, double cK, double cKa, GWork& w, hipStream_t st) {
+  if (k <= 0) return;
+  const int np = m.np;
+  w.r.ensure(static_cast<size_t>(k) * np);
+  w.J.ensure(static_cast<size_t>(k) * np);
+  w.ws.ensure(dots_workspace(k, np, np));
+  build_G_any<TR, TF>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, w.r.p, w.J.p, w.ws.p, st);
+}
+
 }  // namespace
+
+size_t g_work_doubles(int k, int np) { return 2 * static_cast<size_t>(k) * np + dots_workspace(k, np, np); }
 
 void build_G(const DeviceMolecule& m, int k, const double* R, long sR, double* F1, double* F2, long sF, GMode mode,
              double cJ, double cK, double cKa, GWork& w, hipStream_t st) {
-  build_G_any<double, double>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, w, st);
+  build_G_owned<double, double>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, w, st);
 }
 
 void build_G(const DeviceMolecule& m, int k, const float* R, long sR, float* F1, float* F2, long sF, GMode mode,
              double cJ, double cK, double cKa, GWork& w, hipStream_t st) {
-  build_G_any<float, float>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, w, st);
+  build_G_owned<float, float>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, w, st);
+}
+
+void build_G(const DeviceMolecule& m, int k, const double* R, long sR, double* F1, double* F2, long sF, GMode mode,
+             double cJ, double cK, double cKa, double* r, double* J, double* ws, hipStream_t st) {
+  build_G_any<double, double>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, r, J, ws, st);
+}
+
+void build_G(const DeviceMolecule& m, int k, const float* R, long sR, float* F1, float* F2, long sF, GMode mode,
+             double cJ, double cK, double cKa, double* r, double* J, double* ws, hipStream_t st) {
+  build_G_any<float, float>(m, k, R, sR, F1, F2, sF, mode, cJ, cK, cKa, r, J, ws, st);
 }
 
 }  // namespace seqx

@@ -26,4 +26,15 @@ void build_G(const DeviceMolecule& m, int k, const double* R, long sR, double* F
 void build_G(const DeviceMolecule& m, int k, const float* R, long sR, float* F1, float* F2, long sF, GMode mode,
              double cJ, double cK, double cKa, GWork& w, hipStream_t st);
 
+// Work arrays of one contraction of k densities, in doubles: the packed
+// densities r [k][np], the Coulomb values J [k][np] and the split-K partial sums.
+size_t g_work_doubles(int k, int np);
+// The same two contractions with caller-provided work arrays (r, J: k*np
+// doubles each; ws: the rest of g_work_doubles(k, np)).  Every element of
+// each is written before it is read, so their previous contents do not matter.
+void build_G(const DeviceMolecule& m, int k, const double* R, long sR, double* F1, double* F2, long sF, GMode mode,
+             double cJ, double cK, double cKa, double* r, double* J, double* ws, hipStream_t st);
+void build_G(const DeviceMolecule& m, int k, const float* R, long sR, float* F1, float* F2, long sF, GMode mode,
+             double cJ, double cK, double cKa, double* r, double* J, double* ws, hipStream_t st);
+
 }  // namespace seqx

@@ -50,6 +50,20 @@ struct SigmaWork {
 void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
                  SigmaWork& w, hipStream_t st, int chunk = 32, long out_stride = 0, int precision = kPrecFP64);
 
+// No-allocation variant: the same products with every intermediate taken
+// from one fixed device workspace per GPU (kSigmaScratchBytes), in chunks of
+// as many vectors as fit.  Calls no allocator.  Consecutive calls on one GPU
+// share the workspace, so calls that overlap in time on one GPU race.
+// Throws Error(kEBufSize) when one vector's intermediates exceed the workspace.
+constexpr size_t kSigmaScratchBytes = static_cast<size_t>(128) << 20;
+// Device address of the workspace on `device` (the current device), looked up
+// once per device; called from context creation.
+void sigma_scratch_setup(int device);
+// Vectors per pass that fit the workspace (0: not even one).
+int sigma_scratch_max_chunk(const DeviceMolecule& m, int theory, int precision);
+void sigma_build_noalloc(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
+                         hipStream_t st, int precision);
+
 // AO transition densities T_I = C_occ X_I C_virt^T for k amplitude vectors (no G, no back-transform).
 void forward_transform(const DeviceMolecule& m, int k, const double* X, double* T, SigmaWork& w, hipStream_t st);
 

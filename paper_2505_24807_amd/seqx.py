@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "seqx_sigma": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _D, _D, _D, C.c_int32]),
         "seqx_sigma_device": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_int32]),
+        "seqx_sigma_device_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                                C.c_void_p, C.c_void_p, C.c_int32]),
         "seqx_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts)]),
         "seqx_results": (C.c_int, [C.c_void_p, C.c_int32, _D, _D, _D, _D, _D]),
         "seqx_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
@@ -343,6 +345,14 @@ class Job:
                                                C.c_void_p(out1.data_ptr()),
                                                C.c_void_p(out2.data_ptr()) if out2 is not None else None,
                                                precision))
+
+    def sigma_device_noalloc(self, V, out1, out2=None, theory=TDHF, mol=0, precision=FP64):
+        """As sigma_device, with the library's fixed per-GPU workspace instead of allocations."""
+        k = V.shape[0]
+        self._check(self.lib.seqx_sigma_device_noalloc(self.h, mol, theory, k, C.c_void_p(V.data_ptr()),
+                                                       C.c_void_p(out1.data_ptr()),
+                                                       C.c_void_p(out2.data_ptr()) if out2 is not None else None,
+                                                       precision))
 
     def features(self, mol=0):
         _, o, v = self.dims(mol)
