@@ -73,6 +73,142 @@ def test_two_centre_long_range_multipoles():
     assert abs(qp - 1.0) < 1e-3
 
 
+def test_square_quadrupole_dipole_long_range():
+    """(p_x p_z | s p_x) far apart: the xz square quadrupole on A (Q_xz = 3 D2_A^2) in
+    the field of the s-p_x dipole on B (D1_B) at R along z: + 3 D2_A^2 D1_B / R^4."""
+    C = model.make_element(6, PR[6])
+    O = model.make_element(8, PR[8])
+    for R in (400.0, 800.0):
+        T = integrals.local_two_centre(C, O, np.array([R]))[0]
+        ratio = T[1, 3, 0, 1] * R ** 4 / (3 * C.D2 ** 2 * O.D1)
+        assert abs(ratio - 1.0) < 1e-3
+        # the y z quadrupole couples to the s-p_y dipole in the same way; x z does not see p_y
+        assert abs(T[2, 3, 0, 2] * R ** 4 / (3 * C.D2 ** 2 * O.D1) - 1.0) < 1e-3
+        assert abs(T[1, 3, 0, 2]) < 1e-18
+
+
+# STO moments of same-atom products by three-dimensional quadrature: radial
+# Gauss-Laguerre (exact for a polynomial times the exponential), Gauss-Legendre
+# in cos(theta) and a uniform rule in phi (exact for the low-order polynomials
+# in x/r, y/r, z/r that appear here).
+_XLAG, _WLAG = np.polynomial.laguerre.laggauss(40)
+_XLEG, _WLEG = np.polynomial.legendre.leggauss(16)
+_NPHI = 32
+
+
+def _sto_product_moments(el):
+    """Charge S, dipole d[k] and second moments m2[i][j] (about the nucleus) of every
+    product of the atom's normalised real STOs s, p_x, p_y, p_z: arrays [4, 4], [3, 4, 4], [3, 3, 4, 4]."""
+    ct, wt = _XLEG, _WLEG
+    st = np.sqrt(1 - ct * ct)
+    ph = 2 * np.pi * np.arange(_NPHI) / _NPHI
+    ux = (st[:, None] * np.cos(ph)[None, :]).ravel()
+    uy = (st[:, None] * np.sin(ph)[None, :]).ravel()
+    uz = np.repeat(ct, _NPHI)
+    wa = np.repeat(wt, _NPHI) * (2 * np.pi / _NPHI)
+    ang = [np.full_like(ux, 1.0 / np.sqrt(4 * np.pi))] + [np.sqrt(3.0 / (4 * np.pi)) * u for u in (ux, uy, uz)]
+    zeta = [el.zs, el.zp, el.zp, el.zp]
+    S = np.zeros((4, 4))
+    d = np.zeros((3, 4, 4))
+    m2 = np.zeros((3, 3, 4, 4))
+    u = (ux, uy, uz)
+    for a in range(4):
+        for b in range(4):
+            za, zb = zeta[a], zeta[b]
+            s = za + zb
+            r = _XLAG / s
+            # radial parts without the exponentials; the Laguerre weight carries exp(-s r)
+            na = (2 * za) ** (el.n + 0.5) / np.sqrt(factorial(2 * el.n))
+            nb = (2 * zb) ** (el.n + 0.5) / np.sqrt(factorial(2 * el.n))
+            rad = na * nb * r ** (2 * el.n - 2) * r * r * _WLAG / s     # times r^2 dr
+            fa = ang[a] * ang[b] * wa
+            S[a, b] = np.sum(rad) * np.sum(fa)
+            for i in range(3):
+                d[i, a, b] = np.sum(rad * r) * np.sum(fa * u[i])
+                for j in range(3):
+                    m2[i, j, a, b] = np.sum(rad * r * r) * np.sum(fa * u[i] * u[j])
+    return S, d, m2
+
+
+@pytest.mark.parametrize("Z", [6, 8])
+def test_multipole_charges_match_sto_moments(Z):
+    """Each same-atom product's point-charge set carries the STO product's charge,
+    dipole and traceless quadrupole, signs included (MNDO-family multipole model):
+    a flipped or misplaced charge of any of the ten distributions fails here."""
+    el = model.make_element(Z, PR[Z])
+    S, d, m2 = _sto_product_moments(el)
+    assert np.abs(S - np.eye(4)).max() < 1e-12
+    for a in range(4):
+        for b in range(a, 4):
+            pcs = integrals.point_charges(el, a, b)
+            q = sum(c for c, _, _ in pcs)
+            dip = sum(c * r for c, r, _ in pcs)
+            quad = sum(c * (3 * np.outer(r, r) - np.dot(r, r) * np.eye(3)) for c, r, _ in pcs)
+            quad_sto = 3 * m2[:, :, a, b] - np.trace(m2[:, :, a, b]) * np.eye(3)
+            assert abs(q - S[a, b]) < 1e-12, (a, b)
+            assert np.abs(dip - d[:, a, b]).max() < 1e-12, (a, b)
+            assert np.abs(quad - quad_sto).max() < 1e-11, (a, b)
+    # the s-p dipoles are the nonzero ones, of length D1 and positive along +axis
+    assert d[0, 0, 1] > 0 and abs(d[0, 0, 1] - el.D1) < 1e-12
+
+
+@pytest.mark.parametrize("Z", [6, 8])
+def test_dipole_integrals_match_sto_quadrature(Z):
+    """<mu|r|nu> on one atom at R_A equals R_A <mu|nu> + <mu|r - R_A|nu> from the
+    quadrature above: the s-p term (sign and size) and the shift by the position."""
+    el = model.make_element(Z, PR[Z])
+    S, d, _ = _sto_product_moments(el)
+    RA = np.array([0.37, -1.21, 2.05])
+    sy = model.make_system(np.array([Z, 1, 1]), np.vstack([RA, RA + [0.0, 30.0, 0.0], RA + [0.0, -30.0, 0.0]])
+                           * model.BOHR_ANG, PR)
+    D = excited.dipole_integrals(sy)
+    a = sy.aos(0)
+    for k in range(3):
+        ref = RA[k] * S + d[k]
+        assert np.abs(D[k][np.ix_(a, a)] - ref).max() < 1e-11
+
+
+# ---------------------------------------------------------------- core attraction
+
+def test_core_attraction_far_heteronuclear():
+    """C and O far apart: each atom's s level is lowered by the other's core charge
+    over the distance, -Z'_B / R (C: Z' = 4, O: Z' = 6)."""
+    R = 1e4
+    sy = model.make_system(np.array([6, 8]), np.array([[0.0, 0.0, 0.0], [0.0, 0.0, R * model.BOHR_ANG]]), PR)
+    ints = integrals.build(sy)
+    H = scf.core_hamiltonian(sy, ints)
+    c, o = sy.aos(0)[0], sy.aos(1)[0]
+    assert abs((H[c, c] - sy.el(0).Uss) * R / -6.0 - 1.0) < 1e-6
+    assert abs((H[o, o] - sy.el(1).Uss) * R / -4.0 - 1.0) < 1e-6
+
+
+def test_separated_fragments_are_independent():
+    """C2H4 and H2O 10^4 bohr apart: every ground- and excited-state quantity is
+    the union of the two molecules'.  For neutral fragments the core attraction
+    of one by the other's cores cancels the Coulomb repulsion of its electrons,
+    which pins the core charges and the sign of the attraction against J."""
+    a, b = molecules.ethylene(), molecules.water_cluster(1, 3)
+    D = 1e4 * model.BOHR_ANG
+    dimer = molecules.Molecule(np.concatenate([a.Z, b.Z]), np.vstack([a.xyz, b.xyz + [0.0, 0.0, D]]), "dimer")
+    K = 6
+    out = {}
+    for key, mol in (("a", a), ("b", b), ("ab", dimer)):
+        sy, ints, res = _run(mol)
+        o, v = res.nocc, sy.nao - res.nocc
+        A, B = excited.build_AB(ints, res.eps, res.C, o)
+        c = excited.cis_dense(A, K, o, v)
+        t = excited.tdhf_dense(A, B, K, o, v)
+        _, f = excited.transition_properties(sy, res.C, o, t)
+        out[key] = (res.eps, c.omega, t.omega, f)
+    eps_u = np.sort(np.concatenate([out["a"][0], out["b"][0]]))
+    assert np.abs(out["ab"][0] - eps_u).max() < 1e-7
+    for idx in (1, 2):
+        u = np.sort(np.concatenate([out["a"][idx], out["b"][idx]]))[:K]
+        assert np.abs(out["ab"][idx] - u).max() < 1e-9
+    fu = np.concatenate([out["a"][3], out["b"][3]])[np.argsort(np.concatenate([out["a"][2], out["b"][2]]))][:K]
+    assert np.abs(out["ab"][3] - fu).max() < 1e-9
+
+
 def test_one_centre_tensor_rotation_invariant():
     el = model.make_element(8, PR[8])
     T = integrals.one_centre(el)
