@@ -216,7 +216,7 @@ def batched_c4(ctx, steps, loop=True):
         n_loop = job.stats().n_sigma
     job.free()
     fl, tsig = st.batched_sigma_flops, st.t_sigma_s
-    return {"workload": "512 uneven molecules (polyenes, alkanes, water clusters; 6-62 atoms, n 12-142), seed 512, "
+    return {"workload": "512 uneven molecules (polyenes, alkanes, water clusters; 6-60 atoms, n 12-142), seed 512, "
                         "CIS 5 roots, residual tol 1e-5 Eh",
             "batched_s": round(t_b, 4), "batched_sigma_vectors_per_s": round(st.n_sigma / t_b, 1),
             "batched_iterations": st.dav_iterations, "batched_n_sigma": st.n_sigma,

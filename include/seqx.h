@@ -202,7 +202,9 @@ seqx_status seqx_load_params(seqx_ctx* ctx, seqx_method method, const char* json
 seqx_status seqx_set_allocator(seqx_ctx* ctx, void* (*alloc)(size_t bytes, void* user),
                                void (*release)(void* ptr, void* user), void* user);
 
-/* Integrals + RHF SCF for nmol molecules given as concatenated arrays:
+/* Integrals + RHF SCF (paper: ground-state subsection, Eq. 1 with S = I; the
+ * two-centre integrals are computed once before the SCF and kept, as in the
+ * GPU-implementation subsection) for nmol molecules given as concatenated arrays:
  * natoms[nmol], Z[sum natoms], xyz_angstrom[sum natoms][3].  opts may be NULL.
  * The job keeps C, eps, the ERI tables and the core Hamiltonian on the device.
  * From four molecules on (and no caller allocator set) the molecules are
@@ -264,7 +266,9 @@ seqx_status seqx_sigma_device_noalloc(seqx_job* job, int32_t mol, int32_t theory
 /* Davidson for every molecule of the job (seqx_solve_opts above). */
 seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts);
 
-/* Results of molecule `mol` after seqx_solve: omega_eV[K], X[K][nocc][nvirt],
+/* Results of molecule `mol` after seqx_solve (the K lowest roots of Eq. 2 or
+ * Eq. 7; transition dipoles and oscillator strengths as used for the spectra
+ * in the results section): omega_eV[K], X[K][nocc][nvirt],
  * Y[K][nocc][nvirt] (zero for CIS), f[K] oscillator strengths,
  * mu[K][3] transition dipoles (atomic units).  Any output may be NULL. */
 seqx_status seqx_results(const seqx_job* job, int32_t mol, double* omega_eV, double* X, double* Y,
@@ -281,7 +285,8 @@ seqx_status seqx_history(const seqx_job* job, int32_t mol, int32_t cap, int32_t*
                          double* omega_eV);
 
 /* ---- Learned starting space -------------------------------------------------
- * Per pair i -> a, 12 features (hartree, bohr): gap, eps_HOMO - eps_i,
+ * The paper's closing outlook lists machine-learned initial guesses for the
+ * Davidson iteration; these calls build one.  Per pair i -> a, 12 features (hartree, bohr): gap, eps_HOMO - eps_i,
  * eps_a - eps_LUMO, sum_A q_A^2, the four largest |q_A| (q_A: transition
  * Mulliken charge on atom A), sum_A g_A q_A^2, sum_A g_A p_A^i p_A^a (p: orbital
  * populations, g_A = (s_A s_A|s_A s_A)), the distance of the two orbital

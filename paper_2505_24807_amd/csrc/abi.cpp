@@ -776,8 +776,9 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
         d.guess = nullptr;
         d.nguess = 0;
       }
-      // subspace cap from the memory budget: V, (A+B)V, (A-B)V rows of nov doubles
-      if (d.max_sub <= 0) {
+      // subspace cap from the memory budget, per molecule: V, (A+B)V, (A-B)V rows of nov doubles
+      DavOptions dm = d;
+      if (dm.max_sub <= 0) {
         size_t budget = opts->mem_budget_bytes;
         if (budget == 0) {
           size_t fr = 0, tot = 0;
@@ -786,9 +787,9 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
         }
         const size_t per = static_cast<size_t>(opts->theory == SEQX_TDHF ? 3 : 2) * nov * sizeof(double);
         const long cap_mem = static_cast<long>(budget / std::max<size_t>(per, 1));
-        d.max_sub = static_cast<int>(std::max<long>(std::min<long>(cap_mem, 20L * opts->nroots + 40), 1));
+        dm.max_sub = static_cast<int>(std::max<long>(std::min<long>(cap_mem, 20L * opts->nroots + 40), 1));
       }
-      DavResult r = davidson(m, d, *job->ctx->ds, job->dw, st);
+      DavResult r = davidson(m, dm, *job->ctx->ds, job->dw, st);
       m.hist_t = r.t_iter;
       m.hist_omega.clear();
       for (const auto& w : r.omega_iter) m.hist_omega.insert(m.hist_omega.end(), w.begin(), w.end());

@@ -588,6 +588,8 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       itimer.mark(kDavCheck);
       d2h(h_rn.data(), w.rn.p, K, st);
       d2h(h_om.data(), om, K, st);
+      double h_w2min = 0.0;  // lowest eigenvalue of the projected problem (TDHF: omega^2)
+      d2h(&h_w2min, w.w2.p, 1, st);
       int h_info[2] = {0, 0};  // eigh, potrf
       ds.info_async(h_info);
       SEQX_HIP(hipStreamSynchronize(st));
@@ -597,6 +599,10 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       if (tdhf && h_info[1] != 0)
         throw Error(kEUnstable, "A-B projected matrix not positive definite (unstable reference)");
       if (h_info[0] != 0) throw Error(kEDevice, "subspace eigensolver failed");
+      // omega^2 <= 0: the projected A+B is not positive definite (L^T M+ L has
+      // the inertia of M+), an imaginary or zero TDHF root
+      if (tdhf && !(h_w2min > 0.0))
+        throw Error(kEUnstable, "A+B projected matrix not positive definite (unstable reference)");
       res.t_iter.push_back(now_s() - t0);
       res.omega_iter.push_back(h_om);
       if (log_enabled()) {

@@ -7,6 +7,8 @@
 // each wavefront accumulates 16x16 tiles.  Operands: lane l holds A[l%16][l/16]
 // and B[l/16][l%16].  Accumulator register r of lane l holds column l%16 and
 // row l/16 + 4r (f64) or row 4(l/16) + r (f32) -- both measured on gfx950.
+#include <algorithm>
+
 #include "gemm.hpp"
 
 namespace seqx {
@@ -520,8 +522,12 @@ void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   SigmaEpilogue ep;
   if (epi) ep = *epi;
   if constexpr (sizeof(T) == 8 && sizeof(To) == 8) {
-    if (!ta && !tb && !epi && batch == 1 && M <= 48 && N >= 4096) {
-      skinny_combine(st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (!ta && !tb && !epi && batch == 1 && N >= 4096 && (M <= 48 || (M <= 256 && N >= 64L * M))) {
+      // combinations of a long basis: passes of at most 48 output rows, each
+      // reading B once
+      for (int r0 = 0; r0 < M; r0 += 48)
+        skinny_combine(st, std::min(48, M - r0), N, K, alpha, A + static_cast<long>(r0) * lda, lda, B, ldb, beta,
+                       C + static_cast<long>(r0) * ldc, ldc);
       return;
     }
   }

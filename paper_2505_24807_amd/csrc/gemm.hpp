@@ -39,12 +39,14 @@ void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
               const double* B, long ldb, double beta, double* C, long ldc);
 
 // C[m][x] = alpha sum_s A[m][s] B[s][x] + beta C[m][x] for M <= 48 rows
+// (dgemm makes passes of 48 rows for more)
 // (row-major, leading dimensions lda, ldb, ldc); beta = 0 does not read C.
 void skinny_combine(hipStream_t st, int M, long N, int K, double alpha, const double* A, long lda, const double* B,
                     long ldb, double beta, double* C, long ldc);
 
 // Split-K inner products out[s*ldo + t] = sum_x X[s*ldx + x] * Y[t*ldy + x]
 // for s < ns, t < nt, over x < len; fixed-order reduction (deterministic).
+// More than 48 rows of X run as passes of 48 that share the workspace.
 // ws must hold dots_workspace(ns, nt, len) doubles.
 size_t dots_workspace(int ns, int nt, long len);
 void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len, double* out,

@@ -253,18 +253,29 @@ long skinny_chunk(int nt, long len) {
   return std::max<long>(chunk, 256);
 }
 
-// Partial sums of either path.  The tall-skinny path makes at most
-// min(1024, len / 256) chunks whatever nt is, so the count is monotone in ns
-// and nt: a workspace sized for the largest shape serves every smaller one.
+// Rows of X per pass of the inner products: the tall-skinny kernels hold at
+// most 48 rows; more rows take several passes, each reading Y once.
+constexpr int kDotRows = 48;
+
+// split-K chunk of the general path: kDotChunk, or longer for very long
+// vectors so that there are at most 256 chunks
+long dot_chunk(long len) { return std::max<long>(kDotChunk, (len + 255) / 256); }
+
+// Partial sums of either path for one pass of at most kDotRows rows.  The
+// tall-skinny path makes at most min(1024, len / 256) chunks whatever nt is,
+// so the count is monotone in ns and nt: a workspace sized for the largest
+// shape serves every smaller one.
 size_t dots_workspace(int ns, int nt, long len) {
-  const long nchunks = std::max((len + kDotChunk - 1) / kDotChunk, std::min<long>(1024, (len + 255) / 256));
-  return static_cast<size_t>(nchunks) * ns * nt;
+  const long nfall = (len + dot_chunk(len) - 1) / dot_chunk(len);
+  const long nchunks = std::max(nfall, std::min<long>(1024, (len + 255) / 256));
+  return static_cast<size_t>(nchunks) * std::min(ns, kDotRows) * nt;
 }
 
-void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len, double* out,
-          long ldo, double* ws) {
-  if (ns <= 0 || nt <= 0) return;
-  if (ns <= 48 && len >= 1024 && ((ldx | ldy) & 1) == 0 && aligned_to(X, 16) && aligned_to(Y, 16)) {
+namespace {
+
+void dots_pass(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len,
+               double* out, long ldo, double* ws) {
+  if (len >= 1024 && ((ldx | ldy) & 1) == 0 && aligned_to(X, 16) && aligned_to(Y, 16)) {
     const long chunk = skinny_chunk(nt, len);
     const int nchunks = static_cast<int>((len + chunk - 1) / chunk);
     const dim3 grid(ceil_div(nt, 128), nchunks);
@@ -282,14 +293,15 @@ void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const doubl
     SEQX_LAUNCH_CHECK();
     return;
   }
-  const int nchunks = static_cast<int>((len + kDotChunk - 1) / kDotChunk);
+  const long dc = dot_chunk(len);
+  const int nchunks = static_cast<int>((len + dc - 1) / dc);
   // chunk c: partial[c] (ns x nt) = X[:, chunk] * Y[:, chunk]^T ; the last chunk is ragged
-  const int full = static_cast<int>(len / kDotChunk);
+  const int full = static_cast<int>(len / dc);
   if (full > 0)
-    dgemm(st, false, true, ns, nt, static_cast<int>(kDotChunk), 1.0, X, ldx, kDotChunk, Y, ldy, kDotChunk, 0.0, ws,
-          nt, static_cast<long>(ns) * nt, full, nullptr);
+    dgemm(st, false, true, ns, nt, static_cast<int>(dc), 1.0, X, ldx, dc, Y, ldy, dc, 0.0, ws, nt,
+          static_cast<long>(ns) * nt, full, nullptr);
   if (full < nchunks) {
-    const long off = static_cast<long>(full) * kDotChunk;
+    const long off = static_cast<long>(full) * dc;
     dgemm(st, false, true, ns, nt, static_cast<int>(len - off), 1.0, X + off, ldx, 0, Y + off, ldy, 0, 0.0,
           ws + static_cast<long>(full) * ns * nt, nt, 0, 1, nullptr);
   }
@@ -299,6 +311,17 @@ void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const doubl
     hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 256)), dim3(256), 0, st, nchunks, ns, nt, ws,
                        out, ldo);
   SEQX_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len, double* out,
+          long ldo, double* ws) {
+  if (ns <= 0 || nt <= 0) return;
+  // passes of at most kDotRows rows share the workspace (ordered on st)
+  for (int r0 = 0; r0 < ns; r0 += kDotRows)
+    dots_pass(st, std::min(kDotRows, ns - r0), X + static_cast<long>(r0) * ldx, ldx, nt, Y, ldy, len,
+              out + static_cast<long>(r0) * ldo, ldo, ws);
 }
 
 }  // namespace seqx
