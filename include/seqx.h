@@ -151,6 +151,12 @@ typedef struct {
   int32_t batched_graph;
   int32_t tile_variant[5];
   double batched_sigma_flops; /* algorithmic transform flops of the batched products, 4 n v (n + o) each */
+  /* Single-molecule solves: the largest subspace reached and the subspace cap
+   * used (max over molecules), and the number of restarts from the Ritz
+   * vectors because the cap was reached (summed over molecules). */
+  int32_t max_subspace_used;
+  int32_t subspace_cap;
+  int32_t n_collapses;
 } seqx_stats;
 
 /* Version of this header the library was built with (SEQX_ABI_VERSION). */

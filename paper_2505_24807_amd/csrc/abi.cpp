@@ -724,6 +724,9 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
     job->stats.t_autotune_s = 0.0;
     job->stats.batched_graph = 0;
     job->stats.batched_sigma_flops = 0.0;
+    job->stats.max_subspace_used = 0;
+    job->stats.subspace_cap = 0;
+    job->stats.n_collapses = 0;
     for (int32_t& x : job->stats.tile_variant) x = 0;
     if (opts->batched) {
       if (opts->theory != SEQX_CIS) throw Error(kEArg, "batched solve supports CIS only");
@@ -798,6 +801,9 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
       job->stats.refine_iteration = std::max(job->stats.refine_iteration, r.refine_iter);
       for (int p = 0; p < kNumDavPhases; ++p) job->stats.dav_phase_ms[p] += r.phase_ms[p];
       job->stats.dav_iterations = std::max(job->stats.dav_iterations, r.iterations);
+      job->stats.max_subspace_used = std::max(job->stats.max_subspace_used, r.max_subspace);
+      job->stats.subspace_cap = std::max(job->stats.subspace_cap, r.subspace_cap);
+      job->stats.n_collapses += r.n_collapses;
       job->stats.t_sigma_s += r.t_sigma_ms * 1e-3;
       if (mi == 0) {
         const int nh = std::min<int>(static_cast<int>(r.t_iter.size()), 64);

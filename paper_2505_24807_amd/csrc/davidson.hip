@@ -409,6 +409,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   const int ng = opt.guess ? opt.nguess : static_cast<int>(std::min<long>(nov, 2L * K));
   if (ng < 1 || ng > Smax) throw Error(kEArg, "guess size out of range");
   DavResult res;
+  res.subspace_cap = Smax;
   const double t0 = now_s();
 
   w.V.ensure(static_cast<size_t>(Smax) * nov);
@@ -547,6 +548,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
         hipLaunchKernelGGL(sym_fill_kernel, dim3(ceil_div(S1, 256), knew), dim3(256), 0, st, w.Mm.p, Smax, S, S1);
       SEQX_LAUNCH_CHECK();
       S = S1;
+      res.max_subspace = std::max(res.max_subspace, S);
       // 3. subspace eigenproblem
       itimer.mark(kDavSmallEig);
       double* tco = w.coef.p;                          // t (TDHF) or x (CIS): S x K, ld Smax
@@ -658,7 +660,10 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       const int nc = tdhf ? 2 * nsel : nsel;
       // 7. collapse onto the best Ritz vectors when the basis would overflow
       itimer.mark(kDavCollapse);
-      if (S + nc > Smax) S = collapse(S, true);
+      if (S + nc > Smax) {
+        S = collapse(S, true);
+        ++res.n_collapses;
+      }
       // 8. orthonormalise and append
       itimer.mark(kDavOrtho);
       knew = orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V.p, Smax - S);

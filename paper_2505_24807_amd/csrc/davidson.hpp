@@ -40,6 +40,9 @@ struct DavResult {
   long n_sigma_fp64 = 0;   // products formed with FP64 transforms
   int refine_iter = 0;     // iteration whose products were the first FP64 ones after a mixed-precision phase
   double t_sigma_ms = 0.0;
+  int max_subspace = 0;    // largest basis size reached
+  int subspace_cap = 0;    // cap in force
+  int n_collapses = 0;     // restarts because the cap was reached
   std::vector<double> t_iter;                 // wall seconds at the end of each iteration
   std::vector<std::vector<double>> omega_iter;  // Ritz values (hartree) per iteration
 };

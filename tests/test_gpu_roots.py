@@ -1,0 +1,188 @@
+"""Many roots, memory-capped subspaces and the other solver paths, through the
+C ABI, against the CPU oracle.
+
+The paper computes up to 100 states per molecule and caps the Krylov subspace
+by the free GPU memory, restarting from the current best eigenvectors when the
+cap is reached (results section, time against number of states; GPU
+implementation subsection).  Tolerances: the FP64 bar of 1e-6 eV on every
+excitation energy.
+"""
+import copy
+import functools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import excited, integrals, model, scf
+from paper_2505_24807_amd import seqx
+from synthetic import molecules, params
+
+pytestmark = pytest.mark.gpu
+HA = model.HARTREE_EV
+HERE = os.path.dirname(os.path.abspath(__file__))
+PR = params.load()
+K20 = json.load(open(os.path.join(HERE, "golden", "c2_polyene40_k20.json")))
+
+MOLS = {
+    "C2H4": molecules.ethylene(),
+    "C20H22n": molecules.add_noise(molecules.polyene(20), 0.02, np.random.default_rng(20)),
+    "C40H42": molecules.workload_polyene40(),
+}
+
+
+def _ctx(pr=PR):
+    c = seqx.Context(0)
+    Zs, vals = seqx.params_table(pr)
+    c.set_params(Zs, vals)
+    return c
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = _ctx()
+    yield c
+    c.close()
+
+
+@functools.lru_cache(maxsize=None)
+def dense_of(name):
+    mol = MOLS[name]
+    sy = model.make_system(mol.Z, mol.xyz, PR)
+    ints = integrals.build(sy)
+    res = scf.run(sy, ints)
+    o = res.nocc
+    A, B = excited.build_AB(ints, res.eps, res.C, o)
+    return sy, res, A, B
+
+
+def _prepare(ctx, names):
+    mols = [MOLS[n] for n in names]
+    print(f"[gpu] prepare {names}", flush=True)
+    return ctx.prepare([m.natoms for m in mols], np.concatenate([m.Z for m in mols]),
+                       np.vstack([m.xyz for m in mols]))
+
+
+@pytest.mark.parametrize("theory", [seqx.CIS, seqx.TDHF], ids=["cis", "tdhf"])
+def test_hundred_roots_against_dense(ctx, theory):
+    """100 roots of C20H22 (nov = 2601): the subspace grows past 256 vectors,
+    so the small eigenproblems leave the one-workgroup kernels for rocSOLVER,
+    and the tall-skinny products run in several passes."""
+    sy, res, A, B = dense_of("C20H22n")
+    o, v = res.nocc, sy.nao - res.nocc
+    K = 100
+    ref = excited.cis_dense(A, K, o, v) if theory == seqx.CIS else excited.tdhf_dense(A, B, K, o, v)
+    job = _prepare(ctx, ["C20H22n"])
+    print(f"[gpu] solve K={K} theory={theory}", flush=True)
+    job.solve(theory=theory, nroots=K, tol=1e-7, max_iter=200)
+    got = job.results()
+    st = job.stats()
+    print(f"[gpu] iterations {st.dav_iterations} max subspace {st.max_subspace_used} cap {st.subspace_cap}",
+          flush=True)
+    assert np.abs(got.omega_eV - ref.omega * HA).max() < 1e-6
+    assert st.max_subspace_used > 256
+    if theory == seqx.TDHF:
+        nrm = np.sum(got.X ** 2, axis=(1, 2)) - np.sum(got.Y ** 2, axis=(1, 2))
+        assert np.abs(nrm - 1.0).max() < 1e-8
+    job.free()
+
+
+@pytest.mark.parametrize("theory", ["cis", "tdhf"])
+def test_twenty_roots_c40h42(ctx, theory):
+    """20 roots of the 82-atom polyene against the stored dense oracle values."""
+    job = _prepare(ctx, ["C40H42"])
+    job.solve(theory=seqx.CIS if theory == "cis" else seqx.TDHF, nroots=20, tol=1e-7, max_iter=200)
+    got = job.results()
+    ref = np.array(K20[theory]["omega_eV"])
+    assert np.abs(got.omega_eV - ref).max() < 1e-6
+    job.free()
+
+
+def test_memory_budget_forces_restarts(ctx):
+    """A budget for 70 basis rows (V, (A+B)V, (A-B)V) caps the TDHF subspace
+    at 80 vectors (2K Ritz vectors + 2K new directions): the solve restarts
+    from its Ritz vectors and still reaches the dense roots."""
+    job = _prepare(ctx, ["C40H42"])
+    _, o, v = job.dims()
+    budget = 70 * 3 * o * v * 8
+    job.solve(theory=seqx.TDHF, nroots=20, tol=1e-7, max_iter=400, mem_budget_bytes=budget)
+    st = job.stats()
+    print(f"[gpu] cap {st.subspace_cap} collapses {st.n_collapses} iterations {st.dav_iterations}", flush=True)
+    assert st.subspace_cap == 80
+    assert st.n_collapses > 0
+    assert st.max_subspace_used <= 80
+    got = job.results()
+    assert np.abs(got.omega_eV - np.array(K20["tdhf"]["omega_eV"])).max() < 1e-6
+    job.free()
+
+
+def test_memory_budget_cap_per_molecule(ctx):
+    """Two molecules, the small one first, under one budget: each gets its own
+    cap (the larger molecule a smaller one), and both match dense."""
+    job = _prepare(ctx, ["C2H4", "C20H22n"])
+    _, o1, v1 = job.dims(1)
+    budget = 30 * 3 * o1 * v1 * 8
+    K = 6
+    job.solve(theory=seqx.TDHF, nroots=K, tol=1e-7, max_iter=400, mem_budget_bytes=budget)
+    st = job.stats()
+    # C2H4 may use all of its 36 pairs; C20H22 is held to its own cap of 30
+    # (a cap taken from the first molecule would have let it grow to 160)
+    assert st.max_subspace_used <= 36
+    assert st.n_collapses > 0
+    for mol, name in ((0, "C2H4"), (1, "C20H22n")):
+        sy, res, A, B = dense_of(name)
+        o, v = res.nocc, sy.nao - res.nocc
+        ref = excited.tdhf_dense(A, B, K, o, v)
+        assert np.abs(job.results(mol).omega_eV - ref.omega * HA).max() < 1e-6
+    job.free()
+
+
+@pytest.mark.parametrize("theory", [seqx.CIS, seqx.TDHF], ids=["cis", "tdhf"])
+def test_user_guess_restart(ctx, theory):
+    """Converged amplitudes handed back as the starting space (checkpoint and
+    restart): the solve converges at once to the same roots."""
+    job = _prepare(ctx, ["C20H22n"])
+    K = 5
+    job.solve(theory=theory, nroots=K, tol=1e-8)
+    first = job.results()
+    it_first = job.stats().dav_iterations
+    if theory == seqx.TDHF:
+        guess = np.concatenate([first.X + first.Y, first.X - first.Y])
+    else:
+        guess = first.X
+    job.solve(theory=theory, nroots=K, tol=1e-8, guess=seqx.GUESS_USER, user_guess=guess)
+    second = job.results()
+    it_second = job.stats().dav_iterations
+    print(f"[gpu] iterations {it_first} -> {it_second}", flush=True)
+    assert it_second <= 2 < it_first
+    assert np.abs(second.omega_eV - first.omega_eV).max() < 1e-9
+    job.free()
+
+
+def test_unstable_reference_is_reported():
+    """Resonance integrals halved: the oracle's RHF reference of C4H6 has
+    indefinite A+B and A-B (an imaginary TDHF root); the library reports
+    SEQX_E_UNSTABLE instead of a root or a failed convergence."""
+    pr = copy.deepcopy(PR)
+    for Z in pr:
+        for key in ("beta_s", "beta_p"):
+            if key in pr[Z]:
+                pr[Z][key] *= 0.5
+    mol = molecules.polyene(4)
+    sy = model.make_system(mol.Z, mol.xyz, pr)
+    ints = integrals.build(sy)
+    res = scf.run(sy, ints)
+    A, B = excited.build_AB(ints, res.eps, res.C, res.nocc)
+    assert np.linalg.eigvalsh(A + B).min() < 0 or np.linalg.eigvalsh(A - B).min() < 0
+    c = _ctx(pr)
+    try:
+        job = c.prepare([mol.natoms], mol.Z, mol.xyz)
+        eps, _, _ = job.scf_results()
+        assert np.abs(eps - res.eps * HA).max() < 1e-6  # the same reference
+        with pytest.raises(seqx.SeqxError) as ei:
+            job.solve(theory=seqx.TDHF, nroots=3, tol=1e-7)
+        assert ei.value.status == 9
+        job.free()
+    finally:
+        c.close()
