@@ -15,6 +15,7 @@ bounded sample of the same workload.
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--precision fp32|fp64]
                     [--no-fp64-comparison] [--no-batched] [--no-batched-loop] [--no-learned]
                     [--no-cpu-baseline]
+    python bench.py --nroots-curve 10,20,50,100 [--curve-budgets-gb 0,4]   # time against root count
 """
 from __future__ import annotations
 
@@ -254,6 +255,48 @@ def sigma_only(ctx, mol, k, reps, precision):
             "sigma_vectors_per_s": round(k * reps / dt, 1), "seconds": round(dt, 4)}
 
 
+def nroots_curve(ctx, roots, budgets_gb):
+    """Total time (integrals + SCF + Davidson) against the number of CIS roots,
+    FP64 transforms, residual tol 1e-5 Eh, for molecules of about 200, 400 and
+    1000 atoms; each point is one run after a warm-up of the same molecule.
+    budgets_gb: subspace memory budgets (GB) for the 990-atom molecule; 0 is the
+    default (40 % of free memory), a small one forces restarts."""
+    import torch
+    from paper_2505_24807_amd import seqx
+    from synthetic import molecules
+    mols = [("C100H102 polyene (202 atoms)", molecules.add_noise(molecules.polyene(100), 0.02,
+                                                               np.random.default_rng(100)), [0]),
+            ("(H2O)133 (399 atoms)", molecules.water_cluster(133, 133), [0]),
+            ("(H2O)330 (990 atoms)", molecules.workload_water330(), budgets_gb)]
+    rows = []
+    for name, mol, budgets in mols:
+        warm = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+        warm.solve(theory=seqx.CIS, nroots=min(roots), tol=1e-5, max_iter=400)
+        warm.free()
+        for gb in budgets:
+            for K in roots:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+                job.solve(theory=seqx.CIS, nroots=K, tol=1e-5, max_iter=400,
+                          mem_budget_bytes=int(gb * 1e9))
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                st = job.stats()
+                om = job.results().omega_eV
+                n, o, v = job.dims()
+                job.free()
+                row = {"molecule": name, "nao": n, "nov": o * v, "nroots": K,
+                       "budget_GB": gb if gb else "40% of free", "total_s": round(dt, 3),
+                       "scf_s": round(st.t_scf_s + st.t_integrals_s, 3), "davidson_s": round(st.t_davidson_s, 3),
+                       "iterations": st.dav_iterations, "n_sigma": st.n_sigma, "subspace_cap": st.subspace_cap,
+                       "max_subspace": st.max_subspace_used, "collapses": st.n_collapses,
+                       "omega_range_eV": [round(float(om[0]), 4), round(float(om[-1]), 4)]}
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+    return rows
+
+
 def learned_c5(ctx, nmol=3):
     """Held-out molecules of the learned-guess evaluation (200-600 atoms), CIS,
     10 roots, FP64: the network shipped in the package against the gap guess."""
@@ -292,6 +335,10 @@ def main():
     ap.add_argument("--cpu-vectors", type=int, default=2)
     ap.add_argument("--sigma-only", type=int, default=0, metavar="K",
                     help="time only K-vector sigma builds of (H2O)330 (for counter passes) and exit")
+    ap.add_argument("--nroots-curve", type=str, default="", metavar="K1,K2,...",
+                    help="time CIS solves of 200-, 400- and 990-atom molecules for these root counts and exit")
+    ap.add_argument("--curve-budgets-gb", type=str, default="0,4",
+                    help="subspace memory budgets (GB) of the 990-atom points of --nroots-curve (0: default)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -320,6 +367,12 @@ def main():
     pr = params.load()
     ctx.set_params(*seqx.params_table(pr))
     mol = molecules.workload_water330()
+    if args.nroots_curve:
+        roots = [int(x) for x in args.nroots_curve.split(",")]
+        budgets = [float(x) for x in args.curve_budgets_gb.split(",")]
+        rows = nroots_curve(ctx, roots, budgets)
+        print(json.dumps({"nroots_curve": rows}))
+        return
     if args.sigma_only > 0:
         prec = seqx.FP32 if args.precision == "fp32" else seqx.FP64
         print(json.dumps(sigma_only(ctx, mol, args.sigma_only, args.steps, prec)))
