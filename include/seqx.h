@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SEQX_ABI_VERSION 3
+#define SEQX_ABI_VERSION 4
 #define SEQX_NPARAM 11 /* per-element parameters, order below */
 
 typedef struct seqx_ctx seqx_ctx; /* one device + one stream */
@@ -111,6 +111,14 @@ typedef struct {
                            subspace cap is min(max_subspace or 8 * nroots, 48) per molecule.
                            Molecules need at most 1536 same-atom AO pairs. */
   int32_t pspace;       /* LEARNED / GAP_PSPACE guesses: number of pairs M; <= 0 selects 4 * nroots */
+  int32_t root_batch;   /* 1 .. nroots-1: low-memory solve of the roots in batches of this many
+                           (the paper's outlook: find a subset of the states, then shift the
+                           ones found out of the search space).  Each batch is a Davidson solve
+                           of its lowest roots with the earlier roots locked and shifted up
+                           (TDHF: A+B += s U U^T over the locked X-Y rows; CIS: A += s X X^T),
+                           so the subspace cap (20 * root_batch + 40, or the memory budget)
+                           applies per batch and only the K converged roots are kept beyond
+                           it.  Single-molecule solver, gap guess only.  0: all roots at once. */
 } seqx_solve_opts;
 
 typedef struct {
@@ -279,6 +287,22 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts);
  * mu[K][3] transition dipoles (atomic units).  Any output may be NULL. */
 seqx_status seqx_results(const seqx_job* job, int32_t mol, double* omega_eV, double* X, double* Y,
                          double* f, double* mu);
+
+/* Absorption spectrum of molecule `mol` after seqx_solve (results section of
+ * the paper: oscillator strengths of every state, then Gaussian broadening of
+ * width 0.1 eV into a continuous profile):
+ *   out[i] = sum_n f_n exp(-(E_i - omega_n)^2 / (2 sigma^2)) / (sigma sqrt(2 pi)),
+ *   E_i = e0_eV + i de_eV, i < npts (host out[npts], 1/eV),
+ * over the solved roots.  sigma_eV is the standard deviation (the paper's width
+ * read as such; full width at half maximum = 2.3548 sigma); the lines have unit
+ * area, so the profile integrates to the summed oscillator strength.
+ * SEQX_E_ARG for sigma_eV <= 0, de_eV <= 0 or npts <= 0; SEQX_E_STATE before a solve. */
+seqx_status seqx_spectrum(const seqx_job* job, int32_t mol, double sigma_eV, double e0_eV, double de_eV,
+                          int32_t npts, double* out);
+/* The same profile for K caller lines (host omega_eV[K], f[K]), e.g. roots
+ * gathered from several solves. */
+seqx_status seqx_broaden(seqx_ctx* ctx, int32_t K, const double* omega_eV, const double* f, double sigma_eV,
+                         double e0_eV, double de_eV, int32_t npts, double* out);
 
 seqx_status seqx_get_stats(const seqx_job* job, seqx_stats* out);
 

@@ -28,6 +28,7 @@
 #include "molecule.hpp"
 #include "scf.hpp"
 #include "sigma.hpp"
+#include "spectrum.hpp"
 
 namespace seqx {
 thread_local const DeviceAllocator* g_device_allocator = nullptr;
@@ -62,6 +63,7 @@ struct seqx_job {
   DavWork dw;
   BatchWork bw;
   DBuf<double> guess_v;
+  DBuf<double> lock_t, lock_u;  // locked roots of a root-batch solve
   seqx_stats stats{};
   bool solved = false;
 };
@@ -728,6 +730,10 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
     job->stats.subspace_cap = 0;
     job->stats.n_collapses = 0;
     for (int32_t& x : job->stats.tile_variant) x = 0;
+    const bool root_batches = opts->root_batch > 0 && opts->root_batch < opts->nroots;
+    if (opts->root_batch < 0) throw Error(kEArg, "root_batch must be >= 0");
+    if (root_batches && (opts->batched || opts->guess != SEQX_GUESS_GAP))
+      throw Error(kEArg, "root batches run the single-molecule solver from the gap guess");
     if (opts->batched) {
       if (opts->theory != SEQX_CIS) throw Error(kEArg, "batched solve supports CIS only");
       if (opts->guess != SEQX_GUESS_GAP) throw Error(kEArg, "batched solve uses the gap guess");
@@ -789,10 +795,17 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
           budget = fr * 2 / 5;
         }
         const size_t per = static_cast<size_t>(opts->theory == SEQX_TDHF ? 3 : 2) * nov * sizeof(double);
-        const long cap_mem = static_cast<long>(budget / std::max<size_t>(per, 1));
-        dm.max_sub = static_cast<int>(std::max<long>(std::min<long>(cap_mem, 20L * opts->nroots + 40), 1));
+        // root batches keep K locked rows (T, and U for TDHF) beside the batch's subspace
+        const size_t locked = root_batches ? static_cast<size_t>(opts->theory == SEQX_TDHF ? 2 : 1) *
+                                                 opts->nroots * nov * sizeof(double)
+                                           : 0;
+        const long cap_mem = static_cast<long>((budget > locked ? budget - locked : 0) / std::max<size_t>(per, 1));
+        const long kcap = root_batches ? opts->root_batch : opts->nroots;
+        dm.max_sub = static_cast<int>(std::max<long>(std::min<long>(cap_mem, 20L * kcap + 40), 1));
       }
-      DavResult r = davidson(m, dm, *job->ctx->ds, job->dw, st);
+      DavResult r = root_batches ? davidson_root_batches(m, dm, opts->root_batch, *job->ctx->ds, job->dw,
+                                                         job->lock_t, job->lock_u, st)
+                                 : davidson(m, dm, *job->ctx->ds, job->dw, st);
       m.hist_t = r.t_iter;
       m.hist_omega.clear();
       for (const auto& w : r.omega_iter) m.hist_omega.insert(m.hist_omega.end(), w.begin(), w.end());
@@ -834,6 +847,49 @@ seqx_status seqx_results(const seqx_job* job, int32_t mol, double* omega_eV, dou
     SEQX_HIP(hipStreamSynchronize(st));
     if (omega_eV)
       for (int j = 0; j < K; ++j) omega_eV[j] = om[j] * kHartreeEV;
+  });
+}
+
+namespace {
+void check_grid(double sigma_eV, double de_eV, int32_t npts, const double* out) {
+  if (!(sigma_eV > 0.0) || !std::isfinite(sigma_eV)) throw Error(kEArg, "sigma must be positive and finite");
+  if (!(de_eV > 0.0) || !std::isfinite(de_eV)) throw Error(kEArg, "grid step must be positive and finite");
+  if (npts <= 0 || !out) throw Error(kEArg, "bad spectrum grid");
+}
+}  // namespace
+
+seqx_status seqx_spectrum(const seqx_job* job, int32_t mol, double sigma_eV, double e0_eV, double de_eV,
+                          int32_t npts, double* out) {
+  if (!job) return SEQX_E_ARG;
+  return guarded(job->ctx, [&] {
+    const DeviceMolecule& m = mol_of(job, mol);
+    if (!job->solved || m.nroots == 0) throw Error(kEState, "no roots: call seqx_solve first");
+    check_grid(sigma_eV, de_eV, npts, out);
+    hipStream_t st = job->ctx->stream;
+    DBuf<double> d(static_cast<size_t>(npts));
+    broaden(st, m.nroots, m.omega.p, kHartreeEV, m.f.p, sigma_eV, e0_eV, de_eV, npts, d.p);
+    d2h(out, d.p, static_cast<size_t>(npts), st);
+    SEQX_HIP(hipStreamSynchronize(st));
+  });
+}
+
+seqx_status seqx_broaden(seqx_ctx* ctx, int32_t K, const double* omega_eV, const double* f, double sigma_eV,
+                         double e0_eV, double de_eV, int32_t npts, double* out) {
+  if (!ctx) return SEQX_E_ARG;
+  return guarded(ctx, [&] {
+    if (K < 0 || (K > 0 && (!omega_eV || !f))) throw Error(kEArg, "bad line list");
+    check_grid(sigma_eV, de_eV, npts, out);
+    hipStream_t st = ctx->stream;
+    DBuf<double> d(static_cast<size_t>(npts) + 2 * static_cast<size_t>(K));
+    double* dw = d.p + npts;
+    double* df = dw + K;
+    if (K > 0) {
+      SEQX_HIP(hipMemcpyAsync(dw, omega_eV, K * sizeof(double), hipMemcpyHostToDevice, st));
+      SEQX_HIP(hipMemcpyAsync(df, f, K * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    broaden(st, K, dw, 1.0, df, sigma_eV, e0_eV, de_eV, npts, d.p);
+    d2h(out, d.p, static_cast<size_t>(npts), st);
+    SEQX_HIP(hipStreamSynchronize(st));
   });
 }
 

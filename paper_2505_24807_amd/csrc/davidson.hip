@@ -407,6 +407,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   const int ncand_max = tdhf ? 2 * K : K;
   Smax = std::max(Smax, std::min<int>(static_cast<int>(nov), 2 * K + ncand_max));
   const int ng = opt.guess ? opt.nguess : static_cast<int>(std::min<long>(nov, 2L * K));
+  if (opt.nlock > 0 && (!opt.lock_u || !(opt.shift > 0.0))) throw Error(kEArg, "locked roots need vectors and a shift");
   if (ng < 1 || ng > Smax) throw Error(kEArg, "guess size out of range");
   DavResult res;
   res.subspace_cap = Smax;
@@ -433,7 +434,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   w.scratch.ensure(static_cast<size_t>(ps) * 2 * K * nov);
   w.G.ensure(static_cast<size_t>(ps) * Smax * Smax);
   w.Q.ensure(static_cast<size_t>(std::max(ncand_max, 2 * K)) * Smax);
-  w.ws.ensure(std::max<size_t>(dots_workspace(2 * Smax, Smax, nov), 4096));
+  w.ws.ensure(std::max<size_t>(dots_workspace(2 * Smax, std::max(Smax, opt.nlock), nov), 4096));
   w.d.ensure(nov);
   w.rn.ensure(2 * K);
   const int nbres = static_cast<int>(std::min<long>(256, ceil_div(nov, 256)));
@@ -454,11 +455,24 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
     knew = orthonormalize_append(st, ds, w, nov, opt.nguess, w.W.p, 0, w.V.p, Smax);
     if (knew == 0) throw Error(kEArg, "user guess vectors are linearly dependent or zero");
   } else {
-    hipLaunchKernelGGL(gap_guess_kernel, dim3(1), dim3(1024), 0, st, o, v, ng, m.eps.p, w.idx.p);
-    hipLaunchKernelGGL(unit_vectors_kernel, dim3(ceil_div(nov, 256), ng), dim3(256), 0, st, ng, nov, w.idx.p, w.V.p);
+    // with locked roots: unit vectors at the ng gaps that follow the nlock smallest
+    const int skip = static_cast<int>(std::min<long>(opt.nlock, nov - ng));
+    w.idx.ensure(skip + ng);
+    hipLaunchKernelGGL(gap_guess_kernel, dim3(1), dim3(1024), 0, st, o, v, skip + ng, m.eps.p, w.idx.p);
+    hipLaunchKernelGGL(unit_vectors_kernel, dim3(ceil_div(nov, 256), ng), dim3(256), 0, st, ng, nov, w.idx.p + skip,
+                       w.V.p);
     SEQX_LAUNCH_CHECK();
     knew = ng;
   }
+  // deflation of the locked roots: out_s += shift * sum_m U_m (U_m . V_s) for
+  // the nv new vectors (their products nv rows of stride ldp from sp)
+  auto deflate = [&](const double* Vn, int nv, double* sp) {
+    if (opt.nlock <= 0 || nv <= 0) return;
+    w.lc.ensure(static_cast<size_t>(nv) * opt.nlock);
+    dots(st, nv, Vn, nov, opt.nlock, opt.lock_u, nov, nov, w.lc.p, opt.nlock, w.ws.p);
+    dgemm(st, false, false, nv, static_cast<int>(nov), opt.nlock, opt.shift, w.lc.p, opt.nlock, 0, opt.lock_u, nov,
+          0, 1.0, sp, ldp, 0, 1, nullptr);
+  };
 
   std::vector<double> h_om(K), h_rn(K);
   std::vector<int> sel;
@@ -533,6 +547,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       double* sp_new = w.SP.p + static_cast<long>(S) * ldp;
       sigma_build(m, opt.theory, knew, w.V.p + S * nov, sp_new, tdhf ? sp_new + nov : nullptr, w.sig, st,
                   opt.sigma_chunk, ldp, prec);
+      deflate(w.V.p + S * nov, knew, sp_new);
       SEQX_HIP(hipEventRecord(e1, st));
       itimer.mark(kDavProject);
       res.n_sigma += knew;
@@ -688,6 +703,99 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   m.dav_iterations = it;
   m.n_sigma = res.n_sigma;
   return res;
+}
+
+__global__ void pair_rows_kernel(long nov, int K, const double* __restrict__ X, const double* __restrict__ Y,
+                                 double* __restrict__ T, double* __restrict__ U) {
+  const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  const int j = blockIdx.y;
+  if (x >= nov) return;
+  const long b = static_cast<long>(j) * nov + x;
+  T[b] = X[b] + Y[b];
+  if (U) U[b] = X[b] - Y[b];
+}
+
+DavResult davidson_root_batches(DeviceMolecule& m, const DavOptions& opt, int batch, DenseSolver& ds, DavWork& w,
+                                DBuf<double>& lock_t, DBuf<double>& lock_u, hipStream_t st) {
+  const int K = opt.nroots, n = m.nao;
+  const long nov = static_cast<long>(m.nocc) * m.nvirt;
+  const bool tdhf = opt.theory == 1;
+  if (batch < 1 || batch >= K) throw Error(kEArg, "root batch must be in [1, nroots)");
+  if (opt.guess) throw Error(kEArg, "root batches start from the gap guess");
+  lock_t.ensure(static_cast<size_t>(K) * nov);
+  if (tdhf) lock_u.ensure(static_cast<size_t>(K) * nov);
+  // spread of the orbital energies: every target root lies below it
+  std::vector<double> eps(n);
+  d2h(eps.data(), m.eps.p, n, st);
+  SEQX_HIP(hipStreamSynchronize(st));
+  const double D = eps[n - 1] - eps[0];
+  DavResult total;
+  std::vector<double> om_all;
+  double t_off = 0.0;
+  for (int k0 = 0; k0 < K; k0 += batch) {
+    const int kb = std::min(batch, K - k0);
+    DavOptions ob = opt;
+    ob.nroots = kb;
+    ob.nlock = k0;
+    ob.lock_t = lock_t.p;
+    ob.lock_u = tdhf ? lock_u.p : lock_t.p;
+    // locked roots move to w + s (CIS) or sqrt(w (w + s)) (TDHF), at least 2 D either way
+    const double wmin = k0 > 0 ? *std::min_element(om_all.begin(), om_all.end()) : 1.0;
+    ob.shift = tdhf ? 4.0 * D * D / std::max(wmin, 1e-3) : 2.0 * D;
+    DavResult r = davidson(m, ob, ds, w, st);
+    hipLaunchKernelGGL(pair_rows_kernel, dim3(ceil_div(nov, 256), kb), dim3(256), 0, st, nov, kb, m.X.p, m.Y.p,
+                       lock_t.p + static_cast<long>(k0) * nov, tdhf ? lock_u.p + static_cast<long>(k0) * nov : nullptr);
+    SEQX_LAUNCH_CHECK();
+    std::vector<double> om(kb);
+    d2h(om.data(), m.omega.p, kb, st);
+    SEQX_HIP(hipStreamSynchronize(st));
+    // history: locked roots at their final values, this batch's Ritz values, NaN beyond
+    for (size_t it = 0; it < r.t_iter.size(); ++it) {
+      total.t_iter.push_back(t_off + r.t_iter[it]);
+      std::vector<double> row(K, std::nan(""));
+      for (int j = 0; j < k0; ++j) row[j] = om_all[j];
+      for (int j = 0; j < kb; ++j) row[k0 + j] = r.omega_iter[it][j];
+      total.omega_iter.push_back(row);
+    }
+    if (!r.t_iter.empty()) t_off += r.t_iter.back();
+    om_all.insert(om_all.end(), om.begin(), om.end());
+    for (int p = 0; p < kNumDavPhases; ++p) total.phase_ms[p] += r.phase_ms[p];
+    total.iterations += r.iterations;
+    total.n_sigma += r.n_sigma;
+    total.n_sigma_fp64 += r.n_sigma_fp64;
+    total.refine_iter = std::max(total.refine_iter, r.refine_iter);
+    total.t_sigma_ms += r.t_sigma_ms;
+    total.max_subspace = std::max(total.max_subspace, r.max_subspace);
+    total.subspace_cap = std::max(total.subspace_cap, r.subspace_cap);
+    total.n_collapses += r.n_collapses;
+  }
+  // all K roots in ascending order
+  std::vector<int> perm(K);
+  for (int j = 0; j < K; ++j) perm[j] = j;
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return om_all[a] < om_all[b]; });
+  std::vector<double> om_sorted(K);
+  for (int j = 0; j < K; ++j) om_sorted[j] = om_all[perm[j]];
+  DBuf<double> omd(K);
+  SEQX_HIP(hipMemcpyAsync(omd.p, om_sorted.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+  bool ordered = true;
+  for (int j = 0; j < K; ++j) ordered = ordered && perm[j] == j;
+  const double* T = lock_t.p;
+  const double* U = tdhf ? lock_u.p : lock_t.p;
+  DBuf<double> Ts, Us;
+  if (!ordered) {
+    Ts.alloc(static_cast<size_t>(K) * nov);
+    if (tdhf) Us.alloc(static_cast<size_t>(K) * nov);
+    for (int j = 0; j < K; ++j) {
+      copy(st, Ts.p + static_cast<long>(j) * nov, lock_t.p + static_cast<long>(perm[j]) * nov, nov);
+      if (tdhf) copy(st, Us.p + static_cast<long>(j) * nov, lock_u.p + static_cast<long>(perm[j]) * nov, nov);
+    }
+    T = Ts.p;
+    U = tdhf ? Us.p : Ts.p;
+  }
+  finalize_roots(m, opt.theory, K, omd.p, T, U, w.sig, w.scratch, st);
+  m.dav_iterations = total.iterations;
+  m.n_sigma = total.n_sigma;
+  return total;
 }
 
 }  // namespace seqx

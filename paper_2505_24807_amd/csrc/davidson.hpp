@@ -19,10 +19,20 @@ struct DavOptions {
   int precision = 0;   // SigmaPrecision of the transforms; the run finishes with FP64 products
   const double* guess = nullptr;  // device [nguess][nov] (user / learned guess), or null for the gap guess
   int nguess = 0;
+  // Roots already found (root batches): nlock locked pairs, lock_t = T rows
+  // (X+Y; CIS: X) and lock_u = U rows (X-Y; CIS: X), device [nlock][nov].
+  // Every product gets the deflation term shift * U (U^T V) (TDHF: on A+B;
+  // CIS: on A), which moves the locked roots up to sqrt(w (w + shift)) (CIS:
+  // w + shift) and leaves the others where they are.  The gap guess then
+  // starts after the nlock smallest gaps.
+  const double* lock_t = nullptr;
+  const double* lock_u = nullptr;
+  int nlock = 0;
+  double shift = 0.0;
 };
 
 struct DavWork {
-  DBuf<double> V, SP, SM, Mp, Mm, Lm, Tmp, Hs, w2, coef, Tv, Uv, PT, MU, W, G, Q, scratch, ws, d, rn, part;
+  DBuf<double> V, SP, SM, Mp, Mm, Lm, Tmp, Hs, w2, coef, Tv, Uv, PT, MU, W, G, Q, scratch, ws, d, rn, part, lc;
   DBuf<int> idx, sel;
   SigmaWork sig;
 };
@@ -57,5 +67,15 @@ void finalize_roots(DeviceMolecule& m, int theory, int K, const double* om, cons
 // Lowest roots of molecule m; fills m.omega, m.X, m.Y, m.f, m.mu.
 // Throws Error(kEDavNoConv) / Error(kEUnstable) on failure.
 DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, DavWork& w, hipStream_t st);
+
+// Low-memory variant: the K roots in batches of `batch` (the paper's outlook
+// on computing eigenstates in batches and shifting the ones already found out
+// of the search space, Wilkinson).  Each batch is one Davidson solve of its
+// lowest roots with the earlier batches locked and deflated (DavOptions
+// nlock, shift); the subspace cap applies per batch.  The locked T and U rows
+// live in lock_t, lock_u (K x nov each; TDHF only for U).  All K roots are
+// then ordered and finalised as one set.
+DavResult davidson_root_batches(DeviceMolecule& m, const DavOptions& opt, int batch, DenseSolver& ds, DavWork& w,
+                                DBuf<double>& lock_t, DBuf<double>& lock_u, hipStream_t st);
 
 }  // namespace seqx

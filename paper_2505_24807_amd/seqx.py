@@ -45,7 +45,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("theory", C.c_int32), ("nroots", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("max_subspace", C.c_int32), ("mem_budget_bytes", C.c_size_t), ("precision", C.c_int32),
                 ("guess", C.c_int32), ("n_user_guess", C.c_int32), ("user_guess", C.POINTER(C.c_double)),
-                ("batched", C.c_int32), ("pspace", C.c_int32)]
+                ("batched", C.c_int32), ("pspace", C.c_int32), ("root_batch", C.c_int32)]
 
 
 class TrainOpts(C.Structure):
@@ -122,6 +122,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "seqx_sigma_device_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                                 C.c_void_p, C.c_void_p, C.c_int32]),
         "seqx_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts)]),
+        "seqx_spectrum": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, _D]),
+        "seqx_broaden": (C.c_int, [C.c_void_p, C.c_int32, _D, _D, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                   _D]),
         "seqx_results": (C.c_int, [C.c_void_p, C.c_int32, _D, _D, _D, _D, _D]),
         "seqx_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
         "seqx_history": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _I, _D, _D]),
@@ -275,6 +278,14 @@ class Context:
                                                 seg.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(loss), _fptr(g)))
         return loss.value, g
 
+    def broaden(self, omega_eV, f, sigma=0.1, e0=0.0, de=0.01, npts=1000):
+        """Gaussian-broadened absorption profile of caller lines (1/eV) on e0 + i de."""
+        w = np.ascontiguousarray(omega_eV, dtype=np.float64)
+        fv = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros(npts)
+        self._check(self.lib.seqx_broaden(self.h, w.size, _dptr(w), _dptr(fv), sigma, e0, de, npts, _dptr(out)))
+        return out
+
     def close(self):
         """Free the context's jobs, then the context (seqx_destroy)."""
         if getattr(self, "h", None):
@@ -374,14 +385,14 @@ class Job:
         return {"loss": list(log.loss[:min(log.n_epochs, 256)]), "seconds": log.seconds}
 
     def solve(self, theory=TDHF, nroots=3, tol=1e-6, max_iter=100, max_subspace=0, mem_budget_bytes=0,
-              precision=FP64, guess=GUESS_GAP, user_guess=None, batched=False, pspace=0):
+              precision=FP64, guess=GUESS_GAP, user_guess=None, batched=False, pspace=0, root_batch=0):
         ug = None
         n_ug = 0
         if user_guess is not None:
             ug = np.ascontiguousarray(user_guess, dtype=np.float64)
             n_ug = ug.shape[0]
         o = SolveOpts(theory, nroots, tol, max_iter, max_subspace, mem_budget_bytes, precision, guess, n_ug,
-                      _dptr(ug) if ug is not None else None, 1 if batched else 0, pspace)
+                      _dptr(ug) if ug is not None else None, 1 if batched else 0, pspace, root_batch)
         self.nroots = 0
         self._check(self.lib.seqx_solve(self.h, C.byref(o)))
         self.nroots = nroots
@@ -393,6 +404,12 @@ class Job:
         X, Y = np.zeros((K, o, v)), np.zeros((K, o, v))
         self._check(self.lib.seqx_results(self.h, mol, _dptr(om), _dptr(X), _dptr(Y), _dptr(f), _dptr(mu)))
         return Results(om, X, Y, f, mu)
+
+    def spectrum(self, mol=0, sigma=0.1, e0=0.0, de=0.01, npts=1000):
+        """Gaussian-broadened absorption profile (1/eV) of the solved roots on e0 + i de."""
+        out = np.zeros(npts)
+        self._check(self.lib.seqx_spectrum(self.h, mol, sigma, e0, de, npts, _dptr(out)))
+        return out
 
     def history(self, mol=0):
         """(t_s[iterations], omega_eV[iterations, K]) of the last solve."""

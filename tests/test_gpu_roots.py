@@ -186,3 +186,51 @@ def test_unstable_reference_is_reported():
         job.free()
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("theory", [seqx.CIS, seqx.TDHF], ids=["cis", "tdhf"])
+def test_root_batches_against_dense(ctx, theory):
+    """40 roots of C20H22 in batches of 10 (locked roots shifted out of the
+    search space): the same roots as dense, with a subspace held to the
+    batch's cap of 240 vectors."""
+    sy, res, A, B = dense_of("C20H22n")
+    o, v = res.nocc, sy.nao - res.nocc
+    K = 40
+    ref = excited.cis_dense(A, K, o, v) if theory == seqx.CIS else excited.tdhf_dense(A, B, K, o, v)
+    job = _prepare(ctx, ["C20H22n"])
+    print(f"[gpu] root batches K={K} theory={theory}", flush=True)
+    job.solve(theory=theory, nroots=K, tol=1e-7, max_iter=400, root_batch=10)
+    got = job.results()
+    st = job.stats()
+    print(f"[gpu] iterations {st.dav_iterations} max subspace {st.max_subspace_used} cap {st.subspace_cap}",
+          flush=True)
+    assert np.abs(got.omega_eV - ref.omega * HA).max() < 1e-6
+    assert st.subspace_cap == 240 and st.max_subspace_used <= 240
+    nrm = np.sum(got.X ** 2, axis=(1, 2)) - np.sum(got.Y ** 2, axis=(1, 2))
+    assert np.abs(nrm - 1.0).max() < 1e-8
+    _, f_ref = excited.transition_properties(sy, res.C, o, ref)
+    gaps = np.diff(ref.omega) * HA
+    iso = np.ones(K, bool)
+    iso[:-1] &= gaps > 1e-3
+    iso[1:] &= gaps > 1e-3
+    assert np.abs(got.f[iso] - f_ref[iso]).max() < 1e-6
+    t, om = job.history()
+    assert om.shape == (st.dav_iterations, K) and np.isfinite(om[-1]).all()
+    job.free()
+
+
+def test_root_batches_twenty_roots_c40h42(ctx):
+    """C40H42, 20 TDHF roots in batches of 5 against the stored dense values."""
+    job = _prepare(ctx, ["C40H42"])
+    job.solve(theory=seqx.TDHF, nroots=20, tol=1e-7, max_iter=400, root_batch=5)
+    assert np.abs(job.results().omega_eV - np.array(K20["tdhf"]["omega_eV"])).max() < 1e-6
+    assert job.stats().max_subspace_used <= 5 * 20 + 40
+    job.free()
+
+
+def test_root_batches_reject_other_guesses(ctx):
+    job = _prepare(ctx, ["C2H4"])
+    with pytest.raises(seqx.SeqxError) as ei:
+        job.solve(theory=seqx.CIS, nroots=6, root_batch=2, guess=seqx.GUESS_GAP_PSPACE)
+    assert ei.value.status == 1
+    job.free()
