@@ -304,6 +304,20 @@ seqx_status seqx_spectrum(const seqx_job* job, int32_t mol, double sigma_eV, dou
 seqx_status seqx_broaden(seqx_ctx* ctx, int32_t K, const double* omega_eV, const double* f, double sigma_eV,
                          double e0_eV, double de_eV, int32_t npts, double* out);
 
+/* Derivatives of the solved excitation energies of molecule `mol` with respect
+ * to every NDDO parameter, for re-optimising the parameters against excited-state
+ * data (the paper's machine-learning interface, which its conclusion extends to
+ * excited states).  grad[K][3][SEQX_NPARAM] (host, cap values): root, element
+ * (H, C, O) and parameter in the seqx_set_params order; eV per eV, or eV per
+ * 1/bohr for the exponents; zero for elements absent from the molecule and for
+ * the p terms of H.  The orbital response is one linear solve with A+B per root
+ * (the CIS and TDHF amplitude equations are stationary, so only the orbitals
+ * respond); the integral derivatives are central differences of the library's
+ * integral tables (step 1e-5 of each value).  zvector_iterations (optional)
+ * receives the largest number of conjugate-gradient steps of that solve.
+ * SEQX_E_STATE before a solve; SEQX_E_BUFSIZE when cap is too small. */
+seqx_status seqx_param_gradient(seqx_job* job, int32_t mol, double* grad, size_t cap, int32_t* zvector_iterations);
+
 seqx_status seqx_get_stats(const seqx_job* job, seqx_stats* out);
 
 /* Convergence history of molecule `mol` in the last seqx_solve: per Davidson

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libseqx.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 SOURCES = ["model.cpp", "integrals.hip", "gemm.hip", "fock.hip", "linalg.hip", "scf.hip", "sigma.hip",
-           "davidson.hip", "skinny.hip", "batch.hip", "mlp.hip", "small_dense.hip", "spectrum.hip", "abi.cpp"]
+           "davidson.hip", "skinny.hip", "batch.hip", "mlp.hip", "small_dense.hip", "spectrum.hip", "gradient.hip", "abi.cpp"]
 
 CFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form",

@@ -21,6 +21,7 @@
 #include "../../include/seqx.h"
 #include "batch.hpp"
 #include "davidson.hpp"
+#include "gradient.hpp"
 #include "integrals.hpp"
 #include "linalg.hpp"
 #include "mlp.hpp"
@@ -47,6 +48,7 @@ struct seqx_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   Elem elems[kNumSlots];
+  double raw[kNumSlots][SEQX_NPARAM] = {};  // the parameter values behind elems (eV, 1/bohr)
   bool have[kNumSlots] = {false, false, false};
   DBuf<Elem> d_elems;
   std::unique_ptr<DenseSolver> ds;
@@ -444,6 +446,7 @@ void set_params_impl(seqx_ctx* ctx, int32_t nelem, const int32_t* Z, const doubl
       if (v[6] <= 0 || (Z[i] != 1 && (v[10] <= 0 || v[8] <= v[9])))
         throw Error(kEArg, "one-centre parameters need g_ss > 0, h_sp > 0 and g_pp > g_p2");
       ctx->elems[s] = make_elem(Z[i], v);
+      for (int k = 0; k < SEQX_NPARAM; ++k) ctx->raw[s][k] = v[k];
       ctx->have[s] = true;
     }
     SEQX_HIP(hipMemcpyAsync(ctx->d_elems.p, ctx->elems, sizeof(ctx->elems), hipMemcpyHostToDevice, ctx->stream));
@@ -890,6 +893,23 @@ seqx_status seqx_broaden(seqx_ctx* ctx, int32_t K, const double* omega_eV, const
     broaden(st, K, dw, 1.0, df, sigma_eV, e0_eV, de_eV, npts, d.p);
     d2h(out, d.p, static_cast<size_t>(npts), st);
     SEQX_HIP(hipStreamSynchronize(st));
+  });
+}
+
+seqx_status seqx_param_gradient(seqx_job* job, int32_t mol, double* grad, size_t cap, int32_t* zvector_iterations) {
+  if (!job) return SEQX_E_ARG;
+  static_assert(SEQX_NPARAM == kNumElemParams, "parameter count of the header and the library differ");
+  return guarded(job->ctx, [&] {
+    DeviceMolecule& m = scf_mol_of(job, mol);
+    if (!job->solved || m.nroots == 0) throw Error(kEState, "no roots: call seqx_solve first");
+    const size_t need = static_cast<size_t>(m.nroots) * kNumSlots * SEQX_NPARAM;
+    if (!grad) throw Error(kEArg, "grad is NULL");
+    if (cap < need) throw Error(kEBufSize, "grad holds fewer than nroots * 3 * SEQX_NPARAM values");
+    std::vector<double> g(need);
+    GradientResult r = param_gradient(m, m.theory, job->ctx->elems, job->ctx->raw, job->dw.sig, job->gw,
+                                      job->ctx->stream, g.data());
+    std::copy(g.begin(), g.end(), grad);
+    if (zvector_iterations) *zvector_iterations = r.zvector_iterations;
   });
 }
 

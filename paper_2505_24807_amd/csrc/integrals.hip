@@ -359,35 +359,37 @@ __global__ void core_diag_kernel(int natoms, const int* __restrict__ slot, const
 
 }  // namespace
 
-void build_integrals(const DeviceMolecule& m, hipStream_t st) {
+void build_integrals(const DeviceMolecule& m, const Elem* elems, double* W, double* H, hipStream_t st) {
   const int ldw = m.np;
   // two-centre blocks, one launch per pair type (heavy-heavy, heavy-H, H-H)
   if (m.npairs[0])
     hipLaunchKernelGGL((two_centre_kernel<10, 10>), dim3(ceil_div(m.npairs[0], 128)), dim3(128), 0, st, m.npairs[0],
-                       m.pairs[0].p, m.slot.p, m.xyz.p, m.pi_off.p, m.elems, m.W.p, ldw);
+                       m.pairs[0].p, m.slot.p, m.xyz.p, m.pi_off.p, elems, W, ldw);
   if (m.npairs[1])
     hipLaunchKernelGGL((two_centre_kernel<10, 1>), dim3(ceil_div(m.npairs[1], 128)), dim3(128), 0, st, m.npairs[1],
-                       m.pairs[1].p, m.slot.p, m.xyz.p, m.pi_off.p, m.elems, m.W.p, ldw);
+                       m.pairs[1].p, m.slot.p, m.xyz.p, m.pi_off.p, elems, W, ldw);
   if (m.npairs[2])
     hipLaunchKernelGGL((two_centre_kernel<1, 1>), dim3(ceil_div(m.npairs[2], 128)), dim3(128), 0, st, m.npairs[2],
-                       m.pairs[2].p, m.slot.p, m.xyz.p, m.pi_off.p, m.elems, m.W.p, ldw);
-  hipLaunchKernelGGL(one_centre_kernel, dim3(m.natoms), dim3(128), 0, st, m.natoms, m.slot.p, m.pi_off.p, m.elems,
-                     m.W.p, ldw);
+                       m.pairs[2].p, m.slot.p, m.xyz.p, m.pi_off.p, elems, W, ldw);
+  hipLaunchKernelGGL(one_centre_kernel, dim3(m.natoms), dim3(128), 0, st, m.natoms, m.slot.p, m.pi_off.p, elems,
+                     W, ldw);
   SEQX_LAUNCH_CHECK();
   // core Hamiltonian: off-atom resonance blocks, then atom-diagonal blocks
   const int ldh = m.nao;
   if (m.npairs[0])
     hipLaunchKernelGGL((resonance_kernel<4, 4>), dim3(ceil_div(m.npairs[0], 128)), dim3(128), 0, st, m.npairs[0],
-                       m.pairs[0].p, m.slot.p, m.xyz.p, m.ao_off.p, m.elems, m.H.p, ldh);
+                       m.pairs[0].p, m.slot.p, m.xyz.p, m.ao_off.p, elems, H, ldh);
   if (m.npairs[1])
     hipLaunchKernelGGL((resonance_kernel<4, 1>), dim3(ceil_div(m.npairs[1], 128)), dim3(128), 0, st, m.npairs[1],
-                       m.pairs[1].p, m.slot.p, m.xyz.p, m.ao_off.p, m.elems, m.H.p, ldh);
+                       m.pairs[1].p, m.slot.p, m.xyz.p, m.ao_off.p, elems, H, ldh);
   if (m.npairs[2])
     hipLaunchKernelGGL((resonance_kernel<1, 1>), dim3(ceil_div(m.npairs[2], 128)), dim3(128), 0, st, m.npairs[2],
-                       m.pairs[2].p, m.slot.p, m.xyz.p, m.ao_off.p, m.elems, m.H.p, ldh);
+                       m.pairs[2].p, m.slot.p, m.xyz.p, m.ao_off.p, elems, H, ldh);
   hipLaunchKernelGGL(core_diag_kernel, dim3(m.natoms), dim3(640), 0, st, m.natoms, m.slot.p, m.ao_off.p, m.pi_off.p,
-                     m.elems, m.W.p, ldw, m.H.p, ldh);
+                     elems, W, ldw, H, ldh);
   SEQX_LAUNCH_CHECK();
 }
+
+void build_integrals(const DeviceMolecule& m, hipStream_t st) { build_integrals(m, m.elems, m.W.p, m.H.p, st); }
 
 }  // namespace seqx

@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "seqx_sigma_device_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                                 C.c_void_p, C.c_void_p, C.c_int32]),
         "seqx_solve": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts)]),
+        "seqx_param_gradient": (C.c_int, [C.c_void_p, C.c_int32, _D, C.c_size_t, _I]),
         "seqx_spectrum": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, _D]),
         "seqx_broaden": (C.c_int, [C.c_void_p, C.c_int32, _D, _D, C.c_double, C.c_double, C.c_double, C.c_int32,
                                    _D]),
@@ -404,6 +405,14 @@ class Job:
         X, Y = np.zeros((K, o, v)), np.zeros((K, o, v))
         self._check(self.lib.seqx_results(self.h, mol, _dptr(om), _dptr(X), _dptr(Y), _dptr(f), _dptr(mu)))
         return Results(om, X, Y, f, mu)
+
+    def param_gradient(self, mol=0):
+        """d omega / d theta [K, 3 (H, C, O), NPARAM] in eV per parameter unit, and the Z-vector iterations."""
+        K = getattr(self, "nroots", 0)
+        g = np.zeros((K, 3, NPARAM))
+        it = C.c_int32()
+        self._check(self.lib.seqx_param_gradient(self.h, mol, _dptr(g), g.size, C.byref(it)))
+        return g, it.value
 
     def spectrum(self, mol=0, sigma=0.1, e0=0.0, de=0.01, npts=1000):
         """Gaussian-broadened absorption profile (1/eV) of the solved roots on e0 + i de."""
