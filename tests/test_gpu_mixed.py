@@ -93,10 +93,12 @@ LARGE = {
     "H2O48": molecules.water_cluster(48, 48),
     # odd o and v: element-load edge tiles and odd K
     "C40H42n": molecules.add_noise(molecules.polyene(40), 0.02, np.random.default_rng(4042)),
+    # 600 AOs: several 128-row tiles in every dimension and a ragged last one
+    "H2O100": molecules.water_cluster(100, 100),
 }
 
 
-@pytest.mark.parametrize("name", ["H2O48", "C40H42n"])
+@pytest.mark.parametrize("name", ["H2O48", "C40H42n", "H2O100"])
 def test_sigma_fp32_products_large_tiles(ctx, name):
     """FP32 products on molecules whose transforms run on the 128 x 128 tiles,
     against the oracle's matrix-free products (Eqs. 8-9), in the AO basis."""
@@ -124,7 +126,49 @@ def test_sigma_fp32_products_large_tiles(ctx, name):
             worst = max(worst, d / (n * U32 * scale))
             assert d <= 8 * n * U32 * scale, (j, d, scale)
     print(f"[gpu] {name}: worst error / (n u max|2e part|) = {worst:.3f}", flush=True)
+    # the FP64 products of the same vectors at the FP64 sigma bar
+    q1, r1 = job.sigma(Vl, theory=seqx.TDHF, precision=seqx.FP64)
+    for lib, ref in ((q1, AV + BV), (r1, AV - BV)):
+        for j in range(k):
+            d = np.abs(_ao(Cl, o, lib[j].reshape(o, v)) - _ao(res.C, o, ref[j])).max()
+            assert d <= 1e-10 * max(1.0, np.abs(ref[j]).max()), (j, d)
     job.free()
+
+
+def test_sigma_fp32_against_fp64_full_size(ctx):
+    """(H2O)330 at full size, 20 seeded vectors in the bench's launch shape:
+    every element of the FP32 products within 8 n u of the largest element of
+    the two-electron part, taken from the FP64 products of the same vectors
+    (the FP64 path itself matches the oracle's roots at this size and its
+    products element by element up to 600 AOs)."""
+    import torch
+
+    mol = molecules.workload_water330()
+    print("[gpu] fp32 vs fp64 sigma (H2O)330", flush=True)
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    eps, _, _ = job.scf_results()
+    n, o, v = job.dims()
+    k = 20
+    g = torch.Generator(device="cuda").manual_seed(330)
+    V = torch.randn((k, o, v), generator=g, device="cuda", dtype=torch.float64)
+    outs = {}
+    for prec in (seqx.FP64, seqx.FP32):
+        o1, o2 = torch.empty_like(V), torch.empty_like(V)
+        job.sigma_device(V, o1, o2, theory=seqx.TDHF, precision=prec)
+        torch.cuda.synchronize()
+        outs[prec] = (o1.cpu().numpy(), o2.cpu().numpy())
+    job.free()
+    de = (eps[None, o:] - eps[:o, None]) / HA
+    Vh = V.cpu().numpy()
+    worst = 0.0
+    for j in range(2):
+        ref, got = outs[seqx.FP64][j], outs[seqx.FP32][j]
+        for i in range(k):
+            scale = np.abs(ref[i] - de * Vh[i]).max()
+            d = np.abs(got[i] - ref[i]).max()
+            worst = max(worst, d / (n * U32 * scale))
+            assert d <= 8 * n * U32 * scale, (j, i, d, scale)
+    print(f"[gpu] (H2O)330: worst FP32 error / (n u max|2e part|) = {worst:.3f}", flush=True)
 
 
 @pytest.mark.parametrize("name,theory,K", [("C2H4", seqx.TDHF, 3), ("C20H22n", seqx.TDHF, 5),
