@@ -335,6 +335,8 @@ def main():
     ap.add_argument("--cpu-vectors", type=int, default=2)
     ap.add_argument("--sigma-only", type=int, default=0, metavar="K",
                     help="time only K-vector sigma builds of (H2O)330 (for counter passes) and exit")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 512-molecule batched CIS section (for profiling) and exit")
     ap.add_argument("--nroots-curve", type=str, default="", metavar="K1,K2,...",
                     help="time CIS solves of 200-, 400- and 990-atom molecules for these root counts and exit")
     ap.add_argument("--curve-budgets-gb", type=str, default="0,4",
@@ -367,6 +369,9 @@ def main():
     pr = params.load()
     ctx.set_params(*seqx.params_table(pr))
     mol = molecules.workload_water330()
+    if args.batched_only:
+        print(json.dumps({"batched_c4": batched_c4(ctx, args.steps, loop=not args.no_batched_loop)}))
+        return
     if args.nroots_curve:
         roots = [int(x) for x in args.nroots_curve.split(",")]
         budgets = [float(x) for x in args.curve_budgets_gb.split(",")]

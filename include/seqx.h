@@ -223,7 +223,9 @@ seqx_status seqx_set_allocator(seqx_ctx* ctx, void* (*alloc)(size_t bytes, void*
  * The job keeps C, eps, the ERI tables and the core Hamiltonian on the device.
  * From four molecules on (and no caller allocator set) the molecules are
  * prepared concurrently by library threads on internal streams, after the
- * context's stream has drained; the call returns once all of them are done. */
+ * context's stream has drained; the call returns once all of them are done.
+ * The environment variable SEQX_PREPARE_THREADS (1 .. 64, default 8) sets the
+ * number of those threads; 1 prepares on the calling thread. */
 seqx_status seqx_prepare(seqx_ctx* ctx, int32_t nmol, const int32_t* natoms, const int32_t* Z,
                          const double* xyz_angstrom, const seqx_scf_opts* opts, seqx_job** out);
 void seqx_job_free(seqx_job* job);

@@ -195,6 +195,18 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
 constexpr int kPrepareParallelMin = 4;
 constexpr int kPrepareThreads = 8;
 
+// Worker threads of a batched preparation: SEQX_PREPARE_THREADS (1 .. 64) when
+// set, else kPrepareThreads; 1 keeps the preparation on the calling thread.
+int prepare_threads() {
+  static const int n = [] {
+    const char* s = std::getenv("SEQX_PREPARE_THREADS");
+    if (!s || !*s) return kPrepareThreads;
+    const int v = std::atoi(s);
+    return v >= 1 && v <= 64 ? v : kPrepareThreads;
+  }();
+  return n;
+}
+
 void prepare_parallel(seqx_ctx* ctx, seqx_job* job, int nmol, const int32_t* natoms, const int32_t* Z,
                       const double* xyz, const ScfOptions& so, bool integrals_only) {
   std::vector<size_t> offs(nmol, 0);
@@ -202,7 +214,7 @@ void prepare_parallel(seqx_ctx* ctx, seqx_job* job, int nmol, const int32_t* nat
   std::vector<std::unique_ptr<DeviceMolecule>> mols(nmol);
   std::vector<double> t_int(nmol, 0.0), t_scf(nmol, 0.0);
   std::atomic<int> next{0};
-  const int nw = std::min(nmol, kPrepareThreads);
+  const int nw = std::min(nmol, prepare_threads());
   std::vector<std::exception_ptr> errs(nw);
   SEQX_HIP(hipStreamSynchronize(ctx->stream));  // element data uploaded on the context stream
   std::vector<std::thread> pool;
@@ -539,7 +551,7 @@ seqx_status seqx_prepare(seqx_ctx* ctx, int32_t nmol, const int32_t* natoms, con
       integrals_only = opts->integrals_only != 0;
     }
     hipStream_t st = ctx->stream;
-    if (nmol >= kPrepareParallelMin && !ctx->allocator) {
+    if (nmol >= kPrepareParallelMin && !ctx->allocator && prepare_threads() > 1) {
       prepare_parallel(ctx, job.get(), nmol, natoms, Z, xyz, so, integrals_only);
       return;
     }

@@ -350,51 +350,95 @@ __global__ void __launch_bounds__(256) items_kernel(int nmol, const MolDesc* __r
   }
 }
 
-// Inner products of b with the rows s0 + 4 i (i < 4, rows < ns) of V, one
-// wavefront: four independent load streams over b and the rows.
-__device__ __forceinline__ void wave_dots4(const double* __restrict__ V, long nov, int s0, int ns,
-                                           const double* __restrict__ b, double* d) {
+// Subspace steps of a molecule are split over kXChunks blocks along the nov
+// entries, so that the largest molecules spread over several CUs; partial
+// inner products go to per-chunk slots and are summed in a fixed order.
+constexpr int kXChunks = 8;
+constexpr int kPartStride = kBatchMaxSub * 2 * kBatchMaxRoots;  // one chunk's [s][j] partials
+
+__device__ __forceinline__ long chunk_begin(long nov, int ch) { return nov * ch / kXChunks; }
+
+// Inner products over x in [x0, x1) of up to 16 vectors b_u (nb of them) with
+// the rows s0, s0 + 1 of V (rows past ns repeat the last), one wavefront: each
+// V element is read once, the b_u stay in L1/L2.  Results in every lane: d[i][u].
+__device__ __forceinline__ void wave_dots2x16(const double* __restrict__ V, long nov, int s0, int ns, long x0,
+                                              long x1, const double* const* b, int nb,
+                                              double (*d)[kBatchMaxRoots]) {
   const int lane = threadIdx.x & 63;
-  const double* a[4];
+  const double* a0 = V + static_cast<long>(min(s0, ns - 1)) * nov;
+  const double* a1 = V + static_cast<long>(min(s0 + 1, ns - 1)) * nov;
+  double acc[2][kBatchMaxRoots];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) a[i] = V + static_cast<long>(min(s0 + 4 * i, ns - 1)) * nov;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (long x = lane; x < nov; x += 64) {
-    const double bx = b[x];
+  for (int u = 0; u < kBatchMaxRoots; ++u) acc[0][u] = acc[1][u] = 0.0;
+  for (long x = x0 + lane; x < x1; x += 64) {
+    const double v0 = a0[x], v1 = a1[x];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] += a[i][x] * bx;
+    for (int u = 0; u < kBatchMaxRoots; ++u)
+      if (u < nb) {
+        const double bx = b[u][x];
+        acc[0][u] += v0 * bx;
+        acc[1][u] += v1 * bx;
+      }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) d[i] = wave_sum(acc[i]);
+  for (int u = 0; u < kBatchMaxRoots; ++u)
+    if (u < nb) {
+      d[0][u] = wave_sum(acc[0][u]);
+      d[1][u] = wave_sum(acc[1][u]);
+    }
 }
 
-// New columns of M = V^T A V (column-major, ld Smax), both triangles: block
-// (m, j) forms column S_m + j against rows s <= S_m + j.  S is advanced by
-// advance_kernel afterwards.
-__global__ void __launch_bounds__(256) project_kernel(const MolDesc* __restrict__ mols, int Smax,
-                                                      const double* __restrict__ Vp, const double* __restrict__ AVp,
+// New columns of M = V^T A V, first half: block (m, c) forms the partial
+// inner products over chunk c of every new product A V_j (j < knew_m, in
+// groups of 16) with every basis row s < S_m + knew_m.
+__global__ void __launch_bounds__(256) project_part_kernel(const MolDesc* __restrict__ mols,
+                                                           const double* __restrict__ Vp,
+                                                           const double* __restrict__ AVp, const int* __restrict__ S,
+                                                           const int* __restrict__ knew,
+                                                           const int* __restrict__ active, double* __restrict__ part) {
+  const int m = blockIdx.x, ch = blockIdx.y;
+  if (!active[m]) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov, x0 = chunk_begin(nov, ch), x1 = chunk_begin(nov, ch + 1);
+  const int S0 = S[m], kn = knew[m], ns = S0 + kn;
+  const double* V = Vp + md.vbase;
+  double* P = part + (static_cast<long>(m) * kXChunks + ch) * kPartStride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < kn; j0 += kBatchMaxRoots) {
+    const int nb = min(kBatchMaxRoots, kn - j0);
+    const double* b[kBatchMaxRoots];
+#pragma unroll
+    for (int u = 0; u < kBatchMaxRoots; ++u) b[u] = AVp + md.vbase + static_cast<long>(S0 + j0 + min(u, nb - 1)) * nov;
+    for (int s0 = 2 * wave; s0 < ns; s0 += 8) {
+      double d[2][kBatchMaxRoots];
+      wave_dots2x16(V, nov, s0, ns, x0, x1, b, nb, d);
+      if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int u = 0; u < kBatchMaxRoots; ++u)
+            if (u < nb && s0 + i < ns) P[(s0 + i) * 2 * kBatchMaxRoots + j0 + u] = d[i][u];
+    }
+  }
+}
+
+// Second half: sum the chunks in order and write both triangles of the new
+// columns (column-major, ld Smax).  S is advanced by advance_kernel afterwards.
+__global__ void __launch_bounds__(256) project_kernel(int Smax, const double* __restrict__ part,
                                                       double* __restrict__ Mp, const int* __restrict__ S,
                                                       const int* __restrict__ knew, const int* __restrict__ active) {
-  const int m = blockIdx.x, jn = blockIdx.y;
-  if (!active[m] || jn >= knew[m]) return;
-  const MolDesc md = mols[m];
-  const long nov = md.nov;
-  const int j = S[m] + jn;
-  const double* V = Vp + md.vbase;
-  const double* b = AVp + md.vbase + j * nov;
+  const int m = blockIdx.x;
+  if (!active[m]) return;
+  const int S0 = S[m], kn = knew[m], ns = S0 + kn;
   double* M = Mp + static_cast<long>(m) * Smax * Smax;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int s0 = wave; s0 <= j; s0 += 16) {  // rows s0, s0 + 4, s0 + 8, s0 + 12
-    double d[4];
-    wave_dots4(V, nov, s0, j + 1, b, d);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int s = s0 + 4 * i;
-      if (lane == 0 && s <= j) {
-        M[s + static_cast<long>(j) * Smax] = d[i];
-        M[j + static_cast<long>(s) * Smax] = d[i];
-      }
-    }
+  const double* P = part + static_cast<long>(m) * kXChunks * kPartStride;
+  for (int idx = threadIdx.x; idx < ns * kn; idx += 256) {
+    const int sidx = idx / kn, jn = idx % kn, j = S0 + jn;
+    if (sidx > j) continue;
+    double d = 0.0;
+    for (int c = 0; c < kXChunks; ++c) d += P[c * kPartStride + sidx * 2 * kBatchMaxRoots + jn];
+    M[sidx + static_cast<long>(j) * Smax] = d;
+    M[j + static_cast<long>(sidx) * Smax] = d;
   }
 }
 
@@ -483,67 +527,92 @@ __global__ void __launch_bounds__(kEigThreads) eig_kernel(int Smax, const double
   if (threadIdx.x == 0) evn[m] = n;
 }
 
-// Ritz vector j of molecule m, its residual r = A x - w x and norm; for an
-// unconverged root the preconditioned correction r / (w - de) (|w - de| kept
-// >= 1e-8) replaces r in Wc.
-__global__ void __launch_bounds__(256) ritz_kernel(const MolDesc* __restrict__ mols, int K, int Smax, double tol,
+// Ritz vectors of molecule m, X_j = sum_s evec(s, j) V_s, and residuals
+// r_j = A X_j - w_j X_j into Wc, for all K roots in one pass over V and A V
+// (each basis element read once); block (m, c) takes chunk c of the nov
+// entries and leaves its partial sums of |r_j|^2 in rpart[m][c][j].
+__global__ void __launch_bounds__(256) ritz_kernel(const MolDesc* __restrict__ mols, int K, int Smax,
                                                    const double* __restrict__ Vp, const double* __restrict__ AVp,
                                                    const double* __restrict__ evec, const double* __restrict__ eval,
                                                    const int* __restrict__ S, const int* __restrict__ active,
                                                    double* __restrict__ Xp, double* __restrict__ Wcp,
-                                                   double* __restrict__ omega, double* __restrict__ rnorm) {
-  __shared__ double c[kBatchMaxSub];
-  __shared__ double red[256];
-  const int m = blockIdx.x, j = blockIdx.y;
+                                                   double* __restrict__ omega, double* __restrict__ rpart) {
+  __shared__ double c[kBatchMaxRoots][kBatchMaxSub];
+  __shared__ double wr[kBatchMaxRoots];
+  __shared__ double red[4][kBatchMaxRoots];
+  const int m = blockIdx.x, ch = blockIdx.y;
   if (!active[m]) return;
   const MolDesc md = mols[m];
   const long nov = md.nov;
   const int n = S[m];
-  for (int s = threadIdx.x; s < n; s += 256) c[s] = evec[static_cast<long>(m) * Smax * Smax + s + static_cast<long>(j) * Smax];
+  for (int idx = threadIdx.x; idx < K * n; idx += 256) {
+    const int j = idx / n, sidx = idx % n;
+    c[j][sidx] = evec[static_cast<long>(m) * Smax * Smax + sidx + static_cast<long>(j) * Smax];
+  }
+  if (threadIdx.x < K) wr[threadIdx.x] = eval[static_cast<long>(m) * Smax + threadIdx.x];
   __syncthreads();
-  const double w = eval[static_cast<long>(m) * Smax + j];
   const double* V = Vp + md.vbase;
   const double* AV = AVp + md.vbase;
-  double* X = Xp + md.xbase + j * nov;
-  double* Wc = Wcp + md.xbase + j * nov;
-  double ss = 0.0;
-  for (long x = threadIdx.x; x < nov; x += 256) {
-    double xv = 0.0, av = 0.0;
-    for (int s = 0; s < n; ++s) {
-      xv += c[s] * V[s * nov + x];
-      av += c[s] * AV[s * nov + x];
+  double* X = Xp + md.xbase;
+  double* Wc = Wcp + md.xbase;
+  const long x0 = chunk_begin(nov, ch), x1 = chunk_begin(nov, ch + 1);
+  double ss[kBatchMaxRoots];
+#pragma unroll
+  for (int j = 0; j < kBatchMaxRoots; ++j) ss[j] = 0.0;
+  for (long x = x0 + threadIdx.x; x < x1; x += 256) {
+    double xv[kBatchMaxRoots], av[kBatchMaxRoots];
+#pragma unroll
+    for (int j = 0; j < kBatchMaxRoots; ++j) xv[j] = av[j] = 0.0;
+    for (int sidx = 0; sidx < n; ++sidx) {
+      const double v = V[sidx * nov + x], a = AV[sidx * nov + x];
+#pragma unroll
+      for (int j = 0; j < kBatchMaxRoots; ++j)
+        if (j < K) {
+          xv[j] += c[j][sidx] * v;
+          av[j] += c[j][sidx] * a;
+        }
     }
-    const double r = av - w * xv;
-    X[x] = xv;
-    Wc[x] = r;
-    ss += r * r;
+#pragma unroll
+    for (int j = 0; j < kBatchMaxRoots; ++j)
+      if (j < K) {
+        const double r = av[j] - wr[j] * xv[j];
+        X[j * nov + x] = xv[j];
+        Wc[j * nov + x] = r;
+        ss[j] += r * r;
+      }
   }
-  const double rn = sqrt(block_sum(ss, red));
-  if (threadIdx.x == 0) {
-    rnorm[m * K + j] = rn;
-    omega[m * K + j] = w;
-  }
-  if (rn > tol)
-    for (long x = threadIdx.x; x < nov; x += 256) {
-      double den = w - (md.eps[md.o + x % md.v] - md.eps[x / md.v]);
-      if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
-      Wc[x] = Wc[x] / den;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kBatchMaxRoots; ++j)
+    if (j < K) {
+      const double t = wave_sum(ss[j]);
+      if (lane == 0) red[wave][j] = t;
     }
+  __syncthreads();
+  if (threadIdx.x < K)
+    rpart[(static_cast<long>(m) * kXChunks + ch) * kBatchMaxRoots + threadIdx.x] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  if (ch == 0 && threadIdx.x < K) omega[m * K + threadIdx.x] = wr[threadIdx.x];
 }
 
 // Convergence and bookkeeping for every molecule; counts the active ones.
 __global__ void __launch_bounds__(256) select_kernel(int nmol, int K, int Smax, double tol,
-                                                     const double* __restrict__ rnorm, const int* __restrict__ S,
-                                                     int* knew, int* active, int* coll, int* qcol, int* unc, int* conv,
-                                                     int* counters) {
+                                                     const double* __restrict__ rpart, double* __restrict__ rnorm,
+                                                     const int* __restrict__ S, int* knew, int* active, int* coll,
+                                                     int* qcol, int* unc, int* conv, int* counters) {
   __shared__ double red[256];
   const int iter = counters[2] + 1;
   double nact = 0.0;
   for (int m = threadIdx.x; m < nmol; m += 256) {
     if (!active[m]) continue;
     int nu = 0;
-    for (int j = 0; j < K; ++j)
-      if (rnorm[m * K + j] > tol) unc[m * K + nu++] = j;
+    for (int j = 0; j < K; ++j) {
+      double r2 = 0.0;
+      for (int c = 0; c < kXChunks; ++c) r2 += rpart[(static_cast<long>(m) * kXChunks + c) * kBatchMaxRoots + j];
+      const double rn = sqrt(r2);
+      rnorm[m * K + j] = rn;
+      if (rn > tol) unc[m * K + nu++] = j;
+    }
     if (nu == 0) {
       active[m] = 0;
       conv[m] = iter;
@@ -619,44 +688,125 @@ __global__ void __launch_bounds__(256) collapse_copy_kernel(const MolDesc* __res
   }
 }
 
-// Corrections of the unconverged roots: remove their components along the
-// basis (classical Gram-Schmidt, two passes); block (m, u) for correction u.
-// A collapsed molecule's basis is its first qcol rows.
-__global__ void __launch_bounds__(256) deflate_kernel(const MolDesc* __restrict__ mols, int K,
-                                                      const double* __restrict__ Vp, double* __restrict__ Wcp,
+// Corrections of the unconverged roots, first step: precondition the
+// residuals in place, r / (w - de) with |w - de| kept >= 1e-8, and leave the
+// partial sums of their squared norms per chunk (the norms before deflation).
+__global__ void __launch_bounds__(256) precond_kernel(const MolDesc* __restrict__ mols, int K,
+                                                      double* __restrict__ Wcp, const int* __restrict__ knew,
+                                                      const int* __restrict__ active, const int* __restrict__ unc,
+                                                      const double* __restrict__ omega, double* __restrict__ n0part) {
+  __shared__ double wu[kBatchMaxRoots];
+  __shared__ double red[4][kBatchMaxRoots];
+  const int m = blockIdx.x, ch = blockIdx.y;
+  if (!active[m]) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov, x0 = chunk_begin(nov, ch), x1 = chunk_begin(nov, ch + 1);
+  const int nu = knew[m];
+  double* w[kBatchMaxRoots];
+#pragma unroll
+  for (int u = 0; u < kBatchMaxRoots; ++u) w[u] = Wcp + md.xbase + unc[m * K + min(u, nu - 1)] * nov;
+  if (threadIdx.x < nu) wu[threadIdx.x] = omega[m * K + unc[m * K + threadIdx.x]];
+  __syncthreads();
+  double n0[kBatchMaxRoots];
+#pragma unroll
+  for (int u = 0; u < kBatchMaxRoots; ++u) n0[u] = 0.0;
+  for (long x = x0 + threadIdx.x; x < x1; x += 256) {
+    const double de = md.eps[md.o + x % md.v] - md.eps[x / md.v];
+#pragma unroll
+    for (int u = 0; u < kBatchMaxRoots; ++u)
+      if (u < nu) {
+        double den = wu[u] - de;
+        if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
+        const double t = w[u][x] / den;
+        w[u][x] = t;
+        n0[u] += t * t;
+      }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < kBatchMaxRoots; ++u)
+    if (u < nu) {
+      const double t = wave_sum(n0[u]);
+      if (lane == 0) red[wave][u] = t;
+    }
+  __syncthreads();
+  if (threadIdx.x < nu)
+    n0part[(static_cast<long>(m) * kXChunks + ch) * kBatchMaxRoots + threadIdx.x] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// Classical Gram-Schmidt of the corrections against the basis (its first
+// qcol rows after a collapse), one half-pass each: partial inner products
+// per chunk ...
+__global__ void __launch_bounds__(256) gs_dots_kernel(const MolDesc* __restrict__ mols, int K,
+                                                      const double* __restrict__ Vp, const double* __restrict__ Wcp,
                                                       const int* __restrict__ S, const int* __restrict__ knew,
                                                       const int* __restrict__ active, const int* __restrict__ coll,
                                                       const int* __restrict__ qcol, const int* __restrict__ unc,
-                                                      double* __restrict__ n0p) {
-  __shared__ double h[kBatchMaxSub];
-  __shared__ double red[256];
-  const int m = blockIdx.x, u = blockIdx.y;
-  if (!active[m] || u >= knew[m]) return;
+                                                      double* __restrict__ part) {
+  const int m = blockIdx.x, ch = blockIdx.y;
+  if (!active[m]) return;
   const MolDesc md = mols[m];
-  const long nov = md.nov;
+  const long nov = md.nov, x0 = chunk_begin(nov, ch), x1 = chunk_begin(nov, ch + 1);
   const int nb = coll[m] ? qcol[m] : S[m];
-  const double* V = Vp + md.vbase;
-  double* w = Wcp + md.xbase + unc[m * K + u] * nov;
-  double n0 = 0.0;
-  for (long x = threadIdx.x; x < nov; x += 256) n0 += w[x] * w[x];
-  n0 = block_sum(n0, red);
-  if (threadIdx.x == 0) n0p[m * K + u] = sqrt(n0);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int s0 = wave; s0 < nb; s0 += 16) {  // rows s0, s0 + 4, s0 + 8, s0 + 12
-      double d[4];
-      wave_dots4(V, nov, s0, nb, w, d);
+  const int nu = knew[m];
+  const double* w[kBatchMaxRoots];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (lane == 0 && s0 + 4 * i < nb) h[s0 + 4 * i] = d[i];
+  for (int u = 0; u < kBatchMaxRoots; ++u) w[u] = Wcp + md.xbase + unc[m * K + min(u, nu - 1)] * nov;
+  double* P = part + (static_cast<long>(m) * kXChunks + ch) * kPartStride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int s0 = 2 * wave; s0 < nb; s0 += 8) {
+    double d[2][kBatchMaxRoots];
+    wave_dots2x16(Vp + md.vbase, nov, s0, nb, x0, x1, w, nu, d);
+    if (lane == 0)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int u = 0; u < kBatchMaxRoots; ++u)
+          if (u < nu && s0 + i < nb) P[(s0 + i) * 2 * kBatchMaxRoots + u] = d[i][u];
+  }
+}
+
+// ... then the update of chunk c: h = the inner products summed over the
+// chunks in order, w_u -= sum_s h[s][u] V_s.
+__global__ void __launch_bounds__(256) gs_update_kernel(const MolDesc* __restrict__ mols, int K,
+                                                        const double* __restrict__ Vp, double* __restrict__ Wcp,
+                                                        const int* __restrict__ S, const int* __restrict__ knew,
+                                                        const int* __restrict__ active, const int* __restrict__ coll,
+                                                        const int* __restrict__ qcol, const int* __restrict__ unc,
+                                                        const double* __restrict__ part) {
+  __shared__ double h[kBatchMaxSub][kBatchMaxRoots];
+  const int m = blockIdx.x, ch = blockIdx.y;
+  if (!active[m]) return;
+  const MolDesc md = mols[m];
+  const long nov = md.nov, x0 = chunk_begin(nov, ch), x1 = chunk_begin(nov, ch + 1);
+  const int nb = coll[m] ? qcol[m] : S[m];
+  const int nu = knew[m];
+  const double* P = part + static_cast<long>(m) * kXChunks * kPartStride;
+  for (int idx = threadIdx.x; idx < nb * nu; idx += 256) {
+    const int sidx = idx / nu, u = idx % nu;
+    double d = 0.0;
+    for (int c = 0; c < kXChunks; ++c) d += P[c * kPartStride + sidx * 2 * kBatchMaxRoots + u];
+    h[sidx][u] = d;
+  }
+  __syncthreads();
+  const double* V = Vp + md.vbase;
+  double* w[kBatchMaxRoots];
+#pragma unroll
+  for (int u = 0; u < kBatchMaxRoots; ++u) w[u] = Wcp + md.xbase + unc[m * K + min(u, nu - 1)] * nov;
+  for (long x = x0 + threadIdx.x; x < x1; x += 256) {
+    double t[kBatchMaxRoots];
+#pragma unroll
+    for (int u = 0; u < kBatchMaxRoots; ++u) t[u] = u < nu ? w[u][x] : 0.0;
+    for (int sidx = 0; sidx < nb; ++sidx) {
+      const double v = V[sidx * nov + x];
+#pragma unroll
+      for (int u = 0; u < kBatchMaxRoots; ++u)
+        if (u < nu) t[u] -= h[sidx][u] * v;
     }
-    __syncthreads();
-    for (long x = threadIdx.x; x < nov; x += 256) {
-      double t = w[x];
-      for (int s = 0; s < nb; ++s) t -= h[s] * V[s * nov + x];
-      w[x] = t;
-    }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kBatchMaxRoots; ++u)
+      if (u < nu) w[u][x] = t[u];
   }
 }
 
@@ -668,7 +818,7 @@ __global__ void __launch_bounds__(256) append_kernel(const MolDesc* __restrict__
                                                      int* knew, int* active, int* coll, const int* __restrict__ qcol,
                                                      const int* __restrict__ unc, int* conv,
                                                      const int* __restrict__ counters,
-                                                     const double* __restrict__ n0p) {
+                                                     const double* __restrict__ n0part) {
   __shared__ double red[256];
   const int m = blockIdx.x;
   if (!active[m]) return;
@@ -693,7 +843,9 @@ __global__ void __launch_bounds__(256) append_kernel(const MolDesc* __restrict__
     double nw = 0.0;
     for (long x = threadIdx.x; x < nov; x += 256) nw += w[x] * w[x];
     nw = sqrt(block_sum(nw, red));
-    if (nw > 1e-8 * n0p[m * K + u] && nw > 1e-14) {
+    double n02 = 0.0;
+    for (int c = 0; c < kXChunks; ++c) n02 += n0part[(static_cast<long>(m) * kXChunks + c) * kBatchMaxRoots + u];
+    if (nw > 1e-8 * sqrt(n02) && nw > 1e-14) {
       double* dst = V + static_cast<long>(S0 + acc) * nov;
       const double inv = 1.0 / nw;
       for (long x = threadIdx.x; x < nov; x += 256) dst[x] = w[x] * inv;
@@ -816,7 +968,9 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
   w.eval.ensure(static_cast<size_t>(nmol) * Smax);
   w.omega.ensure(static_cast<size_t>(nmol) * K);
   w.rnorm.ensure(static_cast<size_t>(nmol) * K);
-  w.n0.ensure(static_cast<size_t>(nmol) * K);
+  w.rpart.ensure(static_cast<size_t>(nmol) * kXChunks * kBatchMaxRoots);
+  w.part.ensure(static_cast<size_t>(nmol) * kXChunks * kPartStride);
+  w.n0.ensure(static_cast<size_t>(nmol) * kXChunks * kBatchMaxRoots);
   if (f32) w.scratch32.ensure(static_cast<size_t>(G) * scr_stride);
   else w.scratch64.ensure(static_cast<size_t>(G) * scr_stride);
 
@@ -910,22 +1064,31 @@ BatchResult batched_cis(const std::vector<DeviceMolecule*>& mols, const BatchOpt
                          w.active.p, w.items.p, w.counters.p, w.nsig.p);
       launch_sigma();
       if (timed) hipLaunchKernelGGL(stamp_span_kernel, dim3(1), dim3(256), 0, st, G, w.stamps.p, w.nsig.p + 1);
-      hipLaunchKernelGGL(project_kernel, dim3(nmol, maxnew), dim3(256), 0, st, w.mols.p, Smax, w.V.p, w.AV.p, w.Mp.p,
-                         w.S.p, w.knew.p, w.active.p);
+      hipLaunchKernelGGL(project_part_kernel, dim3(nmol, kXChunks), dim3(256), 0, st, w.mols.p, w.V.p, w.AV.p,
+                         w.S.p, w.knew.p, w.active.p, w.part.p);
+      hipLaunchKernelGGL(project_kernel, dim3(nmol), dim3(256), 0, st, Smax, w.part.p, w.Mp.p, w.S.p, w.knew.p,
+                         w.active.p);
       hipLaunchKernelGGL(advance_kernel, dim3(ceil_div(nmol, 256)), dim3(256), 0, st, nmol, w.S.p, w.knew.p,
                          w.active.p);
       hipLaunchKernelGGL(eig_kernel, dim3(nmol), dim3(kEigThreads), 0, st, Smax, w.Mp.p, w.S.p, w.active.p,
                          w.evn.p, w.evec.p, w.eval.p);
-      hipLaunchKernelGGL(ritz_kernel, dim3(nmol, K), dim3(256), 0, st, w.mols.p, K, Smax, opt.tol, w.V.p, w.AV.p,
-                         w.evec.p, w.eval.p, w.S.p, w.active.p, w.X.p, w.Wc.p, w.omega.p, w.rnorm.p);
-      hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, st, nmol, K, Smax, opt.tol, w.rnorm.p, w.S.p,
-                         w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.conv.p, w.counters.p);
+      hipLaunchKernelGGL(ritz_kernel, dim3(nmol, kXChunks), dim3(256), 0, st, w.mols.p, K, Smax, w.V.p, w.AV.p,
+                         w.evec.p, w.eval.p, w.S.p, w.active.p, w.X.p, w.Wc.p, w.omega.p, w.rpart.p);
+      hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, st, nmol, K, Smax, opt.tol, w.rpart.p, w.rnorm.p,
+                         w.S.p, w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.conv.p, w.counters.p);
       hipLaunchKernelGGL(collapse_kernel, dim3(nmol, Q), dim3(256), 0, st, w.mols.p, Smax, w.V.p, w.AV.p, w.evec.p,
                          w.S.p, w.coll.p, w.qcol.p, w.TV.p, w.TAV.p);
       hipLaunchKernelGGL(collapse_copy_kernel, dim3(nmol, Q + 1), dim3(256), 0, st, w.mols.p, Smax, w.TV.p, w.TAV.p,
                          w.eval.p, w.S.p, w.coll.p, w.qcol.p, w.V.p, w.AV.p, w.Mp.p, w.evn.p);
-      hipLaunchKernelGGL(deflate_kernel, dim3(nmol, K), dim3(256), 0, st, w.mols.p, K, w.V.p, w.Wc.p, w.S.p,
-                         w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.n0.p);
+      const dim3 chunks(nmol, kXChunks);
+      hipLaunchKernelGGL(precond_kernel, chunks, dim3(256), 0, st, w.mols.p, K, w.Wc.p, w.knew.p, w.active.p,
+                         w.unc.p, w.omega.p, w.n0.p);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(gs_dots_kernel, chunks, dim3(256), 0, st, w.mols.p, K, w.V.p, w.Wc.p, w.S.p, w.knew.p,
+                           w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.part.p);
+        hipLaunchKernelGGL(gs_update_kernel, chunks, dim3(256), 0, st, w.mols.p, K, w.V.p, w.Wc.p, w.S.p,
+                           w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.part.p);
+      }
       hipLaunchKernelGGL(append_kernel, dim3(nmol), dim3(256), 0, st, w.mols.p, K, Smax, w.V.p, w.Wc.p, w.S.p,
                          w.knew.p, w.active.p, w.coll.p, w.qcol.p, w.unc.p, w.conv.p, w.counters.p, w.n0.p);
       SEQX_LAUNCH_CHECK();

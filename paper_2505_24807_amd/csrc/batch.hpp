@@ -78,7 +78,7 @@ struct BatchWork {
   DBuf<int2> items;
   DBuf<long long> nsig;    // [0] sigma vectors, [1] wall-clock ticks inside sigma launches, [2] flops
   DBuf<long long> stamps;  // start / end tick of each workgroup of the last sigma launch
-  DBuf<double> V, AV, X, Wc, TV, TAV, Mp, evec, eval, omega, rnorm, n0;
+  DBuf<double> V, AV, X, Wc, TV, TAV, Mp, evec, eval, omega, rnorm, rpart, part, n0;
   DBuf<float> scratch32;
   DBuf<double> scratch64;
   DBuf<double> fin;
