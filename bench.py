@@ -31,7 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "σ-vectors/s and time-to-10-roots at 1e-4 eV, learned/mixed vs plain FP64"
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # TFLOP/s, dense, MI355X
+# TFLOP/s, dense, MI355X; split bfloat16 takes three bfloat16 products per product
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3}
 HBM_PEAK_GBS = 8000.0
 NROOTS, TOL = 10, 1e-5
 
@@ -175,12 +176,12 @@ def roofline_of(r, dtype):
     ms, launches, flops = phase[0, p], phase[1, p], phase[2, p]
     avg_s = ms * 1e-3 / launches
     achieved = flops / launches / avg_s / 1e12
-    ctype = "double" if dtype == "fp64" else "float"
+    ctype = {"fp64": "double", "fp32": "float", "bf16x3": "float, split bfloat16"}[dtype]
     traffic = _traffic("gemm128_kernel<float>:G_C_virt", flops / launches) if (dtype == "fp32" and p == 3) else None
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[dtype], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[dtype], 4),
             "traffic": round(traffic / 1e9, 3) if traffic else None, "traffic_unit": "GB per launch",
-            "kernel": f"gemm128_kernel<{ctype}> ({seqx.Stats.PHASES[p]})",
+            "kernel": (f"gemm128x3_kernel<{ctype}>" if dtype == "bf16x3" else f"gemm128_kernel<{ctype}>") + f" ({seqx.Stats.PHASES[p]})",
             "flops_per_launch": flops / launches, "avg_launch_ms": ms / launches}
 
 
@@ -322,8 +323,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
-                    help="transform precision of the timed run (fp32: mixed mode finishing in FP64)")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp64"], default="fp32",
+                    help="transform precision of the timed run (fp32, bf16x3: mixed modes finishing in FP64)")
     ap.add_argument("--guess", choices=["learned", "gap"], default="learned",
                     help="starting space of the timed run (learned: the packaged network's 2K best pairs)")
     ap.add_argument("--no-fp64-comparison", action="store_true")
@@ -353,6 +354,8 @@ def main():
     from paper_2505_24807_amd import seqx
     from synthetic import molecules, params
 
+    global PRECISIONS
+    PRECISIONS = {"fp32": seqx.FP32, "bf16x3": seqx.BF16X3, "fp64": seqx.FP64}
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.init()
@@ -379,20 +382,21 @@ def main():
         print(json.dumps({"nroots_curve": rows}))
         return
     if args.sigma_only > 0:
-        prec = seqx.FP32 if args.precision == "fp32" else seqx.FP64
-        print(json.dumps(sigma_only(ctx, mol, args.sigma_only, args.steps, prec)))
+        print(json.dumps(sigma_only(ctx, mol, args.sigma_only, args.steps, PRECISIONS[args.precision])))
         return
     ref = _golden()
     K = args.steps
-    prec = seqx.FP32 if args.precision == "fp32" else seqx.FP64
+    prec = PRECISIONS[args.precision]
     guess, pspace = (seqx.GUESS_LEARNED, 2 * NROOTS) if args.guess == "learned" else (seqx.GUESS_GAP, 0)
     if guess == seqx.GUESS_LEARNED:
         ctx.mlp_load(os.path.join(ROOT, "paper_2505_24807_amd", "guess_net.bin"))
     main_run = run_mode(ctx, mol, ref, prec, K, args.warmup, guess, pspace)
     n, o, v = main_run["dims"]
     s = summary(main_run, K)
-    mode = ("FP32 transforms (FP64 contraction sums, FP64 subspace), finished with FP64 products"
-            if prec == seqx.FP32 else "FP64 transforms")
+    mode = {seqx.FP32: "FP32 transforms (FP64 contraction sums, FP64 subspace), finished with FP64 products",
+            seqx.BF16X3: "split-bfloat16 transforms (three bfloat16 products, FP32 accumulation; FP64 contraction "
+                         "sums, FP64 subspace), finished with FP64 products",
+            seqx.FP64: "FP64 transforms"}[prec]
     mode += (", learned starting space (the 20 best-scored pairs)" if guess == seqx.GUESS_LEARNED
              else ", gap guess")
     out = {
@@ -422,6 +426,9 @@ def main():
                                                  if k in ("value", "ms_per_step", "time_to_10_roots_at_1e-4_eV_s",
                                                           "davidson_iterations", "n_sigma_per_step",
                                                           "parity_max_abs_eV_vs_oracle")}
+    # the sigma build alone in each transform precision: 20 seeded vectors, 3 builds after a warm-up
+    out["sigma_build_by_precision"] = {
+        name: sigma_only(ctx, mol, 20, 3, PRECISIONS[name])["sigma_vectors_per_s"] for name in ("fp64", "fp32", "bf16x3")}
     if not args.no_batched:
         out["batched_c4"] = batched_c4(ctx, K, loop=not args.no_batched_loop)
     if not args.no_learned:

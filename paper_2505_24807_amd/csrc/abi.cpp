@@ -662,9 +662,8 @@ seqx_status seqx_integrals(const seqx_job* job, int32_t mol, double* out, size_t
 
 namespace {
 void check_precision(int32_t precision) {
-  if (precision == SEQX_FP64 || precision == SEQX_FP32) return;
-  if (precision == SEQX_BF16 || precision == SEQX_BF16X3)
-    throw Error(kEArg, "BF16 transforms are not available");
+  if (precision == SEQX_FP64 || precision == SEQX_FP32 || precision == SEQX_BF16X3) return;
+  if (precision == SEQX_BF16) throw Error(kEArg, "single-bfloat16 transforms are not available (use SEQX_BF16X3)");
   throw Error(kEArg, "unknown precision");
 }
 }  // namespace

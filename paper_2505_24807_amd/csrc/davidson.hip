@@ -528,14 +528,16 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   double floor_low = 0.0, rbest = 1e300;
   int stall = 0;
   if (prec != kPrecFP64) {
-    // rounding floor of the FP32 products: FP32 sums over n terms carry a
-    // relative error of about sqrt(n) u (u = 2^-24), on a scale set by the
-    // largest orbital-energy gap; four times that
+    // rounding floor of the low-precision products: sums over n terms carry a
+    // relative error of about sqrt(n) u (FP32: u = 2^-24; split bfloat16:
+    // u = 3 * 2^-16 per product), on a scale set by the largest orbital-energy
+    // gap; four times that
     max_abs(st, nov, w.d.p, w.rn.p, w.ws.p);
     double dmax = 0.0;
     d2h(&dmax, w.rn.p, 1, st);
     SEQX_HIP(hipStreamSynchronize(st));
-    floor_low = 4.0 * std::sqrt(static_cast<double>(m.nao)) * std::ldexp(1.0, -24) * dmax;
+    const double u = prec == kPrecBF16x3 ? 3.0 * std::ldexp(1.0, -16) : std::ldexp(1.0, -24);
+    floor_low = 4.0 * std::sqrt(static_cast<double>(m.nao)) * u * dmax;
   }
   bool converged = false;
   int it = 0;

@@ -557,6 +557,274 @@ void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   SEQX_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------- split-bfloat16 tiles
+// FP32 operands multiplied as x = hi + lo, hi = bf16(x), lo = bf16(x - hi)
+// (round to nearest even both times): a b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b
+// on the bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16, 32 k per
+// instruction), FP32 accumulation.  Dropped: lo_a lo_b and the rounding of the
+// lo parts, so each product carries a relative error of at most 3 * 2^-16.
+// Same 128 x 128 tile, prefetch and XCD order as the FP32 kernel; the panels
+// are split once, when stored to LDS, as hi and lo planes with k contiguous per
+// row (one 16-byte LDS read per operand of an MFMA).
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+
+// hi and lo parts of two values, packed two per word (element 0 in the low
+// half): one hardware conversion (round to nearest even) per pair for each part
+__device__ __forceinline__ void split_pair(float x, float y, unsigned& hi, unsigned& lo) {
+  const bf2 h = {static_cast<__bf16>(x), static_cast<__bf16>(y)};
+  const unsigned hb = __builtin_bit_cast(unsigned, h);
+  const float hx = __uint_as_float(hb << 16), hy = __uint_as_float(hb & 0xffff0000u);
+  const bf2 l = {static_cast<__bf16>(x - hx), static_cast<__bf16>(y - hy)};
+  hi = hb;
+  lo = __builtin_bit_cast(unsigned, l);
+}
+
+constexpr int kBK3 = 32;           // k per panel
+constexpr int kLd3 = kBK3 + 8;     // bf16 per LDS row (k contiguous), padded; rows stay 16-byte aligned
+
+struct Lds3 {
+  unsigned short ahi[2][kBM][kLd3], alo[2][kBM][kLd3], bhi[2][kBN][kLd3], blo[2][kBN][kLd3];
+};
+
+// Which elements a thread loads.  An operand whose rows in memory run along k
+// (A not transposed, B transposed) is loaded as pairs of consecutive k of one
+// row / column; one whose rows run along the tile index (A transposed, B not)
+// as 2 x 2 blocks: pairs 2q and 2q + 1 hold index i, i + 1 at k and k + 1.
+// Either way each LDS word written holds two consecutive k of one row.
+// Element pair j of thread tid: tile index i, panel column k (first element).
+template <bool KM>
+__device__ __forceinline__ void pair_pos3(int tid, int j, int& i, int& k) {
+  constexpr int HK = kBK3 / 2, HM = kBM / 2;
+  if (!KM) {
+    const int c = tid + 256 * j;
+    i = c / HK;
+    k = (c % HK) * 2;
+  } else {
+    const int c = tid + 256 * (j >> 1);
+    k = 2 * (c / HM) + (j & 1);
+    i = (c % HM) * 2;
+  }
+}
+
+// Panel loads, clamped at the edges like panel_load_edge: element (i, k) of
+// A (rows i, KA: A[k lda + i] when transposed) and of B (columns i).
+template <bool TA, bool TB>
+__device__ __forceinline__ void panel_load_edge3(const float* __restrict__ A, long lda, const float* __restrict__ B,
+                                                 long ldb, int M, int N, int K, int m0, int n0, int k0, int tid,
+                                                 f2* ra, f2* rb) {
+  auto ld_a = [&](int gi, int gk) {
+    const float v = TA ? A[static_cast<long>(min(gk, K - 1)) * lda + min(gi, M - 1)]
+                       : A[static_cast<long>(min(gi, M - 1)) * lda + min(gk, K - 1)];
+    return gk < K ? v : 0.0f;
+  };
+  auto ld_b = [&](int gj, int gk) {
+    const float v = TB ? B[static_cast<long>(min(gj, N - 1)) * ldb + min(gk, K - 1)]
+                       : B[static_cast<long>(min(gk, K - 1)) * ldb + min(gj, N - 1)];
+    return gk < K ? v : 0.0f;
+  };
+#pragma unroll
+  for (int j = 0; j < Panel<float>::NP; ++j) {
+    int i, k;
+    pair_pos3<TA>(tid, j, i, k);
+    ra[j].x = ld_a(m0 + i, k0 + k);
+    ra[j].y = TA ? ld_a(m0 + i + 1, k0 + k) : ld_a(m0 + i, k0 + k + 1);
+    pair_pos3<!TB>(tid, j, i, k);
+    rb[j].x = ld_b(n0 + i, k0 + k);
+    rb[j].y = TB ? ld_b(n0 + i, k0 + k + 1) : ld_b(n0 + i + 1, k0 + k);
+  }
+}
+
+template <bool KM>
+__device__ __forceinline__ void store_plane3(unsigned short (*hi)[kLd3], unsigned short (*lo)[kLd3], int tid,
+                                             const f2* r) {
+  if (!KM) {
+#pragma unroll
+    for (int j = 0; j < Panel<float>::NP; ++j) {
+      int i, k;
+      pair_pos3<false>(tid, j, i, k);
+      unsigned h, l;
+      split_pair(r[j].x, r[j].y, h, l);
+      *reinterpret_cast<unsigned*>(&hi[i][k]) = h;
+      *reinterpret_cast<unsigned*>(&lo[i][k]) = l;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Panel<float>::NP / 2; ++q) {
+      int i, k;
+      pair_pos3<true>(tid, 2 * q, i, k);
+      unsigned h, l;
+      split_pair(r[2 * q].x, r[2 * q + 1].x, h, l);  // index i at k, k + 1
+      *reinterpret_cast<unsigned*>(&hi[i][k]) = h;
+      *reinterpret_cast<unsigned*>(&lo[i][k]) = l;
+      split_pair(r[2 * q].y, r[2 * q + 1].y, h, l);  // index i + 1
+      *reinterpret_cast<unsigned*>(&hi[i + 1][k]) = h;
+      *reinterpret_cast<unsigned*>(&lo[i + 1][k]) = l;
+    }
+  }
+}
+
+template <bool TA, bool TB>
+__device__ __forceinline__ void panel_store3(Lds3& L, int buf, int tid, const f2* ra, const f2* rb) {
+  store_plane3<TA>(L.ahi[buf], L.alo[buf], tid, ra);
+  store_plane3<!TB>(L.bhi[buf], L.blo[buf], tid, rb);
+}
+
+// one panel of 32 k: lane l reads k 8 (l / 16) .. + 7 of row l % 16 of each tile
+__device__ __forceinline__ void panel_mfma3(const Lds3& L, int buf, int lane, int wm, int wn, f4 (*acc)[4]) {
+  const int r = lane & 15, k8 = 8 * (lane >> 4);
+  bf8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ah[i] = *reinterpret_cast<const bf8*>(&L.ahi[buf][wm + i * 16 + r][k8]);
+    al[i] = *reinterpret_cast<const bf8*>(&L.alo[buf][wm + i * 16 + r][k8]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    bh[j] = *reinterpret_cast<const bf8*>(&L.bhi[buf][wn + j * 16 + r][k8]);
+    bl[j] = *reinterpret_cast<const bf8*>(&L.blo[buf][wn + j * 16 + r][k8]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+template <class To, bool TA, bool TB, bool EPI, int EM>
+__device__ __forceinline__ void tile128x3(int M, int N, int K, double alpha, const float* __restrict__ A, long lda,
+                                          const float* __restrict__ B, long ldb, double beta, To* __restrict__ C,
+                                          long ldc, long b, const SigmaEpilogue& ep, int m0, int n0, Lds3& L) {
+  typedef f2 P2;
+  constexpr int BK = kBK3;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+  // K as a head panel of K % BK columns (zero filled), then full panels; two
+  // register sets prefetch two panels ahead (as in the FP32 kernel)
+  P2 ra0[Panel<float>::NP], rb0[Panel<float>::NP], ra1[Panel<float>::NP], rb1[Panel<float>::NP];
+  const int kr = K % BK;
+  const int npan = K / BK + (kr ? 1 : 0);
+  const int kshift = kr ? kr - BK : 0;
+  const int im = M - 1 - m0, in = N - 1 - n0;
+  unsigned oa[Panel<float>::NP], ob[Panel<float>::NP];
+#pragma unroll
+  for (int j = 0; j < Panel<float>::NP; ++j) {
+    int i, kk;
+    pair_pos3<TA>(tid, j, i, kk);
+    if (EM == 1) i = TA ? min(i, im - 1) : min(i, im);
+    oa[j] = static_cast<unsigned>(TA ? kk * lda + i : i * lda + kk) * sizeof(float);
+    int jj, kb;
+    pair_pos3<!TB>(tid, j, jj, kb);
+    if (EM == 1) jj = TB ? min(jj, in) : min(jj, in - 1);
+    ob[j] = static_cast<unsigned>(TB ? jj * ldb + kb : kb * ldb + jj) * sizeof(float);
+  }
+  const __amdgpu_buffer_rsrc_t ar = buffer_rsrc(TA ? A + m0 : A + static_cast<long>(m0) * lda);
+  const __amdgpu_buffer_rsrc_t br = buffer_rsrc(TB ? B + static_cast<long>(n0) * ldb : B + n0);
+  auto load_full = [&](int p, P2* ra, P2* rb) {
+    const int k0 = p * BK + kshift;
+    if (EM < 2)
+      panel_load_fast<float>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(float), br,
+                             static_cast<unsigned>(TB ? k0 : k0 * ldb) * sizeof(float), oa, ob, ra, rb);
+    else
+      panel_load_edge3<TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, tid, ra, rb);
+  };
+  if (kr) panel_load_edge3<TA, TB>(A, lda, B, ldb, M, N, kr, m0, n0, 0, tid, ra0, rb0);
+  else load_full(0, ra0, rb0);
+  load_full(min(1, npan - 1), ra1, rb1);
+  panel_store3<TA, TB>(L, 0, tid, ra0, rb0);
+  __syncthreads();
+  int kt = 0;
+  for (; kt + 1 < npan; kt += 2) {
+    load_full(min(kt + 2, npan - 1), ra0, rb0);
+    __builtin_amdgcn_sched_barrier(0);
+    panel_mfma3(L, 0, lane, wm, wn, acc);
+    panel_store3<TA, TB>(L, 1, tid, ra1, rb1);
+    __syncthreads();
+    load_full(min(kt + 3, npan - 1), ra1, rb1);
+    __builtin_amdgcn_sched_barrier(0);
+    panel_mfma3(L, 1, lane, wm, wn, acc);
+    if (kt + 2 < npan) panel_store3<TA, TB>(L, 0, tid, ra0, rb0);
+    __syncthreads();
+  }
+  if (kt < npan) panel_mfma3(L, 0, lane, wm, wn, acc);
+  constexpr bool EDGE = EM != 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (!EDGE || (row < M && col < N)) store_elem<To, EPI>(C, ldc, b, row, col, alpha, acc[i][j][r], beta, ep);
+      }
+}
+
+template <class To, bool TA, bool TB, bool EPI>
+__global__ void __launch_bounds__(256) gemm128x3_kernel(int M, int N, int K, double alpha,
+                                                        const float* __restrict__ A, long lda, long sA,
+                                                        const float* __restrict__ B, long ldb, long sB, double beta,
+                                                        To* __restrict__ C, long ldc, long sC, SigmaEpilogue ep) {
+  __shared__ Lds3 L;
+  const long b = blockIdx.z;
+  const int nbx = gridDim.x, nb = gridDim.x * gridDim.y, nfull = nb - nb % 8;
+  int bid = blockIdx.y * nbx + blockIdx.x;
+  if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
+  const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * kBN;
+  const bool keven = (K & 1) == 0;
+  if (m0 + kBM <= M && n0 + kBN <= N && keven)
+    tile128x3<To, TA, TB, EPI, 0>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
+                                  n0, L);
+  else if (keven && (!TA || (M & 1) == 0) && (TB || (N & 1) == 0))
+    tile128x3<To, TA, TB, EPI, 1>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
+                                  n0, L);
+  else
+    tile128x3<To, TA, TB, EPI, 2>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
+                                  n0, L);
+}
+
+template <class To>
+void gemm_x3(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda, long sA,
+             const float* B, long ldb, long sB, double beta, To* C, long ldc, long sC, int batch,
+             const SigmaEpilogue* epi) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  const bool even = ((lda | ldb | sA | sB) & 1) == 0 && aligned_to(A, 8) && aligned_to(B, 8);
+  const long ldmax = lda > ldb ? lda : ldb;
+  const bool small_offsets = (ldmax * (static_cast<long>(K > kBM ? K : kBM) + kBM) + K) * 4L < (1L << 31);
+  if (!(even && small_offsets && M >= 96 && N >= 96 && K >= 32)) {
+    // shapes outside the tile path stay on the FP32 matrix cores
+    gemm_any<float, To>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, epi);
+    return;
+  }
+  SigmaEpilogue ep;
+  if (epi) ep = *epi;
+  dim3 grid(ceil_div(N, kBN), ceil_div(M, kBM), batch);
+#define SEQX_X3(TA_, TB_)                                                                                        \
+  do {                                                                                                          \
+    if (epi)                                                                                                    \
+      hipLaunchKernelGGL((gemm128x3_kernel<To, TA_, TB_, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, \
+                         sA, B, ldb, sB, beta, C, ldc, sC, ep);                                                 \
+    else                                                                                                        \
+      hipLaunchKernelGGL((gemm128x3_kernel<To, TA_, TB_, false>), grid, dim3(256), 0, st, M, N, K, alpha, A,    \
+                         lda, sA, B, ldb, sB, beta, C, ldc, sC, ep);                                            \
+  } while (0)
+  if (!ta && !tb) SEQX_X3(false, false);
+  else if (!ta && tb) SEQX_X3(false, true);
+  else if (ta && !tb) SEQX_X3(true, false);
+  else SEQX_X3(true, true);
+#undef SEQX_X3
+  SEQX_LAUNCH_CHECK();
+}
+
 }  // namespace
 
 void dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda, long sA,
@@ -574,6 +842,17 @@ void sgemm_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double a
                  long sA, const float* B, long ldb, long sB, double beta, double* C, long ldc, long sC, int batch,
                  const SigmaEpilogue* epi) {
   gemm_any<float, double>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, epi);
+}
+
+void sgemm3(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda, long sA,
+            const float* B, long ldb, long sB, double beta, float* C, long ldc, long sC, int batch) {
+  gemm_x3<float>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, nullptr);
+}
+
+void sgemm3_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda,
+                  long sA, const float* B, long ldb, long sB, double beta, double* C, long ldc, long sC, int batch,
+                  const SigmaEpilogue* epi) {
+  gemm_x3<double>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, epi);
 }
 
 void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,

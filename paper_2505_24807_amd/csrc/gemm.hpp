@@ -33,6 +33,16 @@ void sgemm_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double a
                  long sA, const float* B, long ldb, long sB, double beta, double* C, long ldc, long sC, int batch = 1,
                  const SigmaEpilogue* epi = nullptr);
 
+// FP32 inputs multiplied on the bfloat16 matrix cores as three products of
+// split operands (x = hi + lo, both bfloat16; hi hi + hi lo + lo hi), FP32
+// accumulation: at most 3 * 2^-16 relative error per product.  Shapes outside
+// the 128 x 128 tile path (M or N < 96, K < 32, odd strides) run as sgemm.
+void sgemm3(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda, long sA,
+            const float* B, long ldb, long sB, double beta, float* C, long ldc, long sC, int batch = 1);
+void sgemm3_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda,
+                  long sA, const float* B, long ldb, long sB, double beta, double* C, long ldc, long sC,
+                  int batch = 1, const SigmaEpilogue* epi = nullptr);
+
 // Column-major (BLAS) semantics for small subspace matrices:
 //   C = alpha * op(A) op(B) + beta * C, op(A) M x K, op(B) K x N, column-major.
 void dgemm_cm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, long lda,

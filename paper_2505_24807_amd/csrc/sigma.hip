@@ -116,33 +116,37 @@ void sigma_chunk(const DeviceMolecule& m, int theory, int kc, const double* Vc, 
       if (tdhf) dgemm(st, true, false, o, v, n, 1.0, m.C.p, n, 0, b.Z + kc * nv, v, nv, 0.0, out2c, v, os, kc, &ep);
     }
   } else {
+    // FP32 storage; products on the FP32 matrix cores or as split bfloat16 (BF16x3)
+    const bool x3 = precision == kPrecBF16x3;
+    auto mm = x3 ? sgemm3 : sgemm;
+    auto mm64 = x3 ? sgemm3_out64 : sgemm_out64;
     const float* C32 = m.C32.p;
     to_float(st, kc * ov, Vc, b.V32);
-    sgemm(st, false, false, n, v, o, 1.0, C32, n, 0, b.V32, v, ov, 0.0, b.T1s, v, nv, kc);
+    mm(st, false, false, n, v, o, 1.0, C32, n, 0, b.V32, v, ov, 0.0, b.T1s, v, nv, kc);
     mark(1);
-    sgemm(st, false, true, kc * n, n, v, 1.0, b.T1s, v, 0, C32 + o, n, 0, 0.0, b.Rs, n, 0, 1);
+    mm(st, false, true, kc * n, n, v, 1.0, b.T1s, v, 0, C32 + o, n, 0, 0.0, b.Rs, n, 0, 1);
     mark(2);
     if (tdhf)
       build_G(m, kc, b.Rs, nn, b.Fs, b.Fs + f2off, sF, kTwo, 4.0, -2.0, -2.0, b.gr, b.gJ, b.gws, st);
     else
       build_G(m, kc, b.Rs, nn, b.Fs, static_cast<float*>(nullptr), nn, kSum, 2.0, -1.0, -1.0, b.gr, b.gJ, b.gws, st);
     mark(3);
-    sgemm(st, false, false, nb * n, v, n, 1.0, b.Fs, n, 0, C32 + o, n, 0, 0.0, b.Zs, v, 0, 1);
+    mm(st, false, false, nb * n, v, n, 1.0, b.Fs, n, 0, C32 + o, n, 0, 0.0, b.Zs, v, 0, 1);
     mark(4);
     if (merged) {
-      sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs, v, nv, 0.0, out1c, v, os / 2, nb, &ep);
+      mm64(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs, v, nv, 0.0, out1c, v, os / 2, nb, &ep);
     } else {
-      sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs, v, nv, 0.0, out1c, v, os, kc, &ep);
-      if (tdhf)
-        sgemm_out64(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs + kc * nv, v, nv, 0.0, out2c, v, os, kc, &ep);
+      mm64(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs, v, nv, 0.0, out1c, v, os, kc, &ep);
+      if (tdhf) mm64(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs + kc * nv, v, nv, 0.0, out2c, v, os, kc, &ep);
     }
   }
   mark(5);
 }
 
 void check_sigma_args(const DeviceMolecule& m, int precision) {
-  if (precision != kPrecFP64 && precision != kPrecFP32) throw Error(kEArg, "unsupported transform precision");
-  if (precision == kPrecFP32 && m.C32.n < static_cast<size_t>(m.nao) * m.nao)
+  if (precision != kPrecFP64 && precision != kPrecFP32 && precision != kPrecBF16x3)
+    throw Error(kEArg, "unsupported transform precision");
+  if (precision != kPrecFP64 && m.C32.n < static_cast<size_t>(m.nao) * m.nao)
     throw Error(kEState, "FP32 MO coefficients missing");
 }
 
@@ -186,7 +190,7 @@ void chunk_work(const DeviceMolecule& m, int theory, int kc, int precision, bool
                 std::array<long, kNumPhases>& la) {
   const int n = m.nao, o = m.nocc, v = m.nvirt;
   const long nn = static_cast<long>(n) * n, nv = static_cast<long>(n) * v, ov = static_cast<long>(o) * v;
-  const bool tdhf = theory == 1, f32 = precision == kPrecFP32;
+  const bool tdhf = theory == 1, f32 = precision != kPrecFP64;
   const int nb = tdhf ? 2 * kc : kc;
   const double d = f32 ? 4.0 : 8.0;
   fl = {};
@@ -222,7 +226,7 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
     const int kc = std::min(chunk, k - c0);
     const int nb = tdhf ? 2 * kc : kc;
     ChunkBufs b;
-    if (precision == kPrecFP32) {
+    if (precision != kPrecFP64) {
       w.V32.ensure(static_cast<size_t>(kc) * ov);
       w.Rs.ensure(static_cast<size_t>(kc) * nn);
       w.Fs.ensure(static_cast<size_t>(nb) * nn);

@@ -43,6 +43,8 @@ struct SigmaWork {
 // C_occ^T G C_virt + (eps_a - eps_i) V_I.  Works in chunks of at most
 // `chunk` vectors (memory cap).  out_stride: distance (doubles) between the
 // outputs of consecutive vectors (0: nocc*nvirt, i.e. contiguous).
+// precision kPrecBF16x3: the same FP32 storage, with the four transforms as
+// split-bfloat16 products on the bfloat16 matrix cores (sgemm3).
 // precision kPrecFP32: V, C, R, F and the transform intermediates are stored in
 // FP32 and the four transforms run on the FP32 matrix cores; the NDDO
 // contraction still multiplies and adds in FP64 and the (eps_a - eps_i) V term

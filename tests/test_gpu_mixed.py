@@ -135,12 +135,14 @@ def test_sigma_fp32_products_large_tiles(ctx, name):
     job.free()
 
 
-def test_sigma_fp32_against_fp64_full_size(ctx):
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_sigma_low_precision_against_fp64_full_size(ctx, prec):
     """(H2O)330 at full size, 20 seeded vectors in the bench's launch shape:
-    every element of the FP32 products within 8 n u of the largest element of
-    the two-electron part, taken from the FP64 products of the same vectors
-    (the FP64 path itself matches the oracle's roots at this size and its
-    products element by element up to 600 AOs)."""
+    every element of the FP32 (BF16x3) products within 8 n u (8 n u3) of the
+    largest element of the two-electron part, taken from the FP64 products of
+    the same vectors (the FP64 path itself matches the oracle's roots at this
+    size and its products element by element up to 600 AOs)."""
+    low, u = (seqx.FP32, U32) if prec == "fp32" else (seqx.BF16X3, U3)
     import torch
 
     mol = molecules.workload_water330()
@@ -152,23 +154,23 @@ def test_sigma_fp32_against_fp64_full_size(ctx):
     g = torch.Generator(device="cuda").manual_seed(330)
     V = torch.randn((k, o, v), generator=g, device="cuda", dtype=torch.float64)
     outs = {}
-    for prec in (seqx.FP64, seqx.FP32):
+    for p in (seqx.FP64, low):
         o1, o2 = torch.empty_like(V), torch.empty_like(V)
-        job.sigma_device(V, o1, o2, theory=seqx.TDHF, precision=prec)
+        job.sigma_device(V, o1, o2, theory=seqx.TDHF, precision=p)
         torch.cuda.synchronize()
-        outs[prec] = (o1.cpu().numpy(), o2.cpu().numpy())
+        outs[p] = (o1.cpu().numpy(), o2.cpu().numpy())
     job.free()
     de = (eps[None, o:] - eps[:o, None]) / HA
     Vh = V.cpu().numpy()
     worst = 0.0
     for j in range(2):
-        ref, got = outs[seqx.FP64][j], outs[seqx.FP32][j]
+        ref, got = outs[seqx.FP64][j], outs[low][j]
         for i in range(k):
             scale = np.abs(ref[i] - de * Vh[i]).max()
             d = np.abs(got[i] - ref[i]).max()
-            worst = max(worst, d / (n * U32 * scale))
-            assert d <= 8 * n * U32 * scale, (j, i, d, scale)
-    print(f"[gpu] (H2O)330: worst FP32 error / (n u max|2e part|) = {worst:.3f}", flush=True)
+            worst = max(worst, d / (n * u * scale))
+            assert d <= 8 * n * u * scale, (j, i, d, scale)
+    print(f"[gpu] (H2O)330: worst {prec} error / (n u max|2e part|) = {worst:.4f}", flush=True)
 
 
 @pytest.mark.parametrize("name,theory,K", [("C2H4", seqx.TDHF, 3), ("C20H22n", seqx.TDHF, 5),
@@ -192,12 +194,66 @@ def test_fp32_solve_finishes_in_fp64(ctx, name, theory, K):
     job.free()
 
 
-def test_bf16_modes_are_rejected(ctx):
+def test_single_bf16_mode_is_rejected(ctx):
     mol = MOLS["C2H4"]
     job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
     _, o, v = job.dims()
-    for p in (seqx.BF16, seqx.BF16X3):
-        with pytest.raises(seqx.SeqxError) as e:
-            job.sigma(np.zeros((1, o, v)), theory=seqx.CIS, precision=p)
-        assert e.value.name == "E_ARG"
+    with pytest.raises(seqx.SeqxError) as e:
+        job.sigma(np.zeros((1, o, v)), theory=seqx.CIS, precision=seqx.BF16)
+    assert e.value.name == "E_ARG"
+    job.free()
+
+
+# Split-bfloat16 products (BF16x3): every transform product a b is formed as
+# hi_a hi_b + hi_a lo_b + lo_a hi_b with x = hi + lo both bfloat16, so it
+# carries at most 3 * 2^-16 relative error; with FP32 accumulation the Q16
+# analysis above holds with u = 3 * 2^-16.
+U3 = 3.0 * 2.0 ** -16
+
+
+@pytest.mark.parametrize("name", ["H2O48", "H2O100"])
+def test_sigma_bf16x3_products(ctx, name):
+    """BF16x3 products on the 128 x 128 tile path against the oracle, in the
+    AO basis, within 8 n u3 of the largest element of the two-electron part;
+    and visibly different from the FP32 products (the bfloat16 path ran)."""
+    mol = LARGE[name]
+    sy = model.make_system(mol.Z, mol.xyz, PR)
+    ints = integrals.build(sy)
+    res = scf.run(sy, ints)
+    print(f"[gpu] bf16x3 sigma {name}", flush=True)
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    _, Cl, _ = job.scf_results()
+    n, o, v = job.dims()
+    k = 4
+    Y = np.random.default_rng(13).normal(size=(k, n, n))
+    Vl = np.stack([Cl[:, :o].T @ y @ Cl[:, o:] for y in Y])
+    Vo = np.stack([res.C[:, :o].T @ y @ res.C[:, o:] for y in Y])
+    AV, BV = excited.sigma(ints, res.eps, res.C, o, Vo)
+    de = res.eps[None, o:] - res.eps[:o, None]
+    p3, m3 = job.sigma(Vl, theory=seqx.TDHF, precision=seqx.BF16X3)
+    p1, _ = job.sigma(Vl, theory=seqx.TDHF, precision=seqx.FP32)
+    worst = 0.0
+    for lib, ref in ((p3, AV + BV), (m3, AV - BV)):
+        for j in range(k):
+            d = np.abs(_ao(Cl, o, lib[j].reshape(o, v)) - _ao(res.C, o, ref[j])).max()
+            scale = np.abs(_ao(res.C, o, ref[j] - de * Vo[j])).max()
+            worst = max(worst, d / (n * U3 * scale))
+            assert d <= 8 * n * U3 * scale, (j, d, scale)
+    print(f"[gpu] {name}: worst BF16x3 error / (n u3 max|2e part|) = {worst:.4f}", flush=True)
+    # the split-bfloat16 rounding (about 2^-16) shows far above FP32 rounding (2^-24)
+    assert np.abs(p3 - p1).max() > 16 * U32 * np.abs(p1).max()
+    job.free()
+
+
+@pytest.mark.parametrize("name,theory,K", [("H2O12", seqx.TDHF, 4), ("C20H22n", seqx.CIS, 4)])
+def test_bf16x3_solve_finishes_in_fp64(ctx, name, theory, K):
+    sy, ints, res = _oracle(name)
+    o, v = res.nocc, sy.nao - res.nocc
+    A, B = excited.build_AB(ints, res.eps, res.C, o)
+    ref = excited.cis_dense(A, K, o, v) if theory == seqx.CIS else excited.tdhf_dense(A, B, K, o, v)
+    mol = MOLS[name]
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    job.solve(theory=theory, nroots=K, tol=1e-7, precision=seqx.BF16X3)
+    assert np.abs(job.results().omega_eV - ref.omega * HA).max() < 1e-6
+    assert job.stats().refine_iteration >= 1
     job.free()

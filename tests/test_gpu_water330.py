@@ -1,8 +1,8 @@
 """(H2O)330 TDHF, 10 roots, at full size through the C ABI, against the stored
 values of the CPU oracle Davidson (tol 1e-7 hartree).
 
-Excitation energies must agree to 1e-6 eV in FP64 and in the mixed FP32 mode
-(which finishes in FP64).  Oscillator strengths: several roots are only
+Excitation energies must agree to 1e-6 eV in FP64 and in the mixed FP32 and
+split-bfloat16 (BF16x3) modes (which finish in FP64).  Oscillator strengths: several roots are only
 about 1e-3 eV apart, so an eigenvector converged to a residual r is rotated
 by up to r / gap within such a pair; at r = 1e-7 hartree on both sides that
 moves f by a few 1e-5, and the check is 1e-4.
@@ -36,7 +36,7 @@ def job():
 REF = json.load(open(os.path.join(HERE, "golden", "c3_water330_tdhf.json")))
 
 
-@pytest.mark.parametrize("precision", [seqx.FP64, seqx.FP32])
+@pytest.mark.parametrize("precision", [seqx.FP64, seqx.FP32, seqx.BF16X3])
 def test_water330_tdhf_matches_oracle(job, precision):
     print(f"[gpu] (H2O)330 TDHF precision={precision}", flush=True)
     job.solve(theory=seqx.TDHF, nroots=10, tol=1e-7, max_iter=600, precision=precision)
