@@ -82,7 +82,7 @@ def cpu_baseline(mol, params_eV, k=2):
                       f"{dt:.1f} s; ERI build excluded"}
 
 
-def run_mode(ctx, mol, ref, precision, steps, warmup, guess=0, pspace=0):
+def run_mode(ctx, mol, ref, precision, steps, warmup, guess=0, pspace=0, nguard=0):
     """Warm up, then time `steps` whole steps (integrals + SCF + Davidson) in one
     transform precision and starting space."""
     import torch
@@ -91,7 +91,7 @@ def run_mode(ctx, mol, ref, precision, steps, warmup, guess=0, pspace=0):
     def step():
         job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
         job.solve(theory=seqx.TDHF, nroots=NROOTS, tol=TOL, max_iter=400, precision=precision, guess=guess,
-                  pspace=pspace)
+                  pspace=pspace, nguard=nguard)
         return job
 
     for _ in range(warmup):
@@ -327,6 +327,7 @@ def main():
                     help="transform precision of the timed run (fp32, bf16x3: mixed modes finishing in FP64)")
     ap.add_argument("--guess", choices=["learned", "gap"], default="learned",
                     help="starting space of the timed run (learned: the packaged network's 2K best pairs)")
+    ap.add_argument("--guard", type=int, default=0, help="extra roots iterated beside the 10 wanted ones")
     ap.add_argument("--no-fp64-comparison", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-molecule batched CIS section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess section")
@@ -390,7 +391,7 @@ def main():
     guess, pspace = (seqx.GUESS_LEARNED, 2 * NROOTS) if args.guess == "learned" else (seqx.GUESS_GAP, 0)
     if guess == seqx.GUESS_LEARNED:
         ctx.mlp_load(os.path.join(ROOT, "paper_2505_24807_amd", "guess_net.bin"))
-    main_run = run_mode(ctx, mol, ref, prec, K, args.warmup, guess, pspace)
+    main_run = run_mode(ctx, mol, ref, prec, K, args.warmup, guess, pspace, args.guard)
     n, o, v = main_run["dims"]
     s = summary(main_run, K)
     mode = {seqx.FP32: "FP32 transforms (FP64 contraction sums, FP64 subspace), finished with FP64 products",

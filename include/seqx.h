@@ -119,6 +119,11 @@ typedef struct {
                            so the subspace cap (20 * root_batch + 40, or the memory budget)
                            applies per batch and only the K converged roots are kept beyond
                            it.  Single-molecule solver, gap guess only.  0: all roots at once. */
+  int32_t nguard;       /* 0 .. 64 extra roots iterated above the nroots wanted ones (single-molecule
+                           solver): their Ritz vectors join the expansion and the restarts, which
+                           helps when the wanted roots sit in a dense cluster; only the wanted
+                           roots decide convergence and are returned; the default subspace cap
+                           counts them (20 * (nroots + nguard) + 40). */
 } seqx_solve_opts;
 
 typedef struct {

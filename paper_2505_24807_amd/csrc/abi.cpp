@@ -727,6 +727,8 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
     d.max_iter = opts->max_iter > 0 ? opts->max_iter : 100;
     d.max_sub = opts->max_subspace;
     d.precision = opts->precision;
+    if (opts->nguard < 0 || opts->nguard > 64) throw Error(kEArg, "nguard must be in [0, 64]");
+    d.nguard = opts->nguard;
     DBuf<double> guess;
     job->solved = false;
     job->stats.n_sigma = 0;
@@ -751,6 +753,7 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
     if (opts->batched) {
       if (opts->theory != SEQX_CIS) throw Error(kEArg, "batched solve supports CIS only");
       if (opts->guess != SEQX_GUESS_GAP) throw Error(kEArg, "batched solve uses the gap guess");
+      if (opts->nguard != 0) throw Error(kEArg, "guard roots need the single-molecule solver");
       std::vector<DeviceMolecule*> ms;
       for (size_t mi = 0; mi < job->mols.size(); ++mi) ms.push_back(&scf_mol_of(job, static_cast<int32_t>(mi)));
       BatchOptions bo;
@@ -814,7 +817,7 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
                                                  opts->nroots * nov * sizeof(double)
                                            : 0;
         const long cap_mem = static_cast<long>((budget > locked ? budget - locked : 0) / std::max<size_t>(per, 1));
-        const long kcap = root_batches ? opts->root_batch : opts->nroots;
+        const long kcap = (root_batches ? opts->root_batch : opts->nroots) + opts->nguard;
         dm.max_sub = static_cast<int>(std::max<long>(std::min<long>(cap_mem, 20L * kcap + 40), 1));
       }
       DavResult r = root_batches ? davidson_root_batches(m, dm, opts->root_batch, *job->ctx->ds, job->dw,

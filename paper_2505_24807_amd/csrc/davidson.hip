@@ -398,10 +398,12 @@ void finalize_roots(DeviceMolecule& m, int theory, int K, const double* om, cons
 }
 
 DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, DavWork& w, hipStream_t st) {
-  const int o = m.nocc, v = m.nvirt, K = opt.nroots;
+  const int o = m.nocc, v = m.nvirt, Kreq = opt.nroots;
   const long nov = static_cast<long>(o) * v;
   const bool tdhf = opt.theory == 1;
-  if (K < 1 || K > nov) throw Error(kEArg, "nroots must be in [1, nocc*nvirt]");
+  if (Kreq < 1 || Kreq > nov) throw Error(kEArg, "nroots must be in [1, nocc*nvirt]");
+  // K Ritz pairs are iterated: the Kreq wanted ones and the guard roots above them
+  const int K = static_cast<int>(std::min<long>(nov, Kreq + std::max(0, opt.nguard)));
   int Smax = opt.max_sub > 0 ? opt.max_sub : 20 * K + 40;
   Smax = static_cast<int>(std::min<long>(Smax, nov));
   const int ncand_max = tdhf ? 2 * K : K;
@@ -623,7 +625,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       if (tdhf && !(h_w2min > 0.0))
         throw Error(kEUnstable, "A+B projected matrix not positive definite (unstable reference)");
       res.t_iter.push_back(now_s() - t0);
-      res.omega_iter.push_back(h_om);
+      res.omega_iter.push_back(std::vector<double>(h_om.begin(), h_om.begin() + Kreq));
       if (log_enabled()) {
         double rmax = 0.0;
         for (double r : h_rn) rmax = std::max(rmax, r);
@@ -633,13 +635,17 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
                      it, S, knew, rmax, h_om[0] * kHartreeEV, h_om[K - 1] * kHartreeEV, res.t_iter.back());
       }
       sel.clear();
-      double rmax = 0.0;
+      double rmax = 0.0;  // over the wanted roots
+      bool wanted_done = true;
       for (int j = 0; j < K; ++j) {
         if (!std::isfinite(h_rn[j]) || !std::isfinite(h_om[j])) throw Error(kEDavNoConv, "Davidson produced NaN");
-        if (h_rn[j] > opt.tol) sel.push_back(j);
-        rmax = std::max(rmax, h_rn[j]);
+        if (h_rn[j] > opt.tol) {
+          sel.push_back(j);
+          if (j < Kreq) wanted_done = false;
+        }
+        if (j < Kreq) rmax = std::max(rmax, h_rn[j]);
       }
-      if (prec == kPrecFP64 && sel.empty()) {
+      if (prec == kPrecFP64 && wanted_done) {
         converged = true;
         break;
       }
@@ -698,9 +704,9 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   itimer.accumulate(res.phase_ms);
   if (!converged) throw Error(kEDavNoConv, "Davidson did not converge in " + std::to_string(opt.max_iter) + " iterations");
 
-  // 9. amplitudes, sign convention, properties
-  finalize_roots(m, opt.theory, K, om, w.Tv.p, Uv, w.sig, w.scratch, st);
-  m.nroots = K;
+  // 9. amplitudes, sign convention, properties of the wanted roots
+  finalize_roots(m, opt.theory, Kreq, om, w.Tv.p, Uv, w.sig, w.scratch, st);
+  m.nroots = Kreq;
   m.theory = opt.theory;
   m.dav_iterations = it;
   m.n_sigma = res.n_sigma;

@@ -19,6 +19,10 @@ struct DavOptions {
   int precision = 0;   // SigmaPrecision of the transforms; the run finishes with FP64 products
   const double* guess = nullptr;  // device [nguess][nov] (user / learned guess), or null for the gap guess
   int nguess = 0;
+  // Extra (guard) roots iterated beside the nroots wanted ones: their Ritz
+  // vectors take part in the expansion and the restarts, but only the wanted
+  // roots decide convergence and are returned.
+  int nguard = 0;
   // Roots already found (root batches): nlock locked pairs, lock_t = T rows
   // (X+Y; CIS: X) and lock_u = U rows (X-Y; CIS: X), device [nlock][nov].
   // Every product gets the deflation term shift * U (U^T V) (TDHF: on A+B;

@@ -45,7 +45,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("theory", C.c_int32), ("nroots", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("max_subspace", C.c_int32), ("mem_budget_bytes", C.c_size_t), ("precision", C.c_int32),
                 ("guess", C.c_int32), ("n_user_guess", C.c_int32), ("user_guess", C.POINTER(C.c_double)),
-                ("batched", C.c_int32), ("pspace", C.c_int32), ("root_batch", C.c_int32)]
+                ("batched", C.c_int32), ("pspace", C.c_int32), ("root_batch", C.c_int32), ("nguard", C.c_int32)]
 
 
 class TrainOpts(C.Structure):
@@ -386,14 +386,14 @@ class Job:
         return {"loss": list(log.loss[:min(log.n_epochs, 256)]), "seconds": log.seconds}
 
     def solve(self, theory=TDHF, nroots=3, tol=1e-6, max_iter=100, max_subspace=0, mem_budget_bytes=0,
-              precision=FP64, guess=GUESS_GAP, user_guess=None, batched=False, pspace=0, root_batch=0):
+              precision=FP64, guess=GUESS_GAP, user_guess=None, batched=False, pspace=0, root_batch=0, nguard=0):
         ug = None
         n_ug = 0
         if user_guess is not None:
             ug = np.ascontiguousarray(user_guess, dtype=np.float64)
             n_ug = ug.shape[0]
         o = SolveOpts(theory, nroots, tol, max_iter, max_subspace, mem_budget_bytes, precision, guess, n_ug,
-                      _dptr(ug) if ug is not None else None, 1 if batched else 0, pspace, root_batch)
+                      _dptr(ug) if ug is not None else None, 1 if batched else 0, pspace, root_batch, nguard)
         self.nroots = 0
         self._check(self.lib.seqx_solve(self.h, C.byref(o)))
         self.nroots = nroots

@@ -234,3 +234,24 @@ def test_root_batches_reject_other_guesses(ctx):
         job.solve(theory=seqx.CIS, nroots=6, root_batch=2, guess=seqx.GUESS_GAP_PSPACE)
     assert ei.value.status == 1
     job.free()
+
+
+@pytest.mark.parametrize("theory", [seqx.CIS, seqx.TDHF], ids=["cis", "tdhf"])
+def test_guard_roots_against_dense(ctx, theory):
+    """Four guard roots above the five wanted ones: the wanted roots match dense
+    and only they are returned."""
+    sy, res, A, B = dense_of("C20H22n")
+    o, v = res.nocc, sy.nao - res.nocc
+    K = 5
+    ref = excited.cis_dense(A, K, o, v) if theory == seqx.CIS else excited.tdhf_dense(A, B, K, o, v)
+    job = _prepare(ctx, ["C20H22n"])
+    job.solve(theory=theory, nroots=K, tol=1e-7, nguard=4)
+    got = job.results()
+    assert got.omega_eV.shape == (K,)
+    assert np.abs(got.omega_eV - ref.omega * HA).max() < 1e-6
+    t, om = job.history()
+    assert om.shape[1] == K
+    with pytest.raises(seqx.SeqxError) as ei:
+        job.solve(theory=theory, nroots=K, nguard=65)
+    assert ei.value.status == 1
+    job.free()
