@@ -173,6 +173,13 @@ __global__ void scale_rows_kernel(long nov, double* __restrict__ W, const double
   W[r * nov + x] *= (g > 0.0) ? 1.0 / sqrt(g) : 0.0;
 }
 
+// dst columns (ld) = src columns over rows [0, s0), zero over rows [s0, s1)
+__global__ void pad_cols_kernel(int s0, int s1, const double* __restrict__ src, double* __restrict__ dst, int ld) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const long c = static_cast<long>(blockIdx.y) * ld;
+  if (r < s1) dst[c + r] = r < s0 ? src[c + r] : 0.0;
+}
+
 __global__ void invsqrt_cols_kernel(double* Q, int ld, int nrows, int j0, const double* __restrict__ lam) {
   const int j = j0 + blockIdx.x;
   const double s = 1.0 / sqrt(lam[j]);
@@ -426,16 +433,25 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   w.Tmp.ensure(static_cast<size_t>(Smax) * Smax);
   w.Hs.ensure(static_cast<size_t>(Smax) * Smax);
   w.w2.ensure(Smax);
-  w.coef.ensure(static_cast<size_t>(Smax) * 2 * K);
+  // Restarts keep, beside the current Ritz coefficients, those of the
+  // previous iteration (padded with zeros for the rows added since): the
+  // basis after a collapse spans both, as in a locally optimal block
+  // iteration, which keeps most of the convergence rate of the unrestarted
+  // iteration.  Two coefficient buffers alternate between iterations.
+  const int q_ritz = 2 * K;                    // TDHF: t, u of K roots; CIS: 2K eigenvectors
+  const int q_prev = opt.keep_prev ? (tdhf ? 2 * K : K) : 0;
+  const bool use_prev = q_prev > 0 && q_ritz + q_prev + ncand_max <= Smax;
+  const int q_max = q_ritz + (use_prev ? q_prev : 0);
+  w.coef.ensure(static_cast<size_t>(Smax) * 4 * K);
   // Ritz rows: Tv holds [T; U] (U only for TDHF), PT holds [(A+B)T; (A-B)U] (CIS: A X)
   w.Tv.ensure(static_cast<size_t>(ps) * K * nov);
   w.PT.ensure(static_cast<size_t>(ps) * K * nov);
   double* Uv = w.Tv.p + static_cast<long>(K) * nov;
   double* MU = w.PT.p + static_cast<long>(K) * nov;
   w.W.ensure(static_cast<size_t>(std::max(ncand_max, opt.guess ? opt.nguess : 0)) * nov);
-  w.scratch.ensure(static_cast<size_t>(ps) * 2 * K * nov);
+  w.scratch.ensure(static_cast<size_t>(ps) * q_max * nov);
   w.G.ensure(static_cast<size_t>(ps) * Smax * Smax);
-  w.Q.ensure(static_cast<size_t>(std::max(ncand_max, 2 * K)) * Smax);
+  w.Q.ensure(static_cast<size_t>(std::max(ncand_max, q_max)) * Smax);
   w.ws.ensure(std::max<size_t>(dots_workspace(2 * Smax, std::max(Smax, opt.nlock), nov), 4096));
   w.d.ensure(nov);
   w.rn.ensure(2 * K);
@@ -486,28 +502,51 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   // (TDHF: the 2K vectors t, u; CIS: the 2K lowest eigenvectors); V stays
   // orthonormal.  products: carry the products and projected matrices along
   // (else the caller recomputes them).  Returns the new basis size.
-  auto collapse = [&](int S, bool products) -> int {
-    double* tco = w.coef.p;
-    const int q0 = tdhf ? 2 * K : std::min(2 * K, S);
-    // coefficient block Cc (S x q0) = [t u] (TDHF) or the q0 lowest eigenvectors (CIS)
+  // prev: the previous iteration's coefficients (rows [0, s_prev)) or null.
+  auto collapse = [&](int S, bool products, const double* tco, const double* prev, int s_prev) -> int {
+    const int qr = tdhf ? 2 * K : std::min(2 * K, S);
+    // coefficient block Cc (S x q0) = [t u] (TDHF) or the qr lowest eigenvectors
+    // (CIS), then the previous coefficients
     double* Cc = w.Q.p;
     if (tdhf) {
       copy(st, Cc, tco, static_cast<long>(2 * K) * Smax);  // t and u are adjacent columns
     } else {
-      copy(st, Cc, w.Hs.p, static_cast<long>(q0) * Smax);
+      copy(st, Cc, w.Hs.p, static_cast<long>(qr) * Smax);
     }
-    // orthonormal columns: Q = Cc Qg diag(lam^-1/2) over the kept eigenpairs of Cc^T Cc
-    dgemm_cm(st, true, false, q0, q0, S, 1.0, Cc, Smax, Cc, Smax, 0.0, w.G.p, q0);
-    ds.eigh(q0, w.G.p, q0, w.w2.p);
-    std::vector<double> lam(q0);
-    d2h(lam.data(), w.w2.p, q0, st);
-    SEQX_HIP(hipStreamSynchronize(st));
-    int j0 = 0;
-    while (j0 < q0 && !(lam[j0] > 1e-12 * lam[q0 - 1])) ++j0;
-    const int q = q0 - j0;
-    hipLaunchKernelGGL(invsqrt_cols_kernel, dim3(q), dim3(64), 0, st, w.G.p, q0, q0, j0, w.w2.p);
-    dgemm_cm(st, false, false, S, q, q0, 1.0, Cc, Smax, w.G.p + static_cast<long>(j0) * q0, q0, 0.0, w.Lm.p,
-             Smax);  // Qc (S x q) in Lm
+    // Orthonormal columns spanning C (S x nc, ld Smax), written to out (ld Smax):
+    // C Z diag(lam^-1/2) over the eigenpairs of C^T C with lam > lmin; returns
+    // their number.  lmin < 0: relative, -lmin times the largest eigenvalue.
+    auto orth_cols = [&](const double* C, int nc, double lmin, double* out) -> int {
+      dgemm_cm(st, true, false, nc, nc, S, 1.0, C, Smax, C, Smax, 0.0, w.G.p, nc);
+      ds.eigh(nc, w.G.p, nc, w.w2.p);
+      std::vector<double> lam(nc);
+      d2h(lam.data(), w.w2.p, nc, st);
+      SEQX_HIP(hipStreamSynchronize(st));
+      const double lo = lmin < 0.0 ? -lmin * lam[nc - 1] : lmin;
+      int j0 = 0;
+      while (j0 < nc && !(lam[j0] > lo)) ++j0;
+      const int kept = nc - j0;
+      if (kept <= 0) return 0;
+      hipLaunchKernelGGL(invsqrt_cols_kernel, dim3(kept), dim3(64), 0, st, w.G.p, nc, nc, j0, w.w2.p);
+      dgemm_cm(st, false, false, S, kept, nc, 1.0, C, Smax, w.G.p + static_cast<long>(j0) * nc, nc, 0.0, out, Smax);
+      return kept;
+    };
+    int q0 = qr;
+    if (prev) {
+      hipLaunchKernelGGL(pad_cols_kernel, dim3(ceil_div(S, 256), q_prev), dim3(256), 0, st, s_prev, S, prev,
+                         Cc + static_cast<long>(qr) * Smax, Smax);
+      SEQX_LAUNCH_CHECK();
+      q0 += q_prev;
+    }
+    int q = orth_cols(Cc, q0, -1e-12, w.Lm.p);
+    if (prev) {
+      // the previous coefficients of converging roots nearly repeat the
+      // current ones, so their directions come out of C^T C with a small lam
+      // and rounding errors scaled by lam^-1/2; a second pass over the (nearly
+      // orthonormal) result restores orthonormality to working precision
+      copy(st, w.Hs.p, w.Lm.p, static_cast<long>(q) * Smax);
+      q = orth_cols(w.Hs.p, q, -1e-12, w.Lm.p);
+    }
     double* Qc = w.Lm.p;
     dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.V.p, nov, 0, 0.0, w.scratch.p, nov, 0, 1,
           nullptr);
@@ -541,6 +580,13 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
     const double u = prec == kPrecBF16x3 ? 3.0 * std::ldexp(1.0, -16) : std::ldexp(1.0, -24);
     floor_low = 4.0 * std::sqrt(static_cast<double>(m.nao)) * u * dmax;
   }
+  // coefficients of iteration it - 1 in the basis of iteration it, unless a
+  // collapse in between rotated the basis
+  int s_at[2] = {0, 0}, last_collapse = 0;
+  auto prev_coef = [&](int it) -> const double* {
+    if (!use_prev || it < 2 || last_collapse == it - 1) return nullptr;
+    return w.coef.p + static_cast<long>((it - 1) & 1) * 2 * K * Smax;
+  };
   bool converged = false;
   int it = 0;
   try {
@@ -570,8 +616,10 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       res.max_subspace = std::max(res.max_subspace, S);
       // 3. subspace eigenproblem
       itimer.mark(kDavSmallEig);
-      double* tco = w.coef.p;                          // t (TDHF) or x (CIS): S x K, ld Smax
-      double* uco = w.coef.p + static_cast<long>(K) * Smax;  // u (TDHF)
+      // t (TDHF) or x (CIS): S x K, ld Smax; u (TDHF) next to it
+      double* tco = w.coef.p + static_cast<long>(it & 1) * 2 * K * Smax;
+      double* uco = tco + static_cast<long>(K) * Smax;
+      s_at[it & 1] = S;
       if (tdhf) {
         copy(st, w.Lm.p, w.Mm.p, static_cast<long>(S) * Smax);
         ds.potrf(S, w.Lm.p, Smax);
@@ -665,7 +713,8 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
             std::fprintf(stderr, "{\"refine_after_iter\": %d, \"max_residual\": %.3e, \"floor\": %.3e}\n", it, rmax,
                          floor_low);
           itimer.mark(kDavCollapse);
-          S = collapse(S, false);
+          S = collapse(S, false, w.coef.p + static_cast<long>(it & 1) * 2 * K * Smax, prev_coef(it), s_at[(it - 1) & 1]);
+          last_collapse = it;
           knew = S;
           S = 0;
           prec = kPrecFP64;
@@ -684,7 +733,8 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       // 7. collapse onto the best Ritz vectors when the basis would overflow
       itimer.mark(kDavCollapse);
       if (S + nc > Smax) {
-        S = collapse(S, true);
+        S = collapse(S, true, w.coef.p + static_cast<long>(it & 1) * 2 * K * Smax, prev_coef(it), s_at[(it - 1) & 1]);
+        last_collapse = it;
         ++res.n_collapses;
       }
       // 8. orthonormalise and append

@@ -23,6 +23,8 @@ struct DavOptions {
   // vectors take part in the expansion and the restarts, but only the wanted
   // roots decide convergence and are returned.
   int nguard = 0;
+  // Restarts keep the previous iteration's Ritz coefficients beside the current ones.
+  int keep_prev = 1;
   // Roots already found (root batches): nlock locked pairs, lock_t = T rows
   // (X+Y; CIS: X) and lock_u = U rows (X-Y; CIS: X), device [nlock][nov].
   // Every product gets the deflation term shift * U (U^T V) (TDHF: on A+B;

@@ -95,14 +95,38 @@ __global__ void __launch_bounds__(256) skinny_combine_kernel(int M, long N, int 
       }
 }
 
-__global__ void reduce_partials_kernel(int nchunks, int ns, int nt, const double* __restrict__ part, double* out,
-                                       long ldo) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ns * nt) return;
-  const int s = idx / nt, t = idx % nt;
-  double acc = 0.0;
-  for (int c = 0; c < nchunks; ++c) acc += part[static_cast<long>(c) * ns * nt + idx];
-  out[static_cast<long>(s) * ldo + t] = acc;
+// sum over the chunks of the partial sums: a workgroup takes 64 outputs (one
+// per lane, coalesced) and splits the chunks over its 16 wavefronts (wavefront
+// w: chunks w, w + 16, ..., four independent running sums), then adds the 16
+// wavefront sums in order, so the result does not depend on timing
+constexpr int kRedWaves = 16;
+__global__ void __launch_bounds__(64 * kRedWaves) reduce_partials_kernel(int nchunks, int ns, int nt,
+                                                                          const double* __restrict__ part, double* out,
+                                                                          long ldo) {
+  __shared__ double red[kRedWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + lane;
+  const long stride = static_cast<long>(ns) * nt;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (idx < ns * nt) {
+    const double* p = part + idx;
+    int c = wave;
+    for (; c + 3 * kRedWaves < nchunks; c += 4 * kRedWaves) {
+      a0 += p[c * stride];
+      a1 += p[(c + kRedWaves) * stride];
+      a2 += p[(c + 2 * kRedWaves) * stride];
+      a3 += p[(c + 3 * kRedWaves) * stride];
+    }
+    for (; c < nchunks; c += kRedWaves) a0 += p[c * stride];
+  }
+  red[wave][lane] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (wave == 0 && idx < ns * nt) {
+    double acc = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRedWaves; ++w) acc += red[w][lane];
+    out[static_cast<long>(idx / nt) * ldo + idx % nt] = acc;
+  }
 }
 
 // few outputs, many chunks: one workgroup per output, fixed-order tree
@@ -288,8 +312,8 @@ void dots_pass(hipStream_t st, int ns, const double* X, long ldx, int nt, const 
     if (ns * nt < 1024 && nchunks >= 64)
       hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
     else
-      hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 256)), dim3(256), 0, st, nchunks, ns, nt, ws,
-                         out, ldo);
+      hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 64)), dim3(64 * kRedWaves), 0, st, nchunks,
+                         ns, nt, ws, out, ldo);
     SEQX_LAUNCH_CHECK();
     return;
   }
@@ -308,8 +332,8 @@ void dots_pass(hipStream_t st, int ns, const double* X, long ldx, int nt, const 
   if (ns * nt < 1024 && nchunks >= 64)
     hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
   else
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 256)), dim3(256), 0, st, nchunks, ns, nt, ws,
-                       out, ldo);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 64)), dim3(64 * kRedWaves), 0, st, nchunks, ns,
+                       nt, ws, out, ldo);
   SEQX_LAUNCH_CHECK();
 }
 
