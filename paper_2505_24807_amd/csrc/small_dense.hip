@@ -6,10 +6,10 @@
 // later phases keep the tridiagonal matrix and the eigenvalues in LDS.
 //
 // Eigenpairs: Householder reduction to tridiagonal form T = Q^T A Q; the k
-// lowest eigenvalues of T by Sturm-count multisection (each wavefront narrows
-// one eigenvalue 65-fold per round); eigenvectors of T by inverse iteration
+// lowest eigenvalues of T by Sturm-count multisection (16 lanes narrow one
+// eigenvalue 17-fold per round); eigenvectors of T by inverse iteration
 // (LU with partial pivoting of T - lambda I), each vector by its own thread,
-// then modified Gram-Schmidt inside clusters of close eigenvalues; finally
+// then Gram-Schmidt inside clusters of close eigenvalues; finally
 // y = Q z by applying the reflectors in reverse order, one wavefront per vector.
 #include <cmath>
 
@@ -24,6 +24,13 @@ constexpr int kNT = 1024;
 constexpr int kNW = kNT / 64;
 constexpr int kIB = 4;   // rows per block of the triangular solves of inverse iteration
 constexpr int kBT = 16;  // reflectors per LDS chunk of the back-transformation
+// lanes per eigenvalue of the multisection: 16 (four eigenvalues per
+// wavefront, 17-fold rounds) measured faster than 64 (65-fold rounds) for the
+// 10-20 lowest of 140-240
+constexpr int kMsLanes = 16;
+constexpr int kIG = 8;   // eigenvectors per group of the inverse iteration (their factors fill 96 KB of LDS)
+// eigenvectors staged in LDS for the orthogonalisation, beside the reflector chunks
+constexpr int kZsMax = 6 * kIG * kSmallDense - kBT * kSmallDense;
 
 // workgroup barrier that orders LDS accesses only (global accesses that must
 // be seen by other threads need __syncthreads)
@@ -48,32 +55,51 @@ __device__ double block_sum_1024(double v, double* red) {
   return r;
 }
 
-// number of eigenvalues of T (d, e2 = e^2) below x
-// (the LDS operands of 8 steps are read ahead of their dependent chain)
+// 1 / x from the hardware reciprocal estimate and one Newton-Raphson step
+// (x finite and nonzero)
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// number of eigenvalues of T (d, e2 = e^2) below x.  The quotients q_i =
+// (d_i - x) - e2_{i-1} / q_{i-1} of the LDL^T factorisation of T - x I are
+// carried as ratios p_i / p_{i-1} of the leading principal minors, p_i =
+// (d_i - x) p_{i-1} - e2_{i-1} p_{i-2}, so a step costs one fused multiply-add
+// instead of a division; q_i <= pivmin counts as negative and is raised in
+// magnitude to -pivmin, as in the quotient form, and every 4 steps both minors
+// are scaled by the same power of two (exact), which keeps them in range.
 __device__ int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
   int c = 0;
-  double q = d[0] - x;
-  if (q < 0.0) ++c;
-  int i = 1;
-  for (; i + 8 <= n; i += 8) {
-    double dx[8], f[8];
+  double pp = 0.0, p = 1.0;  // p_{i-2}, p_{i-1} (p_{-1} = 1)
+  auto step = [&](double dx, double f) {  // selects, no branches
+    const double pn = fma(dx, p, -f * pp);
+    const double m = pivmin * fabs(p);
+    const double t = p >= 0.0 ? pn : -pn;  // q_i times |p_{i-1}|
+    const bool neg = t <= m, raise = neg & (t > -m);
+    c += neg ? 1 : 0;
+    pp = p;
+    p = raise ? -pivmin * pp : pn;
+  };
+  auto rescale = [&]() {
+    int ex;
+    (void)frexp(fmax(fabs(p), fabs(pp)), &ex);
+    p = ldexp(p, -ex);
+    pp = ldexp(pp, -ex);
+  };
+  int i = 0;
+  for (; i + 4 <= n; i += 4) {
+    double dx[4], f[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 4; ++u) {
       dx[u] = d[i + u] - x;
-      f[u] = e2[i + u - 1];
+      f[u] = i + u > 0 ? e2[i + u - 1] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (fabs(q) < pivmin) q = -pivmin;
-      q = dx[u] - f[u] / q;
-      if (q < 0.0) ++c;
-    }
+    for (int u = 0; u < 4; ++u) step(dx[u], f[u]);
+    rescale();
   }
-  for (; i < n; ++i) {
-    if (fabs(q) < pivmin) q = -pivmin;
-    q = d[i] - x - e2[i - 1] / q;
-    if (q < 0.0) ++c;
-  }
+  for (; i < n; ++i) step(d[i] - x, i > 0 ? e2[i - 1] : 0.0);
   return c;
 }
 
@@ -249,21 +275,24 @@ __global__ void __launch_bounds__(kTT) small_tridiag_kernel(int n, const double*
       if (wave + kTW * g == n - 1 && lane + 64 * c == n - 1) dd[n - 1] = a[g][c];
 }
 
-// scratch layout (doubles): W [n * n] reflectors, Z [n * k], d, e, tau [n each], then per vector t: u0, u1, u2, l,
-// piv, y [n each].  Runs after small_tridiag_kernel on the same scratch.
+// scratch layout (doubles): W [n * n] reflectors, Z [n * k], d, e, tau [n each].  Runs after
+// small_tridiag_kernel on the same scratch.
 __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restrict__ A, int lda, int k,
                                                           double* __restrict__ w, double* __restrict__ scratch,
                                                           int* __restrict__ info) {
   __shared__ double d[kSmallDense], e[kSmallDense], e2[kSmallDense], tau[kSmallDense];
   __shared__ double red[kNT];
   __shared__ double lam[kSmallDense];
-  __shared__ double Vs[kBT][kSmallDense];
+  // LDS shared by the inverse iteration (6 arrays of kIG x kSmallDense) and,
+  // afterwards, the back-transformation (kBT reflectors)
+  __shared__ double pool[6 * kIG * kSmallDense > kBT * kSmallDense ? 6 * kIG * kSmallDense : kBT * kSmallDense];
+  double* ivs = pool;
+  double (*Vs)[kSmallDense] = reinterpret_cast<double (*)[kSmallDense]>(pool);
   // the wavefront index, read from lane 0 so that the compiler knows it is uniform
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   double* W = scratch;
   double* Z = scratch + static_cast<long>(n) * n;
   const double* dte = Z + static_cast<long>(n) * k;
-  double* per = Z + static_cast<long>(n) * k + 3L * n;
   for (int i = tid; i < n; i += kNT) {
     d[i] = dte[i];
     e[i] = dte[n + i];
@@ -299,164 +328,225 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
   lo -= 2.2e-16 * tnorm * n + 1e-300;
   hi += 2.2e-16 * tnorm * n + 1e-300;
   const double pivmin = 1e-290 + 2.2e-16 * 2.2e-16 * tnorm * tnorm;
-  for (int tt = wave; tt < k; tt += kNW) {
-    double a = lo, b = hi;
-    for (int round = 0; round < 24; ++round) {
-      if (!(b - a > 4.4e-16 * fmax(fabs(a), fabs(b)) + 1e-300)) break;
-      const double x = a + (b - a) * (lane + 1) / 65.0;
-      const int c = sturm_count(n, d, e2, x, pivmin);
-      // first lane whose point has more than tt eigenvalues below it
-      const unsigned long long above = __ballot(c > tt);
-      const int f = above ? __ffsll(static_cast<long long>(above)) - 1 : 64;
-      const double na = f == 0 ? a : a + (b - a) * f / 65.0;
-      const double nb = f == 64 ? b : a + (b - a) * (f + 1) / 65.0;
-      a = na;
-      b = nb;
+  // Each group of kMsLanes lanes narrows one eigenvalue (kMsLanes + 1)-fold
+  // per round, 64 / kMsLanes eigenvalues per wavefront.
+  {
+    constexpr int GPW = 64 / kMsLanes;
+    constexpr double fold = kMsLanes + 1;
+    const int g = lane / kMsLanes, j = lane % kMsLanes;
+    for (int t0 = GPW * wave; t0 < k; t0 += GPW * kNW) {  // uniform within the wavefront
+      const int tt = t0 + g;
+      double a = lo, b = hi;
+      bool open = tt < k;
+      for (int round = 0; round < 48; ++round) {
+        open = open && b - a > 4.4e-16 * fmax(fabs(a), fabs(b)) + 1e-300;
+        if (!__ballot(open)) break;
+        const double x = a + (b - a) * (j + 1) / fold;
+        const int c = sturm_count(n, d, e2, x, pivmin);
+        // first lane of the group whose point has more than tt eigenvalues below it
+        const unsigned long long above = __ballot(c > tt);
+        const unsigned long long seg =
+            GPW == 1 ? above : (above >> (kMsLanes * g)) & ((1ull << (kMsLanes % 64)) - 1);
+        const int f = seg ? __ffsll(static_cast<long long>(seg)) - 1 : kMsLanes;
+        if (open) {
+          const double na = f == 0 ? a : a + (b - a) * f / fold;
+          const double nb = f == kMsLanes ? b : a + (b - a) * (f + 1) / fold;
+          a = na;
+          b = nb;
+        }
+      }
+      if (j == 0 && tt < k) lam[tt] = 0.5 * (a + b);
     }
-    if (lane == 0) lam[tt] = 0.5 * (a + b);
   }
   __syncthreads();
 
-  // ---- eigenvectors of T by inverse iteration, one thread per vector.  The
-  // per-vector arrays are interleaved by element ([i][t]), so the k threads,
-  // which step through i together, share cache lines.
-  if (tid < k) {
-    const int tt = tid;
-    const long kk = k;
-    double* u0 = per;  // reciprocal pivots after the factorisation
-    double* u1 = u0 + kk * n;
-    double* u2 = u1 + kk * n;
-    double* lm = u2 + kk * n;
-    double* pvt = lm + kk * n;
-    double* y = pvt + kk * n;
-    const double l_t = lam[tt];
-    const double pert = 2.2e-16 * tnorm + 1e-300;
-    // factor P (T - lam I) = L U, U with two superdiagonals; row i of U is (u0, u1, u2)
-    double c0 = d[0] - l_t, c1 = n > 1 ? e[0] : 0.0, c2 = 0.0;  // current pivot row
-    for (int i = 0; i + 1 < n; ++i) {
-      const double sub = e[i];
-      const double r1 = d[i + 1] - l_t, r2 = i + 2 < n ? e[i + 1] : 0.0;
-      double n0, n1;  // next row's entries in columns i+1, i+2
-      if (fabs(sub) > fabs(c0)) {  // swap rows i and i+1
-        const double mlt = c0 / sub;
-        u1[i * kk + tt] = r1;
-        u2[i * kk + tt] = r2;
-        n0 = c1 - mlt * r1;
-        n1 = c2 - mlt * r2;
-        lm[i * kk + tt] = mlt;
-        pvt[i * kk + tt] = 1.0;
-        c0 = sub;
-      } else {
-        const double mlt = c0 != 0.0 ? sub / c0 : 0.0;
-        u1[i * kk + tt] = c1;
-        u2[i * kk + tt] = c2;
-        n0 = r1 - mlt * c1;
-        n1 = r2 - mlt * c2;
-        lm[i * kk + tt] = mlt;
-        pvt[i * kk + tt] = 0.0;
+  // ---- eigenvectors of T by inverse iteration, one thread per vector, in
+  // groups of kIG vectors whose factors and iterates stay in LDS (interleaved
+  // by element, [i][t], so the threads of a group, which step through i
+  // together, read neighbouring words).
+  for (int g0 = 0; g0 < k; g0 += kIG) {
+    const int t = tid, tt = g0 + tid;
+    if (t < kIG && tt < k) {
+      double* u0 = ivs;  // reciprocal pivots after the factorisation
+      double* u1 = u0 + kIG * kSmallDense;
+      double* u2 = u1 + kIG * kSmallDense;
+      double* lm = u2 + kIG * kSmallDense;
+      double* pvt = lm + kIG * kSmallDense;
+      double* y = pvt + kIG * kSmallDense;
+      constexpr int G = kIG;
+      const double l_t = lam[tt];
+      const double pert = 2.2e-16 * tnorm + 1e-300;
+      // factor P (T - lam I) = L U, U with two superdiagonals; row i of U is (u0, u1, u2)
+      double c0 = d[0] - l_t, c1 = n > 1 ? e[0] : 0.0, c2 = 0.0;  // current pivot row
+      // multipliers from reciprocals (one Newton step on the hardware
+      // estimate), which keeps divisions off the dependent chain; the
+      // factorisation only needs to be that of a nearby matrix
+      for (int i = 0; i + 1 < n; ++i) {
+        const double sub = e[i];
+        const double r1 = d[i + 1] - l_t, r2 = i + 2 < n ? e[i + 1] : 0.0;
+        double n0, n1;  // next row's entries in columns i+1, i+2
+        if (fabs(sub) > fabs(c0)) {  // swap rows i and i+1
+          const double mlt = c0 * rcp_nr(sub);
+          u1[i * G + t] = r1;
+          u2[i * G + t] = r2;
+          n0 = c1 - mlt * r1;
+          n1 = c2 - mlt * r2;
+          lm[i * G + t] = mlt;
+          pvt[i * G + t] = 1.0;
+          c0 = sub;
+        } else {
+          const double mlt = (c0 != 0.0 && sub != 0.0) ? sub * rcp_nr(c0) : 0.0;
+          u1[i * G + t] = c1;
+          u2[i * G + t] = c2;
+          n0 = r1 - mlt * c1;
+          n1 = r2 - mlt * c2;
+          lm[i * G + t] = mlt;
+          pvt[i * G + t] = 0.0;
+        }
+        if (fabs(c0) < pert) c0 = c0 < 0.0 ? -pert : pert;
+        u0[i * G + t] = rcp_nr(c0);
+        c0 = n0;
+        c1 = n1;
+        c2 = 0.0;
       }
       if (fabs(c0) < pert) c0 = c0 < 0.0 ? -pert : pert;
-      u0[i * kk + tt] = 1.0 / c0;
-      c0 = n0;
-      c1 = n1;
-      c2 = 0.0;
-    }
-    if (fabs(c0) < pert) c0 = c0 < 0.0 ? -pert : pert;
-    u0[(n - 1) * kk + tt] = 1.0 / c0;
-    u1[(n - 1) * kk + tt] = 0.0;
-    u2[(n - 1) * kk + tt] = 0.0;
-    // deterministic start: a fixed pseudo-random vector per eigenvalue index
-    unsigned long long sd = 0x9E3779B97F4A7C15ULL * (tt + 1);
-    for (int i = 0; i < n; ++i) {
-      sd = sd * 6364136223846793005ULL + 1442695040888963407ULL;
-      y[i * kk + tt] = static_cast<double>(static_cast<long long>(sd >> 11)) / 9007199254740992.0 - 0.5;
-    }
-    // The two triangular solves run in blocks of kIB rows whose operands are
-    // all loaded before the dependent chain goes through them, so a block
-    // waits for memory once.
-    for (int it = 0; it < 2; ++it) {
-      double carry = y[0 * kk + tt];  // running element i of P L^-1 y
-      int i = 0;
-      for (; i + kIB < n; i += kIB) {
-        double yn[kIB], pv[kIB], lv[kIB];
+      u0[(n - 1) * G + t] = rcp_nr(c0);
+      u1[(n - 1) * G + t] = 0.0;
+      u2[(n - 1) * G + t] = 0.0;
+      // deterministic start: a fixed pseudo-random vector per eigenvalue index
+      unsigned long long sd = 0x9E3779B97F4A7C15ULL * (tt + 1);
+      for (int i = 0; i < n; ++i) {
+        sd = sd * 6364136223846793005ULL + 1442695040888963407ULL;
+        y[i * G + t] = static_cast<double>(static_cast<long long>(sd >> 11)) / 9007199254740992.0 - 0.5;
+      }
+      // The two triangular solves run in blocks of kIB rows whose operands are
+      // all read before the dependent chain goes through them.
+      for (int it = 0; it < 2; ++it) {
+        double carry = y[t];  // running element i of P L^-1 y
+        int i = 0;
+        for (; i + kIB < n; i += kIB) {
+          double yn[kIB], pv[kIB], lv[kIB];
 #pragma unroll
-        for (int u = 0; u < kIB; ++u) {
-          yn[u] = y[(i + 1 + u) * kk + tt];
-          pv[u] = pvt[(i + u) * kk + tt];
-          lv[u] = lm[(i + u) * kk + tt];
+          for (int u = 0; u < kIB; ++u) {
+            yn[u] = y[(i + 1 + u) * G + t];
+            pv[u] = pvt[(i + u) * G + t];
+            lv[u] = lm[(i + u) * G + t];
+          }
+#pragma unroll
+          for (int u = 0; u < kIB; ++u) {
+            double next = yn[u];
+            if (pv[u] != 0.0) {
+              const double tmp = carry;
+              carry = next;
+              next = tmp;
+            }
+            y[(i + u) * G + t] = carry;
+            carry = next - lv[u] * carry;
+          }
         }
-#pragma unroll
-        for (int u = 0; u < kIB; ++u) {
-          double next = yn[u];
-          if (pv[u] != 0.0) {
+        for (; i + 1 < n; ++i) {
+          double next = y[(i + 1) * G + t];
+          if (pvt[i * G + t] != 0.0) {
             const double tmp = carry;
             carry = next;
             next = tmp;
           }
-          y[(i + u) * kk + tt] = carry;
-          carry = next - lv[u] * carry;
+          y[i * G + t] = carry;
+          carry = next - lm[i * G + t] * carry;
         }
-      }
-      for (; i + 1 < n; ++i) {
-        double next = y[(i + 1) * kk + tt];
-        if (pvt[i * kk + tt] != 0.0) {
-          const double tmp = carry;
-          carry = next;
-          next = tmp;
-        }
-        y[i * kk + tt] = carry;
-        carry = next - lm[i * kk + tt] * carry;
-      }
-      y[(n - 1) * kk + tt] = carry;
-      double nrm = 0.0, x1 = 0.0, x2 = 0.0;  // x1, x2: solution at rows i+1, i+2
-      i = n - 1;
-      for (; i + 1 >= kIB; i -= kIB) {  // rows i, i - 1, ..., i - kIB + 1
-        double yv[kIB], a0[kIB], a1[kIB], a2[kIB];
+        y[(n - 1) * G + t] = carry;
+        double nrm = 0.0, x1 = 0.0, x2 = 0.0;  // x1, x2: solution at rows i+1, i+2
+        i = n - 1;
+        for (; i + 1 >= kIB; i -= kIB) {  // rows i, i - 1, ..., i - kIB + 1
+          double yv[kIB], a0[kIB], a1[kIB], a2[kIB];
 #pragma unroll
-        for (int u = 0; u < kIB; ++u) {
-          const long r = static_cast<long>(i - u) * kk + tt;
-          yv[u] = y[r];
-          a0[u] = u0[r];
-          a1[u] = u1[r];
-          a2[u] = u2[r];
-        }
+          for (int u = 0; u < kIB; ++u) {
+            const int r = (i - u) * G + t;
+            yv[u] = y[r];
+            a0[u] = u0[r];
+            a1[u] = u1[r];
+            a2[u] = u2[r];
+          }
 #pragma unroll
-        for (int u = 0; u < kIB; ++u) {
-          const double xi = (yv[u] - a1[u] * x1 - a2[u] * x2) * a0[u];
-          y[static_cast<long>(i - u) * kk + tt] = xi;
+          for (int u = 0; u < kIB; ++u) {
+            const double xi = (yv[u] - a1[u] * x1 - a2[u] * x2) * a0[u];
+            y[(i - u) * G + t] = xi;
+            nrm += xi * xi;
+            x2 = x1;
+            x1 = xi;
+          }
+        }
+        for (; i >= 0; --i) {
+          const double xi = (y[i * G + t] - u1[i * G + t] * x1 - u2[i * G + t] * x2) * u0[i * G + t];
+          y[i * G + t] = xi;
           nrm += xi * xi;
           x2 = x1;
           x1 = xi;
         }
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = 0; i < n; ++i) y[i * G + t] *= inv;
       }
-      for (; i >= 0; --i) {
-        const double xi = (y[i * kk + tt] - u1[i * kk + tt] * x1 - u2[i * kk + tt] * x2) * u0[i * kk + tt];
-        y[i * kk + tt] = xi;
-        nrm += xi * xi;
-        x2 = x1;
-        x1 = xi;
-      }
-      const double inv = 1.0 / sqrt(nrm);
-      for (int i = 0; i < n; ++i) y[i * kk + tt] *= inv;
+      for (int i = 0; i < n; ++i) Z[static_cast<long>(tt) * n + i] = y[i * G + t];
     }
-    for (int i = 0; i < n; ++i) Z[static_cast<long>(tt) * n + i] = y[i * kk + tt];
+    __syncthreads();  // the group's LDS is reused by the next group
   }
-  __syncthreads();
-  // modified Gram-Schmidt inside clusters (|lam_s - lam_t| < 1e-3 ||T||)
-  for (int tt = 1; tt < k; ++tt) {
-    for (int s = 0; s < tt; ++s) {
-      if (!(fabs(lam[s] - lam[tt]) < 1e-3 * tnorm)) continue;
-      double dot = 0.0;
-      for (int i = tid; i < n; i += kNT) dot += Z[static_cast<long>(s) * n + i] * Z[static_cast<long>(tt) * n + i];
-      dot = block_sum_1024(dot, red);
-      for (int i = tid; i < n; i += kNT) Z[static_cast<long>(tt) * n + i] -= dot * Z[static_cast<long>(s) * n + i];
-      __syncthreads();
-      double nr = 0.0;
-      for (int i = tid; i < n; i += kNT) nr += Z[static_cast<long>(tt) * n + i] * Z[static_cast<long>(tt) * n + i];
-      nr = block_sum_1024(nr, red);
-      const double inv = 1.0 / sqrt(nr);
-      for (int i = tid; i < n; i += kNT) Z[static_cast<long>(tt) * n + i] *= inv;
-      __syncthreads();
+  // Orthogonalisation inside clusters of close eigenvalues (|lam_s - lam_t| <
+  // 1e-3 ||T||): vector t against the cluster members s < t, in order of t.
+  // When the k vectors fit in LDS beside the reflector chunks they are staged
+  // there: each pass forms all the inner products of t at once (one wavefront
+  // per member), then subtracts them (classical Gram-Schmidt, two passes);
+  // otherwise modified Gram-Schmidt in global memory.
+  const bool staged = static_cast<long>(k) * n <= kZsMax;
+  double* Zs = pool + kBT * kSmallDense;
+  if (staged) {
+    for (int idx = tid; idx < k * n; idx += kNT) Zs[idx] = Z[idx];
+    __syncthreads();
+    for (int tt = 1; tt < k; ++tt) {
+      bool any = false;
+      for (int s = 0; s < tt; ++s) any = any || fabs(lam[s] - lam[tt]) < 1e-3 * tnorm;
+      if (!any) continue;  // uniform
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int s = wave; s < tt; s += kNW) {
+          double dot = 0.0;
+          if (fabs(lam[s] - lam[tt]) < 1e-3 * tnorm)
+            for (int i = lane; i < n; i += 64) dot += Zs[s * n + i] * Zs[tt * n + i];
+          dot = wave_sum64(dot);
+          if (lane == 0) red[s] = dot;
+        }
+        lds_barrier();
+        if (tid < n) {
+          double zi = Zs[tt * n + tid];
+          for (int s = 0; s < tt; ++s) zi -= red[s] * Zs[s * n + tid];
+          Zs[tt * n + tid] = zi;
+        }
+        lds_barrier();
+      }
+      if (wave == 0) {
+        double nr = 0.0;
+        for (int i = lane; i < n; i += 64) nr += Zs[tt * n + i] * Zs[tt * n + i];
+        nr = wave_sum64(nr);
+        if (lane == 0) red[kNT - 1] = 1.0 / sqrt(nr);
+      }
+      lds_barrier();
+      if (tid < n) Zs[tt * n + tid] *= red[kNT - 1];
+      lds_barrier();
+    }
+  } else {
+    for (int tt = 1; tt < k; ++tt) {
+      for (int s = 0; s < tt; ++s) {
+        if (!(fabs(lam[s] - lam[tt]) < 1e-3 * tnorm)) continue;
+        double dot = 0.0;
+        for (int i = tid; i < n; i += kNT) dot += Z[static_cast<long>(s) * n + i] * Z[static_cast<long>(tt) * n + i];
+        dot = block_sum_1024(dot, red);
+        for (int i = tid; i < n; i += kNT) Z[static_cast<long>(tt) * n + i] -= dot * Z[static_cast<long>(s) * n + i];
+        __syncthreads();
+        double nr = 0.0;
+        for (int i = tid; i < n; i += kNT) nr += Z[static_cast<long>(tt) * n + i] * Z[static_cast<long>(tt) * n + i];
+        nr = block_sum_1024(nr, red);
+        const double inv = 1.0 / sqrt(nr);
+        for (int i = tid; i < n; i += kNT) Z[static_cast<long>(tt) * n + i] *= inv;
+        __syncthreads();
+      }
     }
   }
 
@@ -471,7 +561,7 @@ __global__ void __launch_bounds__(kNT) small_syevx_kernel(int n, double* __restr
 #pragma unroll
     for (int q = 0; q < kSmallDense / 64; ++q) {
       const int i = lane + 64 * q;
-      zr[q] = (act && i < n) ? Z[static_cast<long>(tt) * n + i] : 0.0;
+      zr[q] = (act && i < n) ? (staged ? Zs[tt * n + i] : Z[static_cast<long>(tt) * n + i]) : 0.0;
     }
     for (int j1 = n - 3; j1 >= 0; j1 -= kBT) {
       __syncthreads();  // the previous chunk is no longer read
@@ -563,7 +653,7 @@ __global__ void __launch_bounds__(kNT) small_potrf_kernel(int n, double* __restr
 }  // namespace
 
 size_t small_syevx_scratch(int n, int k) {
-  return static_cast<size_t>(n) * n + 7 * static_cast<size_t>(n) * k + 3 * static_cast<size_t>(n);
+  return static_cast<size_t>(n) * n + static_cast<size_t>(n) * k + 3 * static_cast<size_t>(n);
 }
 
 void launch_small_syevx(hipStream_t st, int n, double* A, int lda, int k, double* w, double* scratch, int* info) {
