@@ -138,17 +138,20 @@ constexpr int kBM = 128, kBN = 128, kPad = 2;
 template <class T>
 struct Panel {
   static constexpr int BK = sizeof(T) == 8 ? 16 : 32;
-  static constexpr int NP = kBM * BK / 2 / 256;  // element pairs per thread per operand
+  static constexpr int NP = kBM * BK / 2 / 256;  // element pairs of A per thread
 };
+// element pairs of B per thread for a tile BN columns wide
+template <class T, int BN>
+constexpr int kNPB = BN * Panel<T>::BK / 2 / 256;
 
 // FP64 panels: global loads of element pairs; CHECKED tests every element
 // against M, N and K (edge tiles and the K tail).
-template <class T, bool TA, bool TB, bool CHECKED>
+template <class T, bool TA, bool TB, bool CHECKED, int BN>
 __device__ __forceinline__ void panel_load(const T* __restrict__ A, long lda, const T* __restrict__ B, long ldb, int M,
                                            int N, int K, int m0, int n0, int k0, int tid,
                                            typename Mfma<T>::pair_t* ra, typename Mfma<T>::pair_t* rb) {
   typedef typename Mfma<T>::pair_t P2;
-  constexpr int BK = Panel<T>::BK, HK = BK / 2, HM = kBM / 2, HN = kBN / 2;
+  constexpr int BK = Panel<T>::BK, HK = BK / 2, HM = kBM / 2, HN = BN / 2;
 #pragma unroll
   for (int j = 0; j < Panel<T>::NP; ++j) {
     const int c = tid + 256 * j;
@@ -162,7 +165,11 @@ __device__ __forceinline__ void panel_load(const T* __restrict__ A, long lda, co
       ra[j].x = (gi < M && gk < K) ? p[0] : T(0);
       ra[j].y = (gi1 < M && gk1 < K) ? p[1] : T(0);
     }
-    int gj;
+  }
+#pragma unroll
+  for (int j = 0; j < kNPB<T, BN>; ++j) {
+    const int c = tid + 256 * j;
+    int gj, gk;
     if (!TB) { gk = k0 + c / HN; gj = n0 + (c % HN) * 2; } else { gj = n0 + c / HK; gk = k0 + (c % HK) * 2; }
     const T* q = TB ? B + static_cast<long>(gj) * ldb + gk : B + static_cast<long>(gk) * ldb + gj;
     if (!CHECKED) {
@@ -179,11 +186,11 @@ __device__ __forceinline__ void panel_load(const T* __restrict__ A, long lda, co
 // load is issued unconditionally (which keeps the wait counters exact).  Rows
 // past M and columns past N only feed outputs that are never stored, so their
 // clamped values are harmless; columns k >= K are set to zero.
-template <class T, bool TA, bool TB>
+template <class T, bool TA, bool TB, int BN>
 __device__ __forceinline__ void panel_load_edge(const T* __restrict__ A, long lda, const T* __restrict__ B, long ldb,
                                                 int M, int N, int K, int m0, int n0, int k0, int tid,
                                                 typename Mfma<T>::pair_t* ra, typename Mfma<T>::pair_t* rb) {
-  constexpr int BK = Panel<T>::BK, HK = BK / 2, HM = kBM / 2, HN = kBN / 2;
+  constexpr int BK = Panel<T>::BK, HK = BK / 2, HM = kBM / 2, HN = BN / 2;
   auto ld_a = [&](int gi, int gk) {
     const T v = TA ? A[static_cast<long>(min(gk, K - 1)) * lda + min(gi, M - 1)]
                    : A[static_cast<long>(min(gi, M - 1)) * lda + min(gk, K - 1)];
@@ -206,6 +213,10 @@ __device__ __forceinline__ void panel_load_edge(const T* __restrict__ A, long ld
       ra[j].x = ld_a(gi, gk);
       ra[j].y = ld_a(gi + 1, gk);
     }
+  }
+#pragma unroll
+  for (int j = 0; j < kNPB<T, BN>; ++j) {
+    const int c = tid + 256 * j;
     if (!TB) {
       const int gk = k0 + c / HN, gj = n0 + (c % HN) * 2;
       rb[j].x = ld_b(gj, gk);
@@ -238,21 +249,20 @@ __device__ __forceinline__ d2 buffer_pair<double>(__amdgpu_buffer_rsrc_t r, unsi
   return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
-template <class T>
+template <class T, int BN>
 __device__ __forceinline__ void panel_load_fast(__amdgpu_buffer_rsrc_t ar, unsigned asoff, __amdgpu_buffer_rsrc_t br,
                                                 unsigned bsoff, const unsigned* oa, const unsigned* ob,
                                                 typename Mfma<T>::pair_t* ra, typename Mfma<T>::pair_t* rb) {
 #pragma unroll
-  for (int j = 0; j < Panel<T>::NP; ++j) {
-    ra[j] = buffer_pair<T>(ar, oa[j], asoff);
-    rb[j] = buffer_pair<T>(br, ob[j], bsoff);
-  }
+  for (int j = 0; j < Panel<T>::NP; ++j) ra[j] = buffer_pair<T>(ar, oa[j], asoff);
+#pragma unroll
+  for (int j = 0; j < kNPB<T, BN>; ++j) rb[j] = buffer_pair<T>(br, ob[j], bsoff);
 }
 
-template <class T, bool TA, bool TB>
-__device__ __forceinline__ void panel_store(T (*As)[kBM + kPad], T (*Bs)[kBN + kPad], int tid,
+template <class T, bool TA, bool TB, int BN>
+__device__ __forceinline__ void panel_store(T (*As)[kBM + kPad], T (*Bs)[BN + kPad], int tid,
                                             const typename Mfma<T>::pair_t* ra, const typename Mfma<T>::pair_t* rb) {
-  constexpr int BK = Panel<T>::BK, HK = BK / 2, HM = kBM / 2, HN = kBN / 2;
+  constexpr int BK = Panel<T>::BK, HK = BK / 2, HM = kBM / 2, HN = BN / 2;
 #pragma unroll
   for (int j = 0; j < Panel<T>::NP; ++j) {
     const int c = tid + 256 * j;
@@ -265,6 +275,10 @@ __device__ __forceinline__ void panel_store(T (*As)[kBM + kPad], T (*Bs)[kBN + k
       As[kk][i] = ra[j].x;
       As[kk][i + 1] = ra[j].y;
     }
+  }
+#pragma unroll
+  for (int j = 0; j < kNPB<T, BN>; ++j) {
+    const int c = tid + 256 * j;
     if (!TB) {
       const int kk = c / HN, jj = (c % HN) * 2;
       Bs[kk][jj] = rb[j].x;
@@ -281,31 +295,31 @@ __device__ __forceinline__ void panel_store(T (*As)[kBM + kPad], T (*Bs)[kBN + k
 // step s are issued, so the LDS latency overlaps the matrix-core work.  FP64
 // keeps one operand set: its accumulators take twice the registers, and a
 // second set would cost a wavefront per SIMD.
-template <class T>
-__device__ __forceinline__ void panel_mfma(const T (*As)[kBM + kPad], const T (*Bs)[kBN + kPad], int lane, int wm,
-                                           int wn, typename Mfma<T>::acc_t (*acc)[4]) {
+template <class T, int TN>
+__device__ __forceinline__ void panel_mfma(const T (*As)[kBM + kPad], const T (*Bs)[TN * 32 + kPad], int lane, int wm,
+                                           int wn, typename Mfma<T>::acc_t (*acc)[TN]) {
   constexpr int NS = Panel<T>::BK / 4;
   if constexpr (sizeof(T) == 8) {  // FP64: one operand set, order left to the compiler
 #pragma unroll
     for (int ks = 0; ks < Panel<T>::BK; ks += 4) {
-      T a[4], bb[4];
+      T a[4], bb[TN];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[ks + (lane >> 4)][wm + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
+      for (int j = 0; j < TN; ++j) bb[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::op(a[i], bb[j], acc[i][j]);
+        for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::op(a[i], bb[j], acc[i][j]);
     }
     return;
   }
-  T a[2][4], bb[2][4];
+  T a[2][4], bb[2][TN];
   auto read = [&](int ks, T* ar, T* br) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) ar[i] = As[ks + (lane >> 4)][wm + i * 16 + (lane & 15)];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) br[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
+    for (int j = 0; j < TN; ++j) br[j] = Bs[ks + (lane >> 4)][wn + j * 16 + (lane & 15)];
   };
   read(0, a[0], bb[0]);
 #pragma unroll
@@ -314,57 +328,60 @@ __device__ __forceinline__ void panel_mfma(const T (*As)[kBM + kPad], const T (*
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::op(a[s & 1][i], bb[s & 1][j], acc[i][j]);
+      for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::op(a[s & 1][i], bb[s & 1][j], acc[i][j]);
   }
   // schedule: the LDS reads of step 0, then per step the reads of step s + 1
-  // ahead of the 16 MFMAs of step s (masks: 0x100 LDS read, 0x008 MFMA)
-  __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+  // ahead of the 4 TN MFMAs of step s (masks: 0x100 LDS read, 0x008 MFMA)
+  __builtin_amdgcn_sched_group_barrier(0x100, 4 + TN, 0);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    if (s + 1 < NS) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+    if (s + 1 < NS) __builtin_amdgcn_sched_group_barrier(0x100, 4 + TN, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 4 * TN, 0);
   }
 }
 
 // EM: 0 interior tile; 1 edge tile whose pair dimensions (M when A is
 // transposed, N when B is not) are even, loaded like an interior tile at
 // clamped offsets; 2 other edge tiles, element loads.
-template <class T, class To, bool TA, bool TB, bool EPI, int EM>
+// BN: tile width, 128 or 96 (each wavefront then owns 64 x BN / 2, TN = BN / 32
+// MFMA tiles across).
+template <class T, class To, bool TA, bool TB, bool EPI, int EM, int BN>
 __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const T* __restrict__ A, long lda,
                                         const T* __restrict__ B, long ldb, double beta, To* __restrict__ C, long ldc,
                                         long b, const SigmaEpilogue& ep, int m0, int n0, T (*As)[kBM + kPad],
-                                        T (*Bs)[kBN + kPad]) {
+                                        T (*Bs)[BN + kPad]) {
   typedef Mfma<T> MF;
-  constexpr int BK = Panel<T>::BK;
+  constexpr int BK = Panel<T>::BK, TN = BN / 32, NPB = kNPB<T, BN>;
   constexpr bool EDGE = EM != 0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  typename MF::acc_t acc[4][4];
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * (BN / 2);
+  typename MF::acc_t acc[4][TN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
   typedef typename MF::pair_t P2;
   if constexpr (sizeof(T) == 8) {
     // FP64 (accumulators take 128 registers): one register set for the
     // prefetch of panel p + 1; the K tail is the last panel.
-    P2 ra[Panel<T>::NP], rb[Panel<T>::NP];
+    P2 ra[Panel<T>::NP], rb[NPB];
     const int nfull = K / BK;  // panels without a K tail
     const int npan = (K + BK - 1) / BK;
-    if (nfull > 0) panel_load<T, TA, TB, EDGE>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
-    else panel_load<T, TA, TB, true>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
-    panel_store<T, TA, TB>(As, Bs, tid, ra, rb);
+    if (nfull > 0) panel_load<T, TA, TB, EDGE, BN>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
+    else panel_load<T, TA, TB, true, BN>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
+    panel_store<T, TA, TB, BN>(As, Bs, tid, ra, rb);
     __syncthreads();
     for (int kt = 0; kt < npan; ++kt) {
       const int cur = (kt & 1) * BK, nxt = BK - cur;
       const bool more = kt + 1 < npan;
       if (more) {
-        if (kt + 1 < nfull) panel_load<T, TA, TB, EDGE>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
-        else panel_load<T, TA, TB, true>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
+        if (kt + 1 < nfull)
+          panel_load<T, TA, TB, EDGE, BN>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
+        else panel_load<T, TA, TB, true, BN>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
       }
       __builtin_amdgcn_sched_barrier(0);
-      panel_mfma<T>(As + cur, Bs + cur, lane, wm, wn, acc);
-      if (more) panel_store<T, TA, TB>(As + nxt, Bs + nxt, tid, ra, rb);
+      panel_mfma<T, TN>(As + cur, Bs + cur, lane, wm, wn, acc);
+      if (more) panel_store<T, TA, TB, BN>(As + nxt, Bs + nxt, tid, ra, rb);
       __syncthreads();
     }
   } else {
@@ -376,22 +393,26 @@ __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const
     // stored to LDS.  The loads are unconditional (past the last panel they
     // repeat it and are not stored): a conditional load would make the wait
     // before the LDS stores cover the newest loads as well.
-    P2 ra0[Panel<T>::NP], rb0[Panel<T>::NP], ra1[Panel<T>::NP], rb1[Panel<T>::NP];
+    P2 ra0[Panel<T>::NP], rb0[NPB], ra1[Panel<T>::NP], rb1[NPB];
     const int kr = K % BK;
     const int npan = K / BK + (kr ? 1 : 0);
     const int kshift = kr ? kr - BK : 0;  // panel p >= 1 starts at p * BK + kshift
-    constexpr int HK = BK / 2, HM = kBM / 2, HN = kBN / 2;
+    constexpr int HK = BK / 2, HM = kBM / 2, HN = BN / 2;
     // Byte offsets inside a panel.  On edge tiles (EM == 1) rows and columns
     // past M and N are clamped to the last ones (pair starts to the last
     // pair): they only feed outputs that are not stored.
     const int im = M - 1 - m0, in = N - 1 - n0;  // last valid row / column of the tile
-    unsigned oa[Panel<T>::NP], ob[Panel<T>::NP];
+    unsigned oa[Panel<T>::NP], ob[NPB];
 #pragma unroll
     for (int j = 0; j < Panel<T>::NP; ++j) {
       const int c = tid + 256 * j;
       int i = TA ? (c % HM) * 2 : c / HK, kk = TA ? c / HM : (c % HK) * 2;
       if (EM == 1) i = TA ? min(i, im - 1) : min(i, im);
       oa[j] = static_cast<unsigned>(TA ? kk * lda + i : i * lda + kk) * sizeof(T);
+    }
+#pragma unroll
+    for (int j = 0; j < NPB; ++j) {
+      const int c = tid + 256 * j;
       int jj = TB ? c / HK : (c % HN) * 2, kb = TB ? (c % HK) * 2 : c / HN;
       if (EM == 1) jj = TB ? min(jj, in) : min(jj, in - 1);
       ob[j] = static_cast<unsigned>(TB ? jj * ldb + kb : kb * ldb + jj) * sizeof(T);
@@ -401,36 +422,36 @@ __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const
     auto load_full = [&](int p, P2* ra, P2* rb) {
       const int k0 = p * BK + kshift;
       if (EM < 2)
-        panel_load_fast<T>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(T), br,
-                           static_cast<unsigned>(TB ? k0 : k0 * ldb) * sizeof(T), oa, ob, ra, rb);
+        panel_load_fast<T, BN>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(T), br,
+                               static_cast<unsigned>(TB ? k0 : k0 * ldb) * sizeof(T), oa, ob, ra, rb);
       else
-        panel_load_edge<T, TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, tid, ra, rb);
+        panel_load_edge<T, TA, TB, BN>(A, lda, B, ldb, M, N, K, m0, n0, k0, tid, ra, rb);
     };
     // LDS buffers 0 and 1: rows [0, BK) and [BK, 2 BK) of As / Bs
-    if (kr) panel_load_edge<T, TA, TB>(A, lda, B, ldb, M, N, kr, m0, n0, 0, tid, ra0, rb0);
+    if (kr) panel_load_edge<T, TA, TB, BN>(A, lda, B, ldb, M, N, kr, m0, n0, 0, tid, ra0, rb0);
     else load_full(0, ra0, rb0);
     load_full(min(1, npan - 1), ra1, rb1);
-    panel_store<T, TA, TB>(As, Bs, tid, ra0, rb0);
+    panel_store<T, TA, TB, BN>(As, Bs, tid, ra0, rb0);
     __syncthreads();
     int kt = 0;
     for (; kt + 1 < npan; kt += 2) {
       load_full(min(kt + 2, npan - 1), ra0, rb0);
       __builtin_amdgcn_sched_barrier(0);
-      panel_mfma<T>(As, Bs, lane, wm, wn, acc);
-      panel_store<T, TA, TB>(As + BK, Bs + BK, tid, ra1, rb1);
+      panel_mfma<T, TN>(As, Bs, lane, wm, wn, acc);
+      panel_store<T, TA, TB, BN>(As + BK, Bs + BK, tid, ra1, rb1);
       __syncthreads();
       load_full(min(kt + 3, npan - 1), ra1, rb1);
       __builtin_amdgcn_sched_barrier(0);
-      panel_mfma<T>(As + BK, Bs + BK, lane, wm, wn, acc);
-      if (kt + 2 < npan) panel_store<T, TA, TB>(As, Bs, tid, ra0, rb0);
+      panel_mfma<T, TN>(As + BK, Bs + BK, lane, wm, wn, acc);
+      if (kt + 2 < npan) panel_store<T, TA, TB, BN>(As, Bs, tid, ra0, rb0);
       __syncthreads();
     }
-    if (kt < npan) panel_mfma<T>(As, Bs, lane, wm, wn, acc);  // odd panel count: the last one is in buffer 0
+    if (kt < npan) panel_mfma<T, TN>(As, Bs, lane, wm, wn, acc);  // odd panel count: the last one is in buffer 0
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + i * 16 + MF::row(lane, r);
@@ -439,14 +460,14 @@ __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const
       }
 }
 
-template <class T, class To, bool TA, bool TB, bool EPI>
+template <class T, class To, bool TA, bool TB, bool EPI, int BN>
 __global__ void __launch_bounds__(256) gemm128_kernel(int M, int N, int K, double alpha, const T* __restrict__ A,
                                                       long lda, long sA, const T* __restrict__ B, long ldb, long sB,
                                                       double beta, To* __restrict__ C, long ldc, long sC,
                                                       SigmaEpilogue ep) {
   constexpr int BK = Panel<T>::BK;
   __shared__ T As[2 * BK][kBM + kPad];
-  __shared__ T Bs[2 * BK][kBN + kPad];
+  __shared__ T Bs[2 * BK][BN + kPad];
   const long b = blockIdx.z;
   // Workgroups go to the 8 XCDs round-robin by linear id, and each XCD has its
   // own L2.  Regroup the ids so that each XCD gets a contiguous run of tiles in
@@ -455,21 +476,21 @@ __global__ void __launch_bounds__(256) gemm128_kernel(int M, int N, int K, doubl
   const int nbx = gridDim.x, nb = gridDim.x * gridDim.y, nfull = nb - nb % 8;
   int bid = blockIdx.y * nbx + blockIdx.x;
   if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
-  const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * kBN;
+  const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * BN;
   const bool keven = sizeof(T) == 8 || (K & 1) == 0;  // FP32 panels start at even k
-  if (m0 + kBM <= M && n0 + kBN <= N && keven)
-    tile128<T, To, TA, TB, EPI, 0>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
-                                   n0, As, Bs);
+  if (m0 + kBM <= M && n0 + BN <= N && keven)
+    tile128<T, To, TA, TB, EPI, 0, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
+                                       m0, n0, As, Bs);
   else if constexpr (sizeof(T) == 4) {
     if (keven && (!TA || (M & 1) == 0) && (TB || (N & 1) == 0))
-      tile128<T, To, TA, TB, EPI, 1>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
-                                     m0, n0, As, Bs);
+      tile128<T, To, TA, TB, EPI, 1, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b,
+                                         ep, m0, n0, As, Bs);
     else
-      tile128<T, To, TA, TB, EPI, 2>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
-                                     m0, n0, As, Bs);
+      tile128<T, To, TA, TB, EPI, 2, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b,
+                                         ep, m0, n0, As, Bs);
   } else {
-    tile128<T, To, TA, TB, EPI, 2>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
-                                   n0, As, Bs);
+    tile128<T, To, TA, TB, EPI, 2, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
+                                       m0, n0, As, Bs);
   }
 }
 
@@ -487,12 +508,33 @@ __global__ void __launch_bounds__(256) gemm128_kernel(int M, int N, int K, doubl
                             alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, ep);                       \
   } while (0)
 
-template <class T, class To, bool EPI>
+template <class T, class To, bool EPI, int BN>
 void launch128(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const T* A, long lda, long sA,
                const T* B, long ldb, long sB, double beta, To* C, long ldc, long sC, int batch,
                const SigmaEpilogue& ep) {
-  dim3 grid(ceil_div(N, kBN), ceil_div(M, kBM), batch);
-  SEQX_DISPATCH_T(gemm128_kernel, T, To);
+  dim3 grid(ceil_div(N, BN), ceil_div(M, kBM), batch);
+  const dim3 blk(256);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm128_kernel<T, To, false, false, EPI, BN>), grid, blk, 0, st, M, N, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC, ep);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm128_kernel<T, To, false, true, EPI, BN>), grid, blk, 0, st, M, N, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC, ep);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm128_kernel<T, To, true, false, EPI, BN>), grid, blk, 0, st, M, N, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC, ep);
+  else
+    hipLaunchKernelGGL((gemm128_kernel<T, To, true, true, EPI, BN>), grid, blk, 0, st, M, N, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC, ep);
+}
+
+// Tile width of the 128-row tiles: 96 for FP32 inputs when it pads N by at
+// least 3 % less than 128 does (N = 660: 672 columns instead of 768).
+template <class T>
+int tile_width(int N) {
+  if (sizeof(T) != 4) return 128;
+  const long w128 = static_cast<long>(ceil_div(N, 128)) * 128, w96 = static_cast<long>(ceil_div(N, 96)) * 96;
+  return 100 * w96 < 97 * w128 ? 96 : 128;
 }
 
 template <class T, class To, int WM, int WN, int TM, int TN, bool EPI>
@@ -539,8 +581,15 @@ void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   const bool small_offsets = (ldmax * (static_cast<long>(K > kBM ? K : kBM) + kBM) + K) * static_cast<long>(sizeof(T)) <
                              (1L << 31);
   if (even && small_offsets && M >= 96 && N >= 96 && K >= 16) {
-    if (epi) launch128<T, To, true>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
-    else launch128<T, To, false>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
+    const bool w96 = tile_width<T>(N) == 96;
+    if (epi && w96)
+      launch128<T, To, true, 96>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
+    else if (epi)
+      launch128<T, To, true, 128>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
+    else if (w96)
+      launch128<T, To, false, 96>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
+    else
+      launch128<T, To, false, 128>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
   } else if (epi) {
     launch_cfg<T, To, 2, 2, 2, 2, true>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
                                         ep);
@@ -732,7 +781,7 @@ __device__ __forceinline__ void tile128x3(int M, int N, int K, double alpha, con
   auto load_full = [&](int p, P2* ra, P2* rb) {
     const int k0 = p * BK + kshift;
     if (EM < 2)
-      panel_load_fast<float>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(float), br,
+      panel_load_fast<float, kBN>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(float), br,
                              static_cast<unsigned>(TB ? k0 : k0 * ldb) * sizeof(float), oa, ob, ra, rb);
     else
       panel_load_edge3<TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, tid, ra, rb);
