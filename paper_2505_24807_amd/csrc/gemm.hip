@@ -528,11 +528,9 @@ void launch128(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alp
                        ldb, sB, beta, C, ldc, sC, ep);
 }
 
-// Tile width of the 128-row tiles: 96 for FP32 inputs when it pads N by at
-// least 3 % less than 128 does (N = 660: 672 columns instead of 768).
-template <class T>
+// Tile width of the 128-row tiles: 96 when it pads N by at least 3 % less
+// than 128 does (N = 660: 672 columns instead of 768).
 int tile_width(int N) {
-  if (sizeof(T) != 4) return 128;
   const long w128 = static_cast<long>(ceil_div(N, 128)) * 128, w96 = static_cast<long>(ceil_div(N, 96)) * 96;
   return 100 * w96 < 97 * w128 ? 96 : 128;
 }
@@ -581,7 +579,7 @@ void gemm_any(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alph
   const bool small_offsets = (ldmax * (static_cast<long>(K > kBM ? K : kBM) + kBM) + K) * static_cast<long>(sizeof(T)) <
                              (1L << 31);
   if (even && small_offsets && M >= 96 && N >= 96 && K >= 16) {
-    const bool w96 = tile_width<T>(N) == 96;
+    const bool w96 = tile_width(N) == 96;
     if (epi && w96)
       launch128<T, To, true, 96>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ep);
     else if (epi)
