@@ -811,7 +811,10 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
           SEQX_HIP(hipMemGetInfo(&fr, &tot));
           budget = fr * 2 / 5;
         }
-        const size_t per = static_cast<size_t>(opts->theory == SEQX_TDHF ? 3 : 2) * nov * sizeof(double);
+        // bytes per basis row: the row and its products in FP64, plus their FP32
+        // copies where the low-precision phase keeps an FP32 basis
+        const size_t per = static_cast<size_t>(opts->theory == SEQX_TDHF ? 3 : 2) * nov *
+                           (sizeof(double) + (davidson_f32_basis(nov, opts->precision) ? sizeof(float) : 0));
         // root batches keep K locked rows (T, and U for TDHF) beside the batch's subspace
         const size_t locked = root_batches ? static_cast<size_t>(opts->theory == SEQX_TDHF ? 2 : 1) *
                                                  opts->nroots * nov * sizeof(double)

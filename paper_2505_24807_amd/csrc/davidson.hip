@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "davidson.hpp"
 #include "gemm.hpp"
@@ -58,11 +59,12 @@ __global__ void gap_guess_kernel(int o, int v, int ng, const double* __restrict_
   }
 }
 
-__global__ void unit_vectors_kernel(int ng, long nov, const int* __restrict__ idx, double* __restrict__ V) {
+template <class TV>
+__global__ void unit_vectors_kernel(int ng, long nov, const int* __restrict__ idx, TV* __restrict__ V) {
   const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
   const int r = blockIdx.y;
   if (x >= nov) return;
-  V[r * nov + x] = (x == idx[r]) ? 1.0 : 0.0;
+  V[r * nov + x] = (x == idx[r]) ? TV(1) : TV(0);
 }
 
 // column-major M: new columns t in [S0, S1) are filled for rows [0, S1);
@@ -328,10 +330,32 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Basis operations for FP64 or FP32 basis rows (the FP32 basis of the
+// low-precision phase): FP64 rows go through the general FP64 paths, FP32
+// rows through the tall-skinny kernels that widen them on load.
+template <class TB, class TC>
+void comb(hipStream_t st, int M, long N, int K, double alpha, const double* A, long lda, const TB* B, long ldb,
+          double beta, TC* C, long ldc) {
+  if constexpr (std::is_same<TB, double>::value && std::is_same<TC, double>::value)
+    dgemm(st, false, false, M, static_cast<int>(N), K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, nullptr);
+  else
+    combine_rows<TB, TC>(st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+template <class TX, class TY>
+void dts(hipStream_t st, int ns, const TX* X, long ldx, int nt, const TY* Y, long ldy, long len, double* out, long ldo,
+         double* ws) {
+  if constexpr (std::is_same<TX, double>::value && std::is_same<TY, double>::value)
+    dots(st, ns, X, ldx, nt, Y, ldy, len, out, ldo, ws);
+  else
+    dots_mixed<TX, TY>(st, ns, X, ldx, nt, Y, ldy, len, out, ldo, ws);
+}
+
 // Orthonormalise the nc rows of Wc against V[0:S] and among themselves, append
 // the kept directions at V[S:]; returns how many were kept.
-int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov, int nc, double* Wc, int S,
-                          double* V, int max_keep) {
+template <class TV>
+int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov, int nc, double* Wc, int S, TV* V,
+                          int max_keep) {
   double* G = w.G.p;
   double* Cc = w.Q.p;  // nc x S coefficients, reused below for the Loewdin vectors
   dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
@@ -340,8 +364,8 @@ int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov,
   // classical Gram-Schmidt against V; a second pass only when a unit row lost
   // more than three quarters of its norm ("twice is enough")
   for (int pass = 0; pass < 2 && S > 0; ++pass) {
-    dots(st, nc, Wc, nov, S, V, nov, nov, Cc, S, w.ws.p);
-    dgemm(st, false, false, nc, static_cast<int>(nov), S, -1.0, Cc, S, 0, V, nov, 0, 1.0, Wc, nov, 0, 1, nullptr);
+    dts(st, nc, Wc, nov, S, V, nov, nov, Cc, S, w.ws.p);
+    comb(st, nc, nov, S, -1.0, Cc, S, V, nov, 1.0, Wc, nov);
     dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
     if (pass == 1) break;
     std::vector<double> g(static_cast<size_t>(nc) * nc);
@@ -367,8 +391,7 @@ int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov,
   hipLaunchKernelGGL(invsqrt_cols_kernel, dim3(kept), dim3(64), 0, st, G, nc, nc, j0, w.w2.p);
   SEQX_LAUNCH_CHECK();
   // V[S + r] = sum_c Q(c, j0 + r) W_c
-  dgemm(st, false, false, kept, static_cast<int>(nov), nc, 1.0, G + static_cast<long>(j0) * nc, nc, 0, Wc, nov, 0,
-        0.0, V + static_cast<long>(S) * nov, nov, 0, 1, nullptr);
+  comb(st, kept, nov, nc, 1.0, G + static_cast<long>(j0) * nc, nc, Wc, nov, 0.0, V + static_cast<long>(S) * nov, nov);
   return kept;
 }
 
@@ -402,6 +425,10 @@ void finalize_roots(DeviceMolecule& m, int theory, int K, const double* om, cons
   SEQX_HIP(hipStreamSynchronize(st));
   m.nroots = K;
   m.theory = theory;
+}
+
+bool davidson_f32_basis(long nov, int precision) {
+  return precision != kPrecFP64 && nov % 4 == 0 && nov >= 4096;
 }
 
 DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, DavWork& w, hipStream_t st) {
@@ -452,6 +479,14 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   w.scratch.ensure(static_cast<size_t>(ps) * q_max * nov);
   w.G.ensure(static_cast<size_t>(ps) * Smax * Smax);
   w.Q.ensure(static_cast<size_t>(std::max(ncand_max, q_max)) * Smax);
+  // FP32 basis rows and products while the products are formed in low
+  // precision (their own rounding is far coarser); FP64 after the switch
+  bool lb = davidson_f32_basis(nov, opt.precision);
+  if (lb) {
+    w.V32.ensure(static_cast<size_t>(Smax) * nov);
+    w.SP32.ensure(static_cast<size_t>(ps) * Smax * nov);
+    w.scr32.ensure(static_cast<size_t>(ps) * q_max * nov);
+  }
   w.ws.ensure(std::max<size_t>(dots_workspace(2 * Smax, std::max(Smax, opt.nlock), nov), 4096));
   w.d.ensure(nov);
   w.rn.ensure(2 * K);
@@ -470,26 +505,30 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   int S = 0, knew = 0;
   if (opt.guess) {
     copy(st, w.W.p, opt.guess, static_cast<long>(opt.nguess) * nov);
-    knew = orthonormalize_append(st, ds, w, nov, opt.nguess, w.W.p, 0, w.V.p, Smax);
+    knew = lb ? orthonormalize_append(st, ds, w, nov, opt.nguess, w.W.p, 0, w.V32.p, Smax)
+              : orthonormalize_append(st, ds, w, nov, opt.nguess, w.W.p, 0, w.V.p, Smax);
     if (knew == 0) throw Error(kEArg, "user guess vectors are linearly dependent or zero");
   } else {
     // with locked roots: unit vectors at the ng gaps that follow the nlock smallest
     const int skip = static_cast<int>(std::min<long>(opt.nlock, nov - ng));
     w.idx.ensure(skip + ng);
     hipLaunchKernelGGL(gap_guess_kernel, dim3(1), dim3(1024), 0, st, o, v, skip + ng, m.eps.p, w.idx.p);
-    hipLaunchKernelGGL(unit_vectors_kernel, dim3(ceil_div(nov, 256), ng), dim3(256), 0, st, ng, nov, w.idx.p + skip,
-                       w.V.p);
+    if (lb)
+      hipLaunchKernelGGL(unit_vectors_kernel<float>, dim3(ceil_div(nov, 256), ng), dim3(256), 0, st, ng, nov,
+                         w.idx.p + skip, w.V32.p);
+    else
+      hipLaunchKernelGGL(unit_vectors_kernel<double>, dim3(ceil_div(nov, 256), ng), dim3(256), 0, st, ng, nov,
+                         w.idx.p + skip, w.V.p);
     SEQX_LAUNCH_CHECK();
     knew = ng;
   }
   // deflation of the locked roots: out_s += shift * sum_m U_m (U_m . V_s) for
   // the nv new vectors (their products nv rows of stride ldp from sp)
-  auto deflate = [&](const double* Vn, int nv, double* sp) {
+  auto deflate = [&](const auto* Vn, int nv, auto* sp) {
     if (opt.nlock <= 0 || nv <= 0) return;
     w.lc.ensure(static_cast<size_t>(nv) * opt.nlock);
-    dots(st, nv, Vn, nov, opt.nlock, opt.lock_u, nov, nov, w.lc.p, opt.nlock, w.ws.p);
-    dgemm(st, false, false, nv, static_cast<int>(nov), opt.nlock, opt.shift, w.lc.p, opt.nlock, 0, opt.lock_u, nov,
-          0, 1.0, sp, ldp, 0, 1, nullptr);
+    dts(st, nv, Vn, nov, opt.nlock, opt.lock_u, nov, nov, w.lc.p, opt.nlock, w.ws.p);
+    comb(st, nv, nov, opt.nlock, opt.shift, w.lc.p, opt.nlock, opt.lock_u, nov, 1.0, sp, ldp);
   };
 
   std::vector<double> h_om(K), h_rn(K);
@@ -548,14 +587,30 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       q = orth_cols(w.Hs.p, q, -1e-12, w.Lm.p);
     }
     double* Qc = w.Lm.p;
-    dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.V.p, nov, 0, 0.0, w.scratch.p, nov, 0, 1,
-          nullptr);
-    copy(st, w.V.p, w.scratch.p, static_cast<long>(q) * nov);
-    if (!products) return q;
-    for (int p = 0; p < ps; ++p)  // keep the interleaved product rows interleaved
-      dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.SP.p + p * nov, ldp, 0, 0.0,
-            w.scratch.p + p * nov, ldp, 0, 1, nullptr);
-    copy(st, w.SP.p, w.scratch.p, static_cast<long>(q) * ldp);
+    if (lb && !products) {
+      // leaving the FP32 basis: the collapsed rows in FP64, in scratch (the
+      // caller orthonormalises them into the FP64 basis)
+      comb(st, q, nov, S, 1.0, Qc, Smax, w.V32.p, nov, 0.0, w.scratch.p, nov);
+      return q;
+    }
+    if (lb) {
+      comb(st, q, nov, S, 1.0, Qc, Smax, w.V32.p, nov, 0.0, w.scr32.p, nov);
+      SEQX_HIP(hipMemcpyAsync(w.V32.p, w.scr32.p, static_cast<size_t>(q) * nov * sizeof(float),
+                              hipMemcpyDeviceToDevice, st));
+      for (int p = 0; p < ps; ++p)
+        comb(st, q, nov, S, 1.0, Qc, Smax, w.SP32.p + p * nov, ldp, 0.0, w.scr32.p + p * nov, ldp);
+      SEQX_HIP(hipMemcpyAsync(w.SP32.p, w.scr32.p, static_cast<size_t>(q) * ldp * sizeof(float),
+                              hipMemcpyDeviceToDevice, st));
+    } else {
+      dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.V.p, nov, 0, 0.0, w.scratch.p, nov, 0,
+            1, nullptr);
+      copy(st, w.V.p, w.scratch.p, static_cast<long>(q) * nov);
+      if (!products) return q;
+      for (int p = 0; p < ps; ++p)  // keep the interleaved product rows interleaved
+        dgemm(st, false, false, q, static_cast<int>(nov), S, 1.0, Qc, Smax, 0, w.SP.p + p * nov, ldp, 0, 0.0,
+              w.scratch.p + p * nov, ldp, 0, 1, nullptr);
+      copy(st, w.SP.p, w.scratch.p, static_cast<long>(q) * ldp);
+    }
     for (double* Mx : {w.Mp.p, tdhf ? w.Mm.p : nullptr}) {
       if (!Mx) continue;
       dgemm_cm(st, false, false, S, q, S, 1.0, Mx, Smax, Qc, Smax, 0.0, w.Tmp.p, Smax);
@@ -595,9 +650,16 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       itimer.mark(kDavSigma);
       SEQX_HIP(hipEventRecord(e0, st));
       double* sp_new = w.SP.p + static_cast<long>(S) * ldp;
-      sigma_build(m, opt.theory, knew, w.V.p + S * nov, sp_new, tdhf ? sp_new + nov : nullptr, w.sig, st,
-                  opt.sigma_chunk, ldp, prec);
-      deflate(w.V.p + S * nov, knew, sp_new);
+      float* sp_new32 = lb ? w.SP32.p + static_cast<long>(S) * ldp : nullptr;
+      if (lb) {
+        sigma_build_f32(m, opt.theory, knew, w.V32.p + S * nov, sp_new32, tdhf ? sp_new32 + nov : nullptr, w.sig, st,
+                        opt.sigma_chunk, ldp, prec);
+        deflate(w.V32.p + S * nov, knew, sp_new32);
+      } else {
+        sigma_build(m, opt.theory, knew, w.V.p + S * nov, sp_new, tdhf ? sp_new + nov : nullptr, w.sig, st,
+                    opt.sigma_chunk, ldp, prec);
+        deflate(w.V.p + S * nov, knew, sp_new);
+      }
       SEQX_HIP(hipEventRecord(e1, st));
       itimer.mark(kDavProject);
       res.n_sigma += knew;
@@ -605,7 +667,10 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       const int S1 = S + knew;
       // 2. projected matrices, new columns (column-major, ld = Smax): one pass over
       // V for (A+B) and (A-B) together, since their rows are interleaved
-      dots(st, ps * knew, sp_new, nov, S1, w.V.p, nov, nov, w.G.p, S1, w.ws.p);
+      if (lb)
+        dts(st, ps * knew, sp_new32, nov, S1, w.V32.p, nov, nov, w.G.p, S1, w.ws.p);
+      else
+        dots(st, ps * knew, sp_new, nov, S1, w.V.p, nov, nov, w.G.p, S1, w.ws.p);
       hipLaunchKernelGGL(scatter_cols_kernel, dim3(ceil_div(S1, 256), ps * knew), dim3(256), 0, st, w.G.p, S1, ps, S,
                          w.Mp.p, w.Mm.p, Smax);
       hipLaunchKernelGGL(sym_fill_kernel, dim3(ceil_div(S1, 256), knew), dim3(256), 0, st, w.Mp.p, Smax, S, S1);
@@ -642,13 +707,19 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       // 4. Ritz vectors and products: rows j of Tv = sum_s t(s, j) V_s, etc.
       itimer.mark(kDavRitz);
       // [T; U] in one pass over V (t and u are adjacent coefficient columns)
-      dgemm(st, false, false, ps * K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.V.p, nov, 0, 0.0, w.Tv.p, nov, 0,
-            1, nullptr);
-      dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.SP.p, ldp, 0, 0.0, w.PT.p, nov, 0, 1,
-            nullptr);
-      if (tdhf)
-        dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, uco, Smax, 0, w.SP.p + nov, ldp, 0, 0.0, MU, nov, 0,
-              1, nullptr);
+      if (lb) {
+        comb(st, ps * K, nov, S, 1.0, tco, Smax, w.V32.p, nov, 0.0, w.Tv.p, nov);
+        comb(st, K, nov, S, 1.0, tco, Smax, w.SP32.p, ldp, 0.0, w.PT.p, nov);
+        if (tdhf) comb(st, K, nov, S, 1.0, uco, Smax, w.SP32.p + nov, ldp, 0.0, MU, nov);
+      } else {
+        dgemm(st, false, false, ps * K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.V.p, nov, 0, 0.0, w.Tv.p, nov,
+              0, 1, nullptr);
+        dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.SP.p, ldp, 0, 0.0, w.PT.p, nov, 0, 1,
+              nullptr);
+        if (tdhf)
+          dgemm(st, false, false, K, static_cast<int>(nov), S, 1.0, uco, Smax, 0, w.SP.p + nov, ldp, 0, 0.0, MU, nov,
+                0, 1, nullptr);
+      }
       // 5. residual norms
       hipLaunchKernelGGL(residual_norm_kernel, dim3(nbres, K), dim3(256), 0, st, nov, tdhf ? 1 : 0, om, w.Tv.p, Uv,
                          w.PT.p, MU, w.part.p);
@@ -715,7 +786,14 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
           itimer.mark(kDavCollapse);
           S = collapse(S, false, w.coef.p + static_cast<long>(it & 1) * 2 * K * Smax, prev_coef(it), s_at[(it - 1) & 1]);
           last_collapse = it;
-          knew = S;
+          if (lb) {
+            // FP32 rows are orthonormal to about 1e-7: orthonormalise them again in FP64
+            itimer.mark(kDavOrtho);
+            knew = orthonormalize_append(st, ds, w, nov, S, w.scratch.p, 0, w.V.p, Smax);
+            lb = false;
+          } else {
+            knew = S;
+          }
           S = 0;
           prec = kPrecFP64;
           res.refine_iter = it + 1;
@@ -739,7 +817,8 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       }
       // 8. orthonormalise and append
       itimer.mark(kDavOrtho);
-      knew = orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V.p, Smax - S);
+      knew = lb ? orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V32.p, Smax - S)
+                : orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V.p, Smax - S);
       if (knew == 0) break;
     }
     itimer.mark(kDavSigma);

@@ -39,9 +39,16 @@ struct DavOptions {
 
 struct DavWork {
   DBuf<double> V, SP, SM, Mp, Mm, Lm, Tmp, Hs, w2, coef, Tv, Uv, PT, MU, W, G, Q, scratch, ws, d, rn, part, lc;
+  DBuf<float> V32, SP32, scr32;  // FP32 basis and products of the low-precision phase
   DBuf<int> idx, sel;
   SigmaWork sig;
 };
+
+// The low-precision phase keeps its basis and products in FP32 (half the
+// bytes of every pass over them) when the rows are long and 16-byte aligned
+// (nov a multiple of 4, at least 4096); the rounding of FP32 storage, about
+// 6e-8 relative, is far below that of the products themselves.
+bool davidson_f32_basis(long nov, int precision);
 
 // Davidson iteration phases timed with HIP events on the solve's stream.
 enum DavPhase {

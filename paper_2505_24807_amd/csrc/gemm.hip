@@ -51,8 +51,9 @@ __device__ __forceinline__ void store_elem(To* __restrict__ C, long ldc, long b,
   To* cp = C + static_cast<long>(row) * ldc + col;
   if (beta != 0.0) v += beta * static_cast<double>(*cp);
   if (EPI) {
-    const double* Vb = ep.V + ((b / ep.vdiv) % ep.kv) * ep.strideV;
-    v += (ep.eps[ep.nocc + col] - ep.eps[row]) * Vb[static_cast<long>(row) * ldc + col];
+    const long vo = ((b / ep.vdiv) % ep.kv) * ep.strideV + static_cast<long>(row) * ldc + col;
+    const double vv = ep.Vf ? static_cast<double>(ep.Vf[vo]) : ep.V[vo];
+    v += (ep.eps[ep.nocc + col] - ep.eps[row]) * vv;
   }
   *cp = static_cast<To>(v);
 }
@@ -881,8 +882,9 @@ void dgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, 
 }
 
 void sgemm(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda, long sA,
-           const float* B, long ldb, long sB, double beta, float* C, long ldc, long sC, int batch) {
-  gemm_any<float, float>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, nullptr);
+           const float* B, long ldb, long sB, double beta, float* C, long ldc, long sC, int batch,
+           const SigmaEpilogue* epi) {
+  gemm_any<float, float>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, epi);
 }
 
 void sgemm_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda,
@@ -892,8 +894,9 @@ void sgemm_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double a
 }
 
 void sgemm3(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda, long sA,
-            const float* B, long ldb, long sB, double beta, float* C, long ldc, long sC, int batch) {
-  gemm_x3<float>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, nullptr);
+            const float* B, long ldb, long sB, double beta, float* C, long ldc, long sC, int batch,
+            const SigmaEpilogue* epi) {
+  gemm_x3<float>(st, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, epi);
 }
 
 void sgemm3_out64(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha, const float* A, long lda,

@@ -67,10 +67,19 @@ struct ChunkBufs {
   double *gr = nullptr, *gJ = nullptr, *gws = nullptr;
 };
 
+// FP32 trial vectors in and FP32 products out (low-precision modes only), in
+// place of the FP64 ones
+struct F32Io {
+  const float* V = nullptr;
+  float* out1 = nullptr;
+  float* out2 = nullptr;
+};
+
 // One chunk of the product: kc vectors Vc -> out1c (and out2c), outputs os
-// doubles apart.  ev (optional) receives the phase boundaries.
+// elements apart.  ev (optional) receives the phase boundaries.
 void sigma_chunk(const DeviceMolecule& m, int theory, int kc, const double* Vc, double* out1c, double* out2c, long os,
-                 int precision, const ChunkBufs& b, hipStream_t st, std::array<hipEvent_t, kNumPhases + 1>* ev) {
+                 int precision, const ChunkBufs& b, hipStream_t st, std::array<hipEvent_t, kNumPhases + 1>* ev,
+                 const F32Io* io = nullptr) {
   const int n = m.nao, o = m.nocc, v = m.nvirt;
   const long nn = static_cast<long>(n) * n, nv = static_cast<long>(n) * v, ov = static_cast<long>(o) * v;
   const bool tdhf = theory == 1;
@@ -89,7 +98,7 @@ void sigma_chunk(const DeviceMolecule& m, int theory, int kc, const double* Vc, 
   // apart, as the Davidson basis keeps them): F+ and F- are built
   // interleaved too, so the last product is one launch over all 2 kc
   // matrices (twice the workgroups of a launch per half).
-  const bool merged = tdhf && os % 2 == 0 && out2c == out1c + os / 2;
+  const bool merged = tdhf && os % 2 == 0 && (io ? io->out2 == io->out1 + os / 2 : out2c == out1c + os / 2);
   const long sF = merged ? 2 * nn : nn;
   const long f2off = merged ? nn : kc * nn;
   if (merged) ep.vdiv = 2;
@@ -121,19 +130,33 @@ void sigma_chunk(const DeviceMolecule& m, int theory, int kc, const double* Vc, 
     auto mm = x3 ? sgemm3 : sgemm;
     auto mm64 = x3 ? sgemm3_out64 : sgemm_out64;
     const float* C32 = m.C32.p;
-    to_float(st, kc * ov, Vc, b.V32);
-    mm(st, false, false, n, v, o, 1.0, C32, n, 0, b.V32, v, ov, 0.0, b.T1s, v, nv, kc);
+    const float* Vs = b.V32;
+    if (io) {
+      Vs = io->V;
+      ep.V = nullptr;
+      ep.Vf = io->V;
+    } else {
+      to_float(st, kc * ov, Vc, b.V32);
+    }
+    mm(st, false, false, n, v, o, 1.0, C32, n, 0, Vs, v, ov, 0.0, b.T1s, v, nv, kc, nullptr);
     mark(1);
-    mm(st, false, true, kc * n, n, v, 1.0, b.T1s, v, 0, C32 + o, n, 0, 0.0, b.Rs, n, 0, 1);
+    mm(st, false, true, kc * n, n, v, 1.0, b.T1s, v, 0, C32 + o, n, 0, 0.0, b.Rs, n, 0, 1, nullptr);
     mark(2);
     if (tdhf)
       build_G(m, kc, b.Rs, nn, b.Fs, b.Fs + f2off, sF, kTwo, 4.0, -2.0, -2.0, b.gr, b.gJ, b.gws, st);
     else
       build_G(m, kc, b.Rs, nn, b.Fs, static_cast<float*>(nullptr), nn, kSum, 2.0, -1.0, -1.0, b.gr, b.gJ, b.gws, st);
     mark(3);
-    mm(st, false, false, nb * n, v, n, 1.0, b.Fs, n, 0, C32 + o, n, 0, 0.0, b.Zs, v, 0, 1);
+    mm(st, false, false, nb * n, v, n, 1.0, b.Fs, n, 0, C32 + o, n, 0, 0.0, b.Zs, v, 0, 1, nullptr);
     mark(4);
-    if (merged) {
+    if (io) {
+      if (merged) {
+        mm(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs, v, nv, 0.0, io->out1, v, os / 2, nb, &ep);
+      } else {
+        mm(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs, v, nv, 0.0, io->out1, v, os, kc, &ep);
+        if (tdhf) mm(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs + kc * nv, v, nv, 0.0, io->out2, v, os, kc, &ep);
+      }
+    } else if (merged) {
       mm64(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs, v, nv, 0.0, out1c, v, os / 2, nb, &ep);
     } else {
       mm64(st, true, false, o, v, n, 1.0, C32, n, 0, b.Zs, v, nv, 0.0, out1c, v, os, kc, &ep);
@@ -215,13 +238,19 @@ void chunk_work(const DeviceMolecule& m, int theory, int kc, int precision, bool
 
 }  // namespace
 
-void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
-                 SigmaWork& w, hipStream_t st, int chunk, long out_stride, int precision) {
+namespace {
+
+// FP64 vectors and products (V, out1, out2), or FP32 ones (Vf, out1f, out2f)
+void sigma_build_any(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
+                     const float* Vf, float* out1f, float* out2f, SigmaWork& w, hipStream_t st, int chunk,
+                     long out_stride, int precision) {
   const int n = m.nao, o = m.nocc, v = m.nvirt;
   const long nn = static_cast<long>(n) * n, nv = static_cast<long>(n) * v, ov = static_cast<long>(o) * v;
   const long os = out_stride > 0 ? out_stride : ov;
   const bool tdhf = theory == 1;
+  const bool f32io = Vf != nullptr;
   check_sigma_args(m, precision);
+  if (f32io && precision == kPrecFP64) throw Error(kEArg, "FP32 vectors need a low-precision transform mode");
   for (int c0 = 0; c0 < k; c0 += chunk) {
     const int kc = std::min(chunk, k - c0);
     const int nb = tdhf ? 2 * kc : kc;
@@ -255,10 +284,20 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
     b.gws = w.g.ws.p;
     std::array<hipEvent_t, kNumPhases + 1> ev;
     for (auto& e : ev) SEQX_HIP(hipEventCreate(&e));
-    double* o1 = out1 + c0 * os;
-    double* o2 = out2 ? out2 + c0 * os : nullptr;
-    sigma_chunk(m, theory, kc, V + c0 * ov, o1, o2, os, precision, b, st, &ev);
-    const bool merged = tdhf && os % 2 == 0 && o2 == o1 + os / 2;
+    bool merged;
+    if (f32io) {
+      F32Io io;
+      io.V = Vf + c0 * ov;
+      io.out1 = out1f + c0 * os;
+      io.out2 = out2f ? out2f + c0 * os : nullptr;
+      sigma_chunk(m, theory, kc, nullptr, nullptr, nullptr, os, precision, b, st, &ev, &io);
+      merged = tdhf && os % 2 == 0 && io.out2 == io.out1 + os / 2;
+    } else {
+      double* o1 = out1 + c0 * os;
+      double* o2 = out2 ? out2 + c0 * os : nullptr;
+      sigma_chunk(m, theory, kc, V + c0 * ov, o1, o2, os, precision, b, st, &ev);
+      merged = tdhf && os % 2 == 0 && o2 == o1 + os / 2;
+    }
     std::array<double, kNumPhases> fl, by;
     std::array<long, kNumPhases> la;
     chunk_work(m, theory, kc, precision, merged, fl, by, la);
@@ -267,6 +306,18 @@ void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, do
     w.timer.pending_bytes.push_back(by);
     w.timer.pending_launches.push_back(la);
   }
+}
+
+}  // namespace
+
+void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
+                 SigmaWork& w, hipStream_t st, int chunk, long out_stride, int precision) {
+  sigma_build_any(m, theory, k, V, out1, out2, nullptr, nullptr, nullptr, w, st, chunk, out_stride, precision);
+}
+
+void sigma_build_f32(const DeviceMolecule& m, int theory, int k, const float* V, float* out1, float* out2,
+                     SigmaWork& w, hipStream_t st, int chunk, long out_stride, int precision) {
+  sigma_build_any(m, theory, k, nullptr, nullptr, nullptr, V, out1, out2, w, st, chunk, out_stride, precision);
 }
 
 // ---- no-allocation variant --------------------------------------------------

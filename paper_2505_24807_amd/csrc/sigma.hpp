@@ -52,6 +52,11 @@ struct SigmaWork {
 void sigma_build(const DeviceMolecule& m, int theory, int k, const double* V, double* out1, double* out2,
                  SigmaWork& w, hipStream_t st, int chunk = 32, long out_stride = 0, int precision = kPrecFP64);
 
+// The same with FP32 trial vectors and FP32 products (FP32 or split-bfloat16
+// transforms only; the Δε term is still added in FP64 arithmetic).
+void sigma_build_f32(const DeviceMolecule& m, int theory, int k, const float* V, float* out1, float* out2,
+                     SigmaWork& w, hipStream_t st, int chunk, long out_stride, int precision);
+
 // No-allocation variant: the same products with every intermediate taken
 // from one fixed device workspace per GPU (kSigmaScratchBytes), in chunks of
 // as many vectors as fit.  Calls no allocator.  Consecutive calls on one GPU

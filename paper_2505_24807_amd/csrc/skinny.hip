@@ -21,11 +21,11 @@ bool aligned_to(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p
 // and 64 columns (four 16-column tiles); B is read once, in 128-byte row
 // segments per tile; the operands of the next k-step are loaded before the
 // MFMAs of the current one.
-template <int NX>
+template <int NX, class TB, class TC>
 __global__ void __launch_bounds__(256) skinny_combine_kernel(int M, long N, int K, double alpha,
                                                              const double* __restrict__ A, long lda,
-                                                             const double* __restrict__ B, long ldb, double beta,
-                                                             double* __restrict__ C, long ldc) {
+                                                             const TB* __restrict__ B, long ldb, double beta,
+                                                             TC* __restrict__ C, long ldc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
   const long x0 = (static_cast<long>(blockIdx.x) * 4 + wave) * 64;
@@ -46,9 +46,9 @@ __global__ void __launch_bounds__(256) skinny_combine_kernel(int M, long N, int 
     const int sk = 4 * step + g;
 #pragma unroll
     for (int a = 0; a < NX; ++a) av[a] = ar[a][sk];
-    const double* brow = B + static_cast<long>(sk) * ldb;
+    const TB* brow = B + static_cast<long>(sk) * ldb;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = brow[xc[b]];
+    for (int b = 0; b < 4; ++b) bv[b] = static_cast<double>(brow[xc[b]]);
   };
   auto mma = [&](const double* av, const double* bv) {
 #pragma unroll
@@ -74,9 +74,9 @@ __global__ void __launch_bounds__(256) skinny_combine_kernel(int M, long N, int 
     double av[NX], bv[4];
 #pragma unroll
     for (int a = 0; a < NX; ++a) av[a] = in ? ar[a][sk] : 0.0;
-    const double* brow = B + static_cast<long>(in ? sk : 0) * ldb;
+    const TB* brow = B + static_cast<long>(in ? sk : 0) * ldb;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = in ? brow[xc[b]] : 0.0;
+    for (int b = 0; b < 4; ++b) bv[b] = in ? static_cast<double>(brow[xc[b]]) : 0.0;
     mma(av, bv);
   }
 #pragma unroll
@@ -88,9 +88,9 @@ __global__ void __launch_bounds__(256) skinny_combine_kernel(int M, long N, int 
         const int m = 16 * a + g + 4 * r;
         const long x = x0 + 16 * b + i;
         if (m < M && x < N) {
-          double* cp = C + static_cast<long>(m) * ldc + x;
+          TC* cp = C + static_cast<long>(m) * ldc + x;
           const double v = alpha * acc[a][b][r];
-          *cp = beta == 0.0 ? v : v + beta * *cp;
+          *cp = static_cast<TC>(beta == 0.0 ? v : v + beta * static_cast<double>(*cp));
         }
       }
 }
@@ -153,17 +153,43 @@ constexpr long kDotChunk = 1024;
 
 }  // namespace
 
-void skinny_combine(hipStream_t st, int M, long N, int K, double alpha, const double* A, long lda, const double* B,
-                    long ldb, double beta, double* C, long ldc) {
+template <class TB, class TC>
+void combine_pass(hipStream_t st, int M, long N, int K, double alpha, const double* A, long lda, const TB* B,
+                  long ldb, double beta, TC* C, long ldc) {
   const dim3 grid(static_cast<unsigned>((N + 255) / 256));
   if (M <= 16)
-    hipLaunchKernelGGL(skinny_combine_kernel<1>, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL((skinny_combine_kernel<1, TB, TC>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
   else if (M <= 32)
-    hipLaunchKernelGGL(skinny_combine_kernel<2>, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL((skinny_combine_kernel<2, TB, TC>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
   else
-    hipLaunchKernelGGL(skinny_combine_kernel<3>, grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL((skinny_combine_kernel<3, TB, TC>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
   SEQX_LAUNCH_CHECK();
 }
+
+void skinny_combine(hipStream_t st, int M, long N, int K, double alpha, const double* A, long lda, const double* B,
+                    long ldb, double beta, double* C, long ldc) {
+  combine_pass<double, double>(st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+template <class TB, class TC>
+void combine_rows(hipStream_t st, int M, long N, int K, double alpha, const double* A, long lda, const TB* B, long ldb,
+                  double beta, TC* C, long ldc) {
+  if (M <= 0 || N <= 0) return;
+  for (int r0 = 0; r0 < M; r0 += 48)
+    combine_pass<TB, TC>(st, std::min(48, M - r0), N, K, alpha, A + static_cast<long>(r0) * lda, lda, B, ldb, beta,
+                         C + static_cast<long>(r0) * ldc, ldc);
+}
+template void combine_rows<double, double>(hipStream_t, int, long, int, double, const double*, long, const double*,
+                                           long, double, double*, long);
+template void combine_rows<float, double>(hipStream_t, int, long, int, double, const double*, long, const float*, long,
+                                          double, double*, long);
+template void combine_rows<double, float>(hipStream_t, int, long, int, double, const double*, long, const double*, long,
+                                          double, float*, long);
+template void combine_rows<float, float>(hipStream_t, int, long, int, double, const double*, long, const float*, long,
+                                         double, float*, long);
 
 // Tall-skinny inner products on the FP64 matrix cores: partial[c][s][t] =
 // sum over k in chunk c of X[s][k] Y[t][k], for ns <= 48 rows of X and any
@@ -178,9 +204,27 @@ void skinny_combine(hipStream_t st, int M, long N, int K, double alpha, const do
 namespace {
 
 
-template <int NX>
-__global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const double* __restrict__ X, long ldx,
-                                                          const double* __restrict__ Y, long ldy, long len,
+// 4 contiguous values (16-byte aligned) as doubles
+__device__ __forceinline__ void load4(const double* p, double* o) {
+  const d2 a = *reinterpret_cast<const d2*>(p), b = *reinterpret_cast<const d2*>(p + 2);
+  o[0] = a[0];
+  o[1] = a[1];
+  o[2] = b[0];
+  o[3] = b[1];
+}
+__device__ __forceinline__ void load4(const float* p, double* o) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v a = *reinterpret_cast<const f4v*>(p);
+  o[0] = a[0];
+  o[1] = a[1];
+  o[2] = a[2];
+  o[3] = a[3];
+}
+
+// X and Y rows of FP64 or FP32 elements (FP32 ones widened on load); FP64 products
+template <int NX, class TX, class TY>
+__global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const TX* __restrict__ X, long ldx,
+                                                          const TY* __restrict__ Y, long ldy, long len,
                                                           long chunk, double* __restrict__ part) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, g = lane >> 4;
@@ -189,10 +233,10 @@ __global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const 
   const long k1 = k0 + chunk < len ? k0 + chunk : len;
   if (t0 >= nt) return;
   // rows of this lane (clamped: rows past ns / nt feed outputs that are not stored)
-  const double* xr[NX];
+  const TX* xr[NX];
 #pragma unroll
   for (int a = 0; a < NX; ++a) xr[a] = X + static_cast<long>(min(16 * a + i, ns - 1)) * ldx;
-  const double* yr[2];
+  const TY* yr[2];
 #pragma unroll
   for (int b = 0; b < 2; ++b) yr[b] = Y + static_cast<long>(min(t0 + 16 * b + i, nt - 1)) * ldy;
   d4 acc[NX][2];
@@ -203,33 +247,23 @@ __global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const 
   // blocks of 16 k-values; the loads of block + 1 are issued before the MFMAs
   // of the current block (past the last full block they repeat it)
   const long nfull = (k1 - k0) / 16;
-  auto load = [&](long blk, d2 (*xv)[2], d2 (*yv)[2]) {
+  auto load = [&](long blk, double (*xv)[4], double (*yv)[4]) {
     const long kk = k0 + 16 * blk + 4 * g;
 #pragma unroll
-    for (int a = 0; a < NX; ++a) {
-      xv[a][0] = *reinterpret_cast<const d2*>(xr[a] + kk);
-      xv[a][1] = *reinterpret_cast<const d2*>(xr[a] + kk + 2);
-    }
+    for (int a = 0; a < NX; ++a) load4(xr[a] + kk, xv[a]);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      yv[b][0] = *reinterpret_cast<const d2*>(yr[b] + kk);
-      yv[b][1] = *reinterpret_cast<const d2*>(yr[b] + kk + 2);
-    }
+    for (int b = 0; b < 2; ++b) load4(yr[b] + kk, yv[b]);
   };
-  auto mma = [&](d2 (*xv)[2], d2 (*yv)[2]) {
+  auto mma = [&](double (*xv)[4], double (*yv)[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int a = 0; a < NX; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const double xa = q < 2 ? xv[a][0][q] : xv[a][1][q - 2];
-          const double yb = q < 2 ? yv[b][0][q] : yv[b][1][q - 2];
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, acc[a][b], 0, 0, 0);
-        }
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[a][q], yv[b][q], acc[a][b], 0, 0, 0);
   };
   if (nfull > 0) {
-    d2 xa0[NX][2], ya0[2][2], xa1[NX][2], ya1[2][2];
+    double xa0[NX][4], ya0[2][4], xa1[NX][4], ya1[2][4];
     load(0, xa0, ya0);
     long blk = 0;
     for (; blk + 1 < nfull; blk += 2) {
@@ -250,7 +284,8 @@ __global__ void __launch_bounds__(256) skinny_dots_kernel(int ns, int nt, const 
       for (int a = 0; a < NX; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? xr[a][kk] : 0.0, in ? yr[b][kk] : 0.0, acc[a][b], 0,
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? static_cast<double>(xr[a][kk]) : 0.0,
+                                                           in ? static_cast<double>(yr[b][kk]) : 0.0, acc[a][b], 0,
                                                            0, 0);
     }
   }
@@ -297,24 +332,38 @@ size_t dots_workspace(int ns, int nt, long len) {
 
 namespace {
 
+// rows of X and Y can go through the tall-skinny kernel: long, with rows whose
+// starts are 16-byte aligned (the loads take 4 contiguous values)
+template <class TX, class TY>
+bool skinny_ok(const TX* X, long ldx, const TY* Y, long ldy, long len) {
+  const long ax = 16 / sizeof(TX), ay = 16 / sizeof(TY);
+  return len >= 1024 && ldx % ax == 0 && ldy % ay == 0 && aligned_to(X, 16) && aligned_to(Y, 16);
+}
+
+template <class TX, class TY>
+void dots_fast(hipStream_t st, int ns, const TX* X, long ldx, int nt, const TY* Y, long ldy, long len, double* out,
+               long ldo, double* ws) {
+  const long chunk = skinny_chunk(nt, len);
+  const int nchunks = static_cast<int>((len + chunk - 1) / chunk);
+  const dim3 grid(ceil_div(nt, 128), nchunks);
+  if (ns <= 16)
+    hipLaunchKernelGGL((skinny_dots_kernel<1, TX, TY>), grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
+  else if (ns <= 32)
+    hipLaunchKernelGGL((skinny_dots_kernel<2, TX, TY>), grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
+  else
+    hipLaunchKernelGGL((skinny_dots_kernel<3, TX, TY>), grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
+  if (ns * nt < 1024 && nchunks >= 64)
+    hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
+  else
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 64)), dim3(64 * kRedWaves), 0, st, nchunks, ns,
+                       nt, ws, out, ldo);
+  SEQX_LAUNCH_CHECK();
+}
+
 void dots_pass(hipStream_t st, int ns, const double* X, long ldx, int nt, const double* Y, long ldy, long len,
                double* out, long ldo, double* ws) {
-  if (len >= 1024 && ((ldx | ldy) & 1) == 0 && aligned_to(X, 16) && aligned_to(Y, 16)) {
-    const long chunk = skinny_chunk(nt, len);
-    const int nchunks = static_cast<int>((len + chunk - 1) / chunk);
-    const dim3 grid(ceil_div(nt, 128), nchunks);
-    if (ns <= 16)
-      hipLaunchKernelGGL(skinny_dots_kernel<1>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
-    else if (ns <= 32)
-      hipLaunchKernelGGL(skinny_dots_kernel<2>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
-    else
-      hipLaunchKernelGGL(skinny_dots_kernel<3>, grid, dim3(256), 0, st, ns, nt, X, ldx, Y, ldy, len, chunk, ws);
-    if (ns * nt < 1024 && nchunks >= 64)
-      hipLaunchKernelGGL(reduce_partials_wide_kernel, dim3(ns * nt), dim3(256), 0, st, nchunks, ns, nt, ws, out, ldo);
-    else
-      hipLaunchKernelGGL(reduce_partials_kernel, dim3(ceil_div(ns * nt, 64)), dim3(64 * kRedWaves), 0, st, nchunks,
-                         ns, nt, ws, out, ldo);
-    SEQX_LAUNCH_CHECK();
+  if (skinny_ok(X, ldx, Y, ldy, len)) {
+    dots_fast(st, ns, X, ldx, nt, Y, ldy, len, out, ldo, ws);
     return;
   }
   const long dc = dot_chunk(len);
@@ -347,5 +396,24 @@ void dots(hipStream_t st, int ns, const double* X, long ldx, int nt, const doubl
     dots_pass(st, std::min(kDotRows, ns - r0), X + static_cast<long>(r0) * ldx, ldx, nt, Y, ldy, len,
               out + static_cast<long>(r0) * ldo, ldo, ws);
 }
+
+// Inner products with FP32 rows on either side (widened to FP64 on load, FP64
+// products and sums): the tall-skinny path only, so rows must be long and
+// their starts 16-byte aligned.
+template <class TX, class TY>
+void dots_mixed(hipStream_t st, int ns, const TX* X, long ldx, int nt, const TY* Y, long ldy, long len, double* out,
+                long ldo, double* ws) {
+  if (ns <= 0 || nt <= 0) return;
+  if (!skinny_ok(X, ldx, Y, ldy, len)) throw Error(kEArg, "FP32 inner products need long, 16-byte aligned rows");
+  for (int r0 = 0; r0 < ns; r0 += kDotRows)
+    dots_fast(st, std::min(kDotRows, ns - r0), X + static_cast<long>(r0) * ldx, ldx, nt, Y, ldy, len,
+              out + static_cast<long>(r0) * ldo, ldo, ws);
+}
+template void dots_mixed<float, float>(hipStream_t, int, const float*, long, int, const float*, long, long, double*,
+                                       long, double*);
+template void dots_mixed<double, float>(hipStream_t, int, const double*, long, int, const float*, long, long, double*,
+                                        long, double*);
+template void dots_mixed<float, double>(hipStream_t, int, const float*, long, int, const double*, long, long, double*,
+                                        long, double*);
 
 }  // namespace seqx

@@ -194,6 +194,33 @@ def test_fp32_solve_finishes_in_fp64(ctx, name, theory, K):
     job.free()
 
 
+@pytest.mark.parametrize("theory,K,batch", [(seqx.TDHF, 6, 0), (seqx.CIS, 6, 0), (seqx.TDHF, 6, 3)],
+                         ids=["tdhf", "cis", "tdhf-root-batches"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_low_precision_phase_on_fp32_basis(ctx, theory, K, batch, prec):
+    """(H2O)24 (nov = 4608, a multiple of 4): the low-precision phase keeps its
+    basis and products in FP32 (widened on load for every inner product and
+    combination) and the solve finishes on an FP64 basis; roots and f equal
+    the FP64 solve's (itself pinned to dense oracle values up to (H2O)12 and
+    to the oracle's Davidson at (H2O)330) within the FP64 bar.  With root
+    batches the locked roots are deflated against the FP32 basis."""
+    mol = molecules.water_cluster(24, 24)
+    print(f"[gpu] fp32-basis solve (H2O)24 theory={theory} K={K} batch={batch} prec={prec}", flush=True)
+    job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
+    _, o, v = job.dims()
+    assert (o * v) % 4 == 0 and o * v >= 4096
+    job.solve(theory=theory, nroots=K, tol=1e-7, precision=seqx.FP64, root_batch=batch, max_iter=400)
+    ref = job.results()
+    low = seqx.FP32 if prec == "fp32" else seqx.BF16X3
+    job.solve(theory=theory, nroots=K, tol=1e-7, precision=low, root_batch=batch, max_iter=400)
+    got = job.results()
+    st = job.stats()
+    assert np.abs(got.omega_eV - ref.omega_eV).max() < 1e-6
+    assert np.abs(got.f - ref.f).max() < 1e-6
+    assert st.refine_iteration >= 1 and 0 < st.n_sigma_fp64 < st.n_sigma
+    job.free()
+
+
 def test_single_bf16_mode_is_rejected(ctx):
     mol = MOLS["C2H4"]
     job = ctx.prepare([mol.natoms], mol.Z, mol.xyz)
