@@ -25,20 +25,23 @@ DenseSolver::~DenseSolver() {
 }
 
 namespace {
-// n <= kJacobiMax: one workgroup, Jacobi in LDS on the lower triangle (no failure mode; info = 0)
-__global__ void __launch_bounds__(256) small_eigh_kernel(int n, double* A, int lda, double* w, int* info) {
+// n <= kJacobiMax: one workgroup of NT threads, Jacobi in LDS on the lower
+// triangle (no failure mode; info = 0).  256 threads: one wavefront alone
+// made the orthonormalisation of the (H2O)330 solve 67 -> 91 ms.
+template <int NT>
+__global__ void __launch_bounds__(NT) small_eigh_kernel(int n, double* A, int lda, double* w, int* info) {
   __shared__ JacobiLds L;
-  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
     const int i = idx / n, j = idx % n;
     L.A[i][j] = i >= j ? A[i + static_cast<long>(j) * lda] : A[j + static_cast<long>(i) * lda];  // lower triangle
   }
   __syncthreads();
-  jacobi_lds<256>(n, L);
-  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+  jacobi_lds<NT>(n, L);
+  for (int idx = threadIdx.x; idx < n * n; idx += NT) {
     const int r = idx / n, i = idx % n;
     A[i + static_cast<long>(r) * lda] = L.Q[i][L.perm[r]];
   }
-  for (int r = threadIdx.x; r < n; r += 256) w[r] = L.A[L.perm[r]][L.perm[r]];
+  for (int r = threadIdx.x; r < n; r += NT) w[r] = L.A[L.perm[r]][L.perm[r]];
   if (threadIdx.x == 0) info[0] = 0;
 }
 }  // namespace
@@ -46,7 +49,7 @@ __global__ void __launch_bounds__(256) small_eigh_kernel(int n, double* A, int l
 void DenseSolver::eigh(int n, double* A, int lda, double* w) {
   if (n <= 0) return;
   if (n <= kJacobiMax) {
-    hipLaunchKernelGGL(small_eigh_kernel, dim3(1), dim3(256), 0, st_, n, A, lda, w, info_.p);
+    hipLaunchKernelGGL(small_eigh_kernel<256>, dim3(1), dim3(256), 0, st_, n, A, lda, w, info_.p);
     SEQX_LAUNCH_CHECK();
     return;
   }
