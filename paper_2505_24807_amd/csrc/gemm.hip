@@ -144,6 +144,10 @@ struct Panel {
 // element pairs of B per thread for a tile BN columns wide
 template <class T, int BN>
 constexpr int kNPB = BN * Panel<T>::BK / 2 / 256;
+// two register sets for the global prefetch (panel p + 2 in flight while p is
+// multiplied): FP32 tiles, and FP64 tiles 96 wide, whose accumulators leave room
+template <class T, int BN>
+constexpr bool kTwoSets = sizeof(T) == 4 || BN == 96;
 
 // FP64 panels: global loads of element pairs; CHECKED tests every element
 // against M, N and K (edge tiles and the K tail).
@@ -362,9 +366,9 @@ __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
   typedef typename MF::pair_t P2;
-  if constexpr (sizeof(T) == 8) {
-    // FP64 (accumulators take 128 registers): one register set for the
-    // prefetch of panel p + 1; the K tail is the last panel.
+  if constexpr (!kTwoSets<T, BN>) {
+    // FP64 128-wide tiles (accumulators take 128 registers): one register set
+    // for the prefetch of panel p + 1; the K tail is the last panel.
     P2 ra[Panel<T>::NP], rb[NPB];
     const int nfull = K / BK;  // panels without a K tail
     const int npan = (K + BK - 1) / BK;
@@ -386,9 +390,10 @@ __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const
       __syncthreads();
     }
   } else {
-    // FP32: K is walked as a head panel of K % BK columns (when K is not a
-    // multiple of BK), loaded with zero fill, followed by full panels, so that
-    // the steady-state loop holds no K checks.  Two register sets for the
+    // FP32, and FP64 96-wide tiles (96 accumulator registers): K is walked as
+    // a head panel of K % BK columns (when K is not a multiple of BK), loaded
+    // with zero fill, followed by full panels, so that the steady-state loop
+    // holds no K checks.  Two register sets for the
     // global prefetch: the loads of panel p + 2 are issued while panel p is
     // multiplied and have two panels of MFMA work to land before they are
     // stored to LDS.  The loads are unconditional (past the last panel they
@@ -478,11 +483,12 @@ __global__ void __launch_bounds__(256) gemm128_kernel(int M, int N, int K, doubl
   int bid = blockIdx.y * nbx + blockIdx.x;
   if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
   const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * BN;
-  const bool keven = sizeof(T) == 8 || (K & 1) == 0;  // FP32 panels start at even k
+  // panels of the two-set path start at even k (pair loads)
+  const bool keven = !kTwoSets<T, BN> || (K & 1) == 0;
   if (m0 + kBM <= M && n0 + BN <= N && keven)
     tile128<T, To, TA, TB, EPI, 0, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
                                        m0, n0, As, Bs);
-  else if constexpr (sizeof(T) == 4) {
+  else if constexpr (kTwoSets<T, BN>) {
     if (keven && (!TA || (M & 1) == 0) && (TB || (N & 1) == 0))
       tile128<T, To, TA, TB, EPI, 1, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b,
                                          ep, m0, n0, As, Bs);
