@@ -182,9 +182,11 @@ __global__ void sp2_update_kernel(long nn, double* __restrict__ X, const double*
 constexpr int kSp2DeviceMaxN = 512;
 constexpr int kSp2Group = 4;
 
-// FP32 purification steps stop once sum lambda (1 - lambda) is below this;
-// the FP64 steps that follow converge quadratically from there
+// FP32 purification steps go on below this sum lambda (1 - lambda) only while
+// it keeps falling quadratically, down to kSp2Fp32Floor; the FP64 steps that
+// follow converge quadratically from there
 constexpr double kSp2Switch = 1e-2;
+constexpr double kSp2Fp32Floor = 1e-4;
 // FP32 steps are used for n >= kSp2MixedMinN (where the products dominate)
 // while max |F P - P F| > kSp2MixedMaxErr, far above the ~1e-7 they leave
 constexpr int kSp2MixedMinN = 512;
@@ -213,13 +215,18 @@ void sp2_density(hipStream_t st, int n, int nocc, const double* F, double* P, Sc
     float* Xs = w.X32.p;
     float* X2s = w.X2_32.p;
     to_float(st, nn, X, Xs);
+    double e_prev = 1e300;
     for (int it = 0; it < 200; ++it) {
       sgemm(st, false, false, n, n, n, 1.0, Xs, n, 0, Xs, n, 0, 0.0, X2s, n, 0, 1);
       hipLaunchKernelGGL(traces_kernel<float>, dim3(1), dim3(256), 0, st, n, Xs, X2s, w.scal.p + 2);
       double tr[2];
       SEQX_HIP(hipMemcpyAsync(tr, w.scal.p + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       SEQX_HIP(hipStreamSynchronize(st));
-      if (tr[0] - tr[1] < kSp2Switch) break;
+      const double e = tr[0] - tr[1];
+      // below kSp2Switch the steps converge quadratically until FP32 rounding
+      // stops them: leave once e is small or no longer falls fourfold a step
+      if (e < kSp2Fp32Floor || (e < kSp2Switch && e > 0.25 * e_prev)) break;
+      e_prev = e;
       if (std::fabs(tr[1] - nocc) < std::fabs(2.0 * tr[0] - tr[1] - nocc)) {
         std::swap(Xs, X2s);  // X <- X^2
       } else {
