@@ -127,9 +127,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(int M, int N, int K, double a
 // double-buffered in LDS: the loads of a later panel are issued (and kept
 // ahead of the MFMAs by a scheduling barrier) before the MFMAs of the current
 // one and land in the other LDS buffer afterwards, so one barrier per panel
-// suffices.  FP64 prefetches one panel ahead; FP32 two panels ahead with two
-// register sets, buffer loads on interior tiles and LDS operand reads issued
-// one k-step ahead of the MFMAs.  Interior and edge tiles take separate code
+// suffices.  Both precisions prefetch two panels ahead with two register sets
+// and use buffer loads on interior tiles; FP32 also issues its LDS operand
+// reads one k-step ahead of the MFMAs.  Interior and edge tiles take separate code
 // paths.  Needs even leading dimensions and batch strides and pair-aligned
 // base pointers (checked by the dispatcher).  Panel depth: 16 (FP64) or 32
 // (FP32), which keeps the loads of one panel at 16 registers per lane either
@@ -144,48 +144,6 @@ struct Panel {
 // element pairs of B per thread for a tile BN columns wide
 template <class T, int BN>
 constexpr int kNPB = BN * Panel<T>::BK / 2 / 256;
-// two register sets for the global prefetch (panel p + 2 in flight while p is
-// multiplied): FP32 tiles, and FP64 tiles 96 wide, whose accumulators leave room
-template <class T, int BN>
-constexpr bool kTwoSets = sizeof(T) == 4 || BN == 96;
-
-// FP64 panels: global loads of element pairs; CHECKED tests every element
-// against M, N and K (edge tiles and the K tail).
-template <class T, bool TA, bool TB, bool CHECKED, int BN>
-__device__ __forceinline__ void panel_load(const T* __restrict__ A, long lda, const T* __restrict__ B, long ldb, int M,
-                                           int N, int K, int m0, int n0, int k0, int tid,
-                                           typename Mfma<T>::pair_t* ra, typename Mfma<T>::pair_t* rb) {
-  typedef typename Mfma<T>::pair_t P2;
-  constexpr int BK = Panel<T>::BK, HK = BK / 2, HM = kBM / 2, HN = BN / 2;
-#pragma unroll
-  for (int j = 0; j < Panel<T>::NP; ++j) {
-    const int c = tid + 256 * j;
-    int gi, gk;
-    if (!TA) { gi = m0 + c / HK; gk = k0 + (c % HK) * 2; } else { gk = k0 + c / HM; gi = m0 + (c % HM) * 2; }
-    const T* p = TA ? A + static_cast<long>(gk) * lda + gi : A + static_cast<long>(gi) * lda + gk;
-    if (!CHECKED) {
-      ra[j] = *reinterpret_cast<const P2*>(__builtin_assume_aligned(p, sizeof(P2)));
-    } else {
-      const int gi1 = TA ? gi + 1 : gi, gk1 = TA ? gk : gk + 1;
-      ra[j].x = (gi < M && gk < K) ? p[0] : T(0);
-      ra[j].y = (gi1 < M && gk1 < K) ? p[1] : T(0);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kNPB<T, BN>; ++j) {
-    const int c = tid + 256 * j;
-    int gj, gk;
-    if (!TB) { gk = k0 + c / HN; gj = n0 + (c % HN) * 2; } else { gj = n0 + c / HK; gk = k0 + (c % HK) * 2; }
-    const T* q = TB ? B + static_cast<long>(gj) * ldb + gk : B + static_cast<long>(gk) * ldb + gj;
-    if (!CHECKED) {
-      rb[j] = *reinterpret_cast<const P2*>(__builtin_assume_aligned(q, sizeof(P2)));
-    } else {
-      const int gj1 = TB ? gj : gj + 1, gk1 = TB ? gk + 1 : gk;
-      rb[j].x = (gj < N && gk < K) ? q[0] : T(0);
-      rb[j].y = (gj1 < N && gk1 < K) ? q[1] : T(0);
-    }
-  }
-}
 
 // Edge tiles and the K head panel: element loads at clamped indices, so every
 // load is issued unconditionally (which keeps the wait counters exact).  Rows
@@ -366,34 +324,10 @@ __device__ __forceinline__ void tile128(int M, int N, int K, double alpha, const
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
   typedef typename MF::pair_t P2;
-  if constexpr (!kTwoSets<T, BN>) {
-    // FP64 128-wide tiles (accumulators take 128 registers): one register set
-    // for the prefetch of panel p + 1; the K tail is the last panel.
-    P2 ra[Panel<T>::NP], rb[NPB];
-    const int nfull = K / BK;  // panels without a K tail
-    const int npan = (K + BK - 1) / BK;
-    if (nfull > 0) panel_load<T, TA, TB, EDGE, BN>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
-    else panel_load<T, TA, TB, true, BN>(A, lda, B, ldb, M, N, K, m0, n0, 0, tid, ra, rb);
-    panel_store<T, TA, TB, BN>(As, Bs, tid, ra, rb);
-    __syncthreads();
-    for (int kt = 0; kt < npan; ++kt) {
-      const int cur = (kt & 1) * BK, nxt = BK - cur;
-      const bool more = kt + 1 < npan;
-      if (more) {
-        if (kt + 1 < nfull)
-          panel_load<T, TA, TB, EDGE, BN>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
-        else panel_load<T, TA, TB, true, BN>(A, lda, B, ldb, M, N, K, m0, n0, (kt + 1) * BK, tid, ra, rb);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      panel_mfma<T, TN>(As + cur, Bs + cur, lane, wm, wn, acc);
-      if (more) panel_store<T, TA, TB, BN>(As + nxt, Bs + nxt, tid, ra, rb);
-      __syncthreads();
-    }
-  } else {
-    // FP32, and FP64 96-wide tiles (96 accumulator registers): K is walked as
-    // a head panel of K % BK columns (when K is not a multiple of BK), loaded
-    // with zero fill, followed by full panels, so that the steady-state loop
-    // holds no K checks.  Two register sets for the
+  {
+    // K is walked as a head panel of K % BK columns (when K is not a multiple
+    // of BK), loaded with zero fill, followed by full panels, so that the
+    // steady-state loop holds no K checks.  Two register sets for the
     // global prefetch: the loads of panel p + 2 are issued while panel p is
     // multiplied and have two panels of MFMA work to land before they are
     // stored to LDS.  The loads are unconditional (past the last panel they
@@ -483,22 +417,16 @@ __global__ void __launch_bounds__(256) gemm128_kernel(int M, int N, int K, doubl
   int bid = blockIdx.y * nbx + blockIdx.x;
   if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
   const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * BN;
-  // panels of the two-set path start at even k (pair loads)
-  const bool keven = !kTwoSets<T, BN> || (K & 1) == 0;
+  const bool keven = (K & 1) == 0;  // panels start at even k (pair loads)
   if (m0 + kBM <= M && n0 + BN <= N && keven)
     tile128<T, To, TA, TB, EPI, 0, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
                                        m0, n0, As, Bs);
-  else if constexpr (kTwoSets<T, BN>) {
-    if (keven && (!TA || (M & 1) == 0) && (TB || (N & 1) == 0))
-      tile128<T, To, TA, TB, EPI, 1, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b,
-                                         ep, m0, n0, As, Bs);
-    else
-      tile128<T, To, TA, TB, EPI, 2, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b,
-                                         ep, m0, n0, As, Bs);
-  } else {
+  else if (keven && (!TA || (M & 1) == 0) && (TB || (N & 1) == 0))
+    tile128<T, To, TA, TB, EPI, 1, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
+                                       m0, n0, As, Bs);
+  else
     tile128<T, To, TA, TB, EPI, 2, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
                                        m0, n0, As, Bs);
-  }
 }
 
 // ---------------------------------------------------------------- dispatch
