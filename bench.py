@@ -97,7 +97,8 @@ def run_mode(ctx, mol, ref, precision, steps, warmup, guess=0, pspace=0, nguard=
     for _ in range(warmup):
         step().free()
     torch.cuda.synchronize()
-    totals = {"n_sigma": 0, "n_sigma_fp64": 0, "scf": 0.0, "dav": 0.0, "sig": 0.0, "iters": 0, "refine": 0}
+    totals = {"n_sigma": 0, "n_sigma_fp64": 0, "n_sigma_bf16x3": 0, "scf": 0.0, "dav": 0.0, "sig": 0.0, "iters": 0,
+              "refine": 0, "fp32_iter": 0}
     phase = np.zeros((4, 5))
     dav_phase = np.zeros(8)
     ttr, parity = [], []
@@ -112,6 +113,8 @@ def run_mode(ctx, mol, ref, precision, steps, warmup, guess=0, pspace=0, nguard=
         totals["n_sigma"] += st.n_sigma
         totals["n_sigma_fp64"] += st.n_sigma_fp64
         totals["refine"] = max(totals["refine"], st.refine_iteration)
+        totals["n_sigma_bf16x3"] += st.n_sigma_bf16x3
+        totals["fp32_iter"] = max(totals["fp32_iter"], st.fp32_iteration)
         totals["scf"] += st.t_scf_s + st.t_integrals_s
         totals["dav"] += st.t_davidson_s
         totals["sig"] += st.t_sigma_s
@@ -348,6 +351,8 @@ def main():
                     help="starting space of the timed run (learned: the packaged network's 2K best pairs)")
     ap.add_argument("--guard", type=int, default=0, help="extra roots iterated beside the 10 wanted ones")
     ap.add_argument("--no-fp64-comparison", action="store_true")
+    ap.add_argument("--no-ladder", action="store_true",
+                    help="skip the split-bfloat16 -> FP32 -> FP64 comparison solve")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-molecule batched CIS section")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess section")
     ap.add_argument("--no-batched-loop", action="store_true",
@@ -415,7 +420,7 @@ def main():
     s = summary(main_run, K)
     mode = {seqx.FP32: "FP32 transforms (FP64 contraction sums, FP64 subspace), finished with FP64 products",
             seqx.BF16X3: "split-bfloat16 transforms (three bfloat16 products, FP32 accumulation; FP64 contraction "
-                         "sums, FP64 subspace), finished with FP64 products",
+                         "sums, FP64 subspace), then FP32 transforms, finished with FP64 products",
             seqx.FP64: "FP64 transforms"}[prec]
     mode += (", learned starting space (the 20 best-scored pairs)" if guess == seqx.GUESS_LEARNED
              else ", gap guess")
@@ -440,6 +445,23 @@ def main():
                                             round(s64["time_to_10_roots_at_1e-4_eV_s"] / out["time_to_10_roots_at_1e-4_eV_s"], 3)
                                             if s64["time_to_10_roots_at_1e-4_eV_s"] and out["time_to_10_roots_at_1e-4_eV_s"]
                                             else None)}
+        if prec == seqx.FP32 and not args.no_ladder:
+            # the same solve stepping through split-bfloat16, FP32 and FP64 products
+            rl = run_mode(ctx, mol, ref, seqx.BF16X3, K, args.warmup, guess, pspace, args.guard)
+            sl = summary(rl, K)
+            out["split_bf16_ladder_comparison"] = {
+                **{k: v for k, v in sl.items()
+                   if k in ("value", "ms_per_step", "time_to_10_roots_at_1e-4_eV_s", "parity_max_abs_eV_vs_oracle",
+                            "davidson_s", "davidson_iterations", "n_sigma_per_step", "n_sigma_fp64_per_step",
+                            "refine_iteration", "davidson_phase_ms_per_step")},
+                "n_sigma_bf16x3_per_step": rl["totals"]["n_sigma_bf16x3"] // K,
+                "fp32_iteration": rl["totals"]["fp32_iter"],
+                "speedup_vs_fp32_mixed": {
+                    "time_per_step": round(out["ms_per_step"] / sl["ms_per_step"], 3),
+                    "time_to_10_roots_at_1e-4_eV": (
+                        round(out["time_to_10_roots_at_1e-4_eV_s"] / sl["time_to_10_roots_at_1e-4_eV_s"], 3)
+                        if out["time_to_10_roots_at_1e-4_eV_s"] and sl["time_to_10_roots_at_1e-4_eV_s"] else None)},
+            }
         if prec != seqx.FP64 and guess != seqx.GUESS_GAP:
             rm = run_mode(ctx, mol, ref, prec, K, args.warmup)
             out["mixed_gap_guess_comparison"] = {k: v for k, v in summary(rm, K).items()

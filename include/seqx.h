@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SEQX_ABI_VERSION 4
+#define SEQX_ABI_VERSION 5
 #define SEQX_NPARAM 11 /* per-element parameters, order below */
 
 typedef struct seqx_ctx seqx_ctx; /* one device + one stream */
@@ -67,7 +67,13 @@ typedef enum { SEQX_CIS = 0, SEQX_TDHF = 1 } seqx_theory;
  * paper's outlook).  A seqx_solve in FP32 restarts from its Ritz vectors with
  * FP64 products once its residuals reach max(tol, the FP32 rounding floor) or
  * stop improving, and converges to tol in FP64, so its roots carry FP64
- * accuracy.  SEQX_BF16 and SEQX_BF16X3 are reserved and return SEQX_E_ARG. */
+ * accuracy.  SEQX_BF16X3: the same FP32 storage, each transform as three
+ * bfloat16 matrix-core products of the split operands x = hi + lo (hi lo,
+ * lo hi, hi hi; FP32 accumulation, at most 3 * 2^-16 relative error per
+ * product); a seqx_solve steps through split bfloat16, FP32 and FP64 products,
+ * restarting from its Ritz vectors at each step once the residuals reach the
+ * floor of the current precision, so its roots too carry FP64 accuracy.
+ * SEQX_BF16 (single bfloat16) is reserved and returns SEQX_E_ARG. */
 typedef enum { SEQX_FP64 = 0, SEQX_FP32 = 1, SEQX_BF16 = 2, SEQX_BF16X3 = 3 } seqx_precision;
 
 /* Starting space of the Davidson iteration:
@@ -170,6 +176,11 @@ typedef struct {
   int32_t max_subspace_used;
   int32_t subspace_cap;
   int32_t n_collapses;
+  /* SEQX_BF16X3 solves: the iteration at which the solve restarted from its
+   * Ritz vectors with FP32 products (0 when it did not), and the sigma vectors
+   * formed with split-bfloat16 transforms. */
+  int32_t fp32_iteration;
+  int64_t n_sigma_bf16x3;
 } seqx_stats;
 
 /* Version of this header the library was built with (SEQX_ABI_VERSION). */

@@ -734,6 +734,8 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
     job->stats.n_sigma = 0;
     job->stats.n_sigma_fp64 = 0;
     job->stats.refine_iteration = 0;
+    job->stats.fp32_iteration = 0;
+    job->stats.n_sigma_bf16x3 = 0;
     for (double& x : job->stats.dav_phase_ms) x = 0.0;
     job->dw.sig.timer.reset();
     job->stats.dav_iterations = 0;
@@ -832,6 +834,8 @@ seqx_status seqx_solve(seqx_job* job, const seqx_solve_opts* opts) {
       job->stats.n_sigma += r.n_sigma;
       job->stats.n_sigma_fp64 += r.n_sigma_fp64;
       job->stats.refine_iteration = std::max(job->stats.refine_iteration, r.refine_iter);
+      job->stats.fp32_iteration = std::max(job->stats.fp32_iteration, r.fp32_iter);
+      job->stats.n_sigma_bf16x3 += r.n_sigma_bf16x3;
       for (int p = 0; p < kNumDavPhases; ++p) job->stats.dav_phase_ms[p] += r.phase_ms[p];
       job->stats.dav_iterations = std::max(job->stats.dav_iterations, r.iterations);
       job->stats.max_subspace_used = std::max(job->stats.max_subspace_used, r.max_subspace);

@@ -542,7 +542,9 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   // orthonormal.  products: carry the products and projected matrices along
   // (else the caller recomputes them).  Returns the new basis size.
   // prev: the previous iteration's coefficients (rows [0, s_prev)) or null.
-  auto collapse = [&](int S, bool products, const double* tco, const double* prev, int s_prev) -> int {
+  // to64: the collapsed rows of an FP32 basis go to FP64 scratch (without products).
+  auto collapse = [&](int S, bool products, const double* tco, const double* prev, int s_prev,
+                      bool to64 = false) -> int {
     const int qr = tdhf ? 2 * K : std::min(2 * K, S);
     // coefficient block Cc (S x q0) = [t u] (TDHF) or the qr lowest eigenvectors
     // (CIS), then the previous coefficients
@@ -587,7 +589,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       q = orth_cols(w.Hs.p, q, -1e-12, w.Lm.p);
     }
     double* Qc = w.Lm.p;
-    if (lb && !products) {
+    if (lb && to64) {
       // leaving the FP32 basis: the collapsed rows in FP64, in scratch (the
       // caller orthonormalises them into the FP64 basis)
       comb(st, q, nov, S, 1.0, Qc, Smax, w.V32.p, nov, 0.0, w.scratch.p, nov);
@@ -597,6 +599,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       comb(st, q, nov, S, 1.0, Qc, Smax, w.V32.p, nov, 0.0, w.scr32.p, nov);
       SEQX_HIP(hipMemcpyAsync(w.V32.p, w.scr32.p, static_cast<size_t>(q) * nov * sizeof(float),
                               hipMemcpyDeviceToDevice, st));
+      if (!products) return q;
       for (int p = 0; p < ps; ++p)
         comb(st, q, nov, S, 1.0, Qc, Smax, w.SP32.p + p * nov, ldp, 0.0, w.scr32.p + p * nov, ldp);
       SEQX_HIP(hipMemcpyAsync(w.SP32.p, w.scr32.p, static_cast<size_t>(q) * ldp * sizeof(float),
@@ -621,19 +624,25 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   };
 
   int prec = opt.precision;
-  double floor_low = 0.0, rbest = 1e300;
+  double floor_low = 0.0, rbest = 1e300, dmax = 0.0;
   int stall = 0;
+  // rounding floor of the low-precision products: sums over n terms carry a
+  // relative error of about sqrt(n) u, on a scale set by the largest
+  // orbital-energy gap; four times that.  FP32: u = 2^-24.  Split bfloat16:
+  // one product may be off by 3 * 2^-16, but the operand splits round to
+  // either side and their errors largely cancel in the sums; the residuals
+  // of its phase level off about 16 times above those of the FP32 phase, so
+  // u = 2^-20 there (a lower floor only lengthens that phase until the
+  // stall rule ends it).
+  auto rounding_floor = [&](int p) {
+    const double u = std::ldexp(1.0, p == kPrecBF16x3 ? -20 : -24);
+    return 4.0 * std::sqrt(static_cast<double>(m.nao)) * u * dmax;
+  };
   if (prec != kPrecFP64) {
-    // rounding floor of the low-precision products: sums over n terms carry a
-    // relative error of about sqrt(n) u (FP32: u = 2^-24; split bfloat16:
-    // u = 3 * 2^-16 per product), on a scale set by the largest orbital-energy
-    // gap; four times that
     max_abs(st, nov, w.d.p, w.rn.p, w.ws.p);
-    double dmax = 0.0;
     d2h(&dmax, w.rn.p, 1, st);
     SEQX_HIP(hipStreamSynchronize(st));
-    const double u = prec == kPrecBF16x3 ? 3.0 * std::ldexp(1.0, -16) : std::ldexp(1.0, -24);
-    floor_low = 4.0 * std::sqrt(static_cast<double>(m.nao)) * u * dmax;
+    floor_low = rounding_floor(prec);
   }
   // coefficients of iteration it - 1 in the basis of iteration it, unless a
   // collapse in between rotated the basis
@@ -664,6 +673,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       itimer.mark(kDavProject);
       res.n_sigma += knew;
       if (prec == kPrecFP64) res.n_sigma_fp64 += knew;
+      if (prec == kPrecBF16x3) res.n_sigma_bf16x3 += knew;
       const int S1 = S + knew;
       // 2. projected matrices, new columns (column-major, ld = Smax): one pass over
       // V for (A+B) and (A-B) together, since their rows are interleaved
@@ -772,20 +782,38 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       if (prec != kPrecFP64) {
         // Mixed-precision phase: the residuals cannot fall much below the
         // rounding floor of the low-precision products.  Restart from the
-        // Ritz vectors with FP64 products once every root is below
-        // max(tol, floor), or once the largest residual, within 4x of the
-        // floor, has not halved for four iterations.
+        // Ritz vectors with products of the next precision (split bfloat16
+        // -> FP32 -> FP64) once every root is below max(tol, floor), or once
+        // the largest residual, within 4x of the floor, has not halved for
+        // four iterations.
         if (rmax < 4.0 * floor_low) {
           stall = rmax < 0.5 * rbest ? 0 : stall + 1;
           rbest = std::min(rbest, rmax);
         }
-        if (rmax <= std::max(opt.tol, floor_low) || stall >= 4) {
+        // the split-bfloat16 phase ends after max_iter / 3 iterations at the
+        // latest, should its residuals level off above the stall window
+        const bool bf_cap = prec == kPrecBF16x3 && it >= std::max(20, opt.max_iter / 3);
+        if (rmax <= std::max(opt.tol, floor_low) || stall >= 4 || bf_cap) {
+          const bool to_fp32 = prec == kPrecBF16x3 && rmax > opt.tol;
           if (log_enabled())
-            std::fprintf(stderr, "{\"refine_after_iter\": %d, \"max_residual\": %.3e, \"floor\": %.3e}\n", it, rmax,
-                         floor_low);
+            std::fprintf(stderr, "{\"%s_after_iter\": %d, \"max_residual\": %.3e, \"floor\": %.3e}\n",
+                         to_fp32 ? "fp32" : "refine", it, rmax, floor_low);
           itimer.mark(kDavCollapse);
-          S = collapse(S, false, w.coef.p + static_cast<long>(it & 1) * 2 * K * Smax, prev_coef(it), s_at[(it - 1) & 1]);
+          S = collapse(S, false, w.coef.p + static_cast<long>(it & 1) * 2 * K * Smax, prev_coef(it), s_at[(it - 1) & 1],
+                       !to_fp32);
           last_collapse = it;
+          if (to_fp32) {
+            // same basis (FP32 rows, or FP64 rows for short vectors), products
+            // formed again on the FP32 matrix cores
+            knew = S;
+            S = 0;
+            prec = kPrecFP32;
+            floor_low = rounding_floor(prec);
+            rbest = 1e300;
+            stall = 0;
+            res.fp32_iter = it + 1;
+            continue;
+          }
           if (lb) {
             // FP32 rows are orthonormal to about 1e-7: orthonormalise them again in FP64
             itimer.mark(kDavOrtho);
@@ -900,6 +928,8 @@ DavResult davidson_root_batches(DeviceMolecule& m, const DavOptions& opt, int ba
     total.iterations += r.iterations;
     total.n_sigma += r.n_sigma;
     total.n_sigma_fp64 += r.n_sigma_fp64;
+    total.n_sigma_bf16x3 += r.n_sigma_bf16x3;
+    total.fp32_iter = std::max(total.fp32_iter, r.fp32_iter);
     total.refine_iter = std::max(total.refine_iter, r.refine_iter);
     total.t_sigma_ms += r.t_sigma_ms;
     total.max_subspace = std::max(total.max_subspace, r.max_subspace);

@@ -62,6 +62,8 @@ struct DavResult {
   long n_sigma = 0;
   long n_sigma_fp64 = 0;   // products formed with FP64 transforms
   int refine_iter = 0;     // iteration whose products were the first FP64 ones after a mixed-precision phase
+  int fp32_iter = 0;       // iteration whose products were the first FP32 ones after a split-bfloat16 phase
+  long n_sigma_bf16x3 = 0; // products formed with split-bfloat16 transforms
   double t_sigma_ms = 0.0;
   int max_subspace = 0;    // largest basis size reached
   int subspace_cap = 0;    // cap in force

@@ -65,7 +65,8 @@ class Stats(C.Structure):
                 ("phase_flops", C.c_double * 5), ("phase_bytes", C.c_double * 5), ("dav_phase_ms", C.c_double * 8),
                 ("n_sigma_fp64", C.c_int64), ("refine_iteration", C.c_int32), ("t_autotune_s", C.c_double),
                 ("batched_graph", C.c_int32), ("tile_variant", C.c_int32 * 5), ("batched_sigma_flops", C.c_double),
-                ("max_subspace_used", C.c_int32), ("subspace_cap", C.c_int32), ("n_collapses", C.c_int32)]
+                ("max_subspace_used", C.c_int32), ("subspace_cap", C.c_int32), ("n_collapses", C.c_int32),
+                ("fp32_iteration", C.c_int32), ("n_sigma_bf16x3", C.c_int64)]
 
     DAV_PHASES = ["sigma", "projection", "subspace eig", "ritz+residual", "check", "precond", "collapse", "ortho"]
 

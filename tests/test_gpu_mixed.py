@@ -218,6 +218,12 @@ def test_low_precision_phase_on_fp32_basis(ctx, theory, K, batch, prec):
     assert np.abs(got.omega_eV - ref.omega_eV).max() < 1e-6
     assert np.abs(got.f - ref.f).max() < 1e-6
     assert st.refine_iteration >= 1 and 0 < st.n_sigma_fp64 < st.n_sigma
+    if prec == "bf16x3":
+        # split bfloat16, then FP32, then FP64 products
+        assert st.n_sigma_bf16x3 > 0
+        assert 1 <= st.fp32_iteration <= st.refine_iteration
+    else:
+        assert st.n_sigma_bf16x3 == 0 and st.fp32_iteration == 0
     job.free()
 
 
