@@ -146,10 +146,11 @@ __device__ inline double guard(double x) {
   return fabs(x) < 1e-8 ? (x < 0 ? -1e-8 : 1e-8) : x;
 }
 
+template <class TW>
 __global__ void precond_kernel(long nov, int tdhf, const int* __restrict__ sel, const double* __restrict__ om,
                                const double* __restrict__ d, const double* __restrict__ Tv,
                                const double* __restrict__ Uv, const double* __restrict__ PT,
-                               const double* __restrict__ MU, double* __restrict__ W) {
+                               const double* __restrict__ MU, TW* __restrict__ W) {
   const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
   if (x >= nov) return;
   const int q = blockIdx.y;
@@ -159,20 +160,21 @@ __global__ void precond_kernel(long nov, int tdhf, const int* __restrict__ sel, 
   if (tdhf) {
     const double rT = PT[b] - w * Uv[b];
     const double rU = MU[b] - w * Tv[b];
-    W[(2L * q) * nov + x] = (rT + rU) / guard(w - d[x]);
-    W[(2L * q + 1) * nov + x] = (rT - rU) / guard(-w - d[x]);
+    W[(2L * q) * nov + x] = static_cast<TW>((rT + rU) / guard(w - d[x]));
+    W[(2L * q + 1) * nov + x] = static_cast<TW>((rT - rU) / guard(-w - d[x]));
   } else {
     const double r = PT[b] - w * Tv[b];
-    W[static_cast<long>(q) * nov + x] = r / guard(w - d[x]);
+    W[static_cast<long>(q) * nov + x] = static_cast<TW>(r / guard(w - d[x]));
   }
 }
 
-__global__ void scale_rows_kernel(long nov, double* __restrict__ W, const double* __restrict__ G, int ldg) {
+template <class TW>
+__global__ void scale_rows_kernel(long nov, TW* __restrict__ W, const double* __restrict__ G, int ldg) {
   const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
   const int r = blockIdx.y;
   if (x >= nov) return;
   const double g = G[static_cast<long>(r) * ldg + r];
-  W[r * nov + x] *= (g > 0.0) ? 1.0 / sqrt(g) : 0.0;
+  W[r * nov + x] = static_cast<TW>(W[r * nov + x] * ((g > 0.0) ? 1.0 / sqrt(g) : 0.0));
 }
 
 // dst columns (ld) = src columns over rows [0, s0), zero over rows [s0, s1)
@@ -352,21 +354,22 @@ void dts(hipStream_t st, int ns, const TX* X, long ldx, int nt, const TY* Y, lon
 }
 
 // Orthonormalise the nc rows of Wc against V[0:S] and among themselves, append
-// the kept directions at V[S:]; returns how many were kept.
-template <class TV>
-int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov, int nc, double* Wc, int S, TV* V,
+// the kept directions at V[S:]; returns how many were kept.  Wc: FP64 rows, or
+// FP32 rows beside an FP32 basis (inner products and sums in FP64 either way).
+template <class TV, class TW>
+int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov, int nc, TW* Wc, int S, TV* V,
                           int max_keep) {
   double* G = w.G.p;
   double* Cc = w.Q.p;  // nc x S coefficients, reused below for the Loewdin vectors
-  dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
-  hipLaunchKernelGGL(scale_rows_kernel, dim3(ceil_div(nov, 256), nc), dim3(256), 0, st, nov, Wc, G, nc);
+  dts(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
+  hipLaunchKernelGGL(scale_rows_kernel<TW>, dim3(ceil_div(nov, 256), nc), dim3(256), 0, st, nov, Wc, G, nc);
   SEQX_LAUNCH_CHECK();
   // classical Gram-Schmidt against V; a second pass only when a unit row lost
   // more than three quarters of its norm ("twice is enough")
   for (int pass = 0; pass < 2 && S > 0; ++pass) {
     dts(st, nc, Wc, nov, S, V, nov, nov, Cc, S, w.ws.p);
     comb(st, nc, nov, S, -1.0, Cc, S, V, nov, 1.0, Wc, nov);
-    dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
+    dts(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
     if (pass == 1) break;
     std::vector<double> g(static_cast<size_t>(nc) * nc);
     d2h(g.data(), G, g.size(), st);
@@ -375,7 +378,7 @@ int orthonormalize_append(hipStream_t st, DenseSolver& ds, DavWork& w, long nov,
     for (int r = 0; r < nc; ++r) again = again || g[static_cast<size_t>(r) * nc + r] < 0.25;
     if (!again) break;
   }
-  if (S == 0) dots(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
+  if (S == 0) dts(st, nc, Wc, nov, nc, Wc, nov, nov, G, nc, w.ws.p);
   ds.eigh(nc, G, nc, w.w2.p);
   std::vector<double> lam(nc);
   d2h(lam.data(), w.w2.p, nc, st);
@@ -832,8 +835,14 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       itimer.mark(kDavPrecond);
       const int nsel = static_cast<int>(sel.size());
       SEQX_HIP(hipMemcpyAsync(w.sel.p, sel.data(), nsel * sizeof(int), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(precond_kernel, dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov, tdhf ? 1 : 0,
-                         w.sel.p, om, w.d.p, w.Tv.p, Uv, w.PT.p, MU, w.W.p);
+      // FP32 correction rows beside an FP32 basis (W's storage holds twice as many)
+      float* W32 = reinterpret_cast<float*>(w.W.p);
+      if (lb)
+        hipLaunchKernelGGL(precond_kernel<float>, dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov, tdhf ? 1 : 0,
+                           w.sel.p, om, w.d.p, w.Tv.p, Uv, w.PT.p, MU, W32);
+      else
+        hipLaunchKernelGGL(precond_kernel<double>, dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov,
+                           tdhf ? 1 : 0, w.sel.p, om, w.d.p, w.Tv.p, Uv, w.PT.p, MU, w.W.p);
       SEQX_LAUNCH_CHECK();
       const int nc = tdhf ? 2 * nsel : nsel;
       // 7. collapse onto the best Ritz vectors when the basis would overflow
@@ -845,7 +854,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       }
       // 8. orthonormalise and append
       itimer.mark(kDavOrtho);
-      knew = lb ? orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V32.p, Smax - S)
+      knew = lb ? orthonormalize_append(st, ds, w, nov, nc, W32, S, w.V32.p, Smax - S)
                 : orthonormalize_append(st, ds, w, nov, nc, w.W.p, S, w.V.p, Smax - S);
       if (knew == 0) break;
     }
