@@ -28,7 +28,7 @@ constexpr int kBT = 16;  // reflectors per LDS chunk of the back-transformation
 // wavefront, 17-fold rounds) measured faster than 64 (65-fold rounds) for the
 // 10-20 lowest of 140-240
 constexpr int kMsLanes = 16;
-constexpr int kIG = 8;   // eigenvectors per group of the inverse iteration (their factors fill 96 KB of LDS)
+constexpr int kIG = 10;  // eigenvectors per group of the inverse iteration: ten roots in one pass (factors: 120 KB of LDS)
 // eigenvectors staged in LDS for the orthogonalisation, beside the reflector chunks
 constexpr int kZsMax = 6 * kIG * kSmallDense - kBT * kSmallDense;
 
