@@ -107,9 +107,10 @@ __global__ void scale_cols_kernel(double* C, int ld, int nrows, int K, const dou
 
 // residual norms^2, partial sums per block: TDHF r_T = PT - w U, r_U = MU - w T;
 // CIS r = PT - w T
-__global__ void residual_norm_kernel(long nov, int tdhf, const double* __restrict__ om, const double* __restrict__ Tv,
-                                     const double* __restrict__ Uv, const double* __restrict__ PT,
-                                     const double* __restrict__ MU, double* __restrict__ part) {
+template <class TI>
+__global__ void residual_norm_kernel(long nov, int tdhf, const double* __restrict__ om, const TI* __restrict__ Tv,
+                                     const TI* __restrict__ Uv, const TI* __restrict__ PT,
+                                     const TI* __restrict__ MU, double* __restrict__ part) {
   __shared__ double red[256];
   const int j = blockIdx.y;
   const double w = om[j];
@@ -117,11 +118,11 @@ __global__ void residual_norm_kernel(long nov, int tdhf, const double* __restric
   double s = 0.0;
   for (long x = blockIdx.x * 256L + threadIdx.x; x < nov; x += 256L * gridDim.x) {
     if (tdhf) {
-      const double rT = PT[base + x] - w * Uv[base + x];
-      const double rU = MU[base + x] - w * Tv[base + x];
+      const double rT = static_cast<double>(PT[base + x]) - w * static_cast<double>(Uv[base + x]);
+      const double rU = static_cast<double>(MU[base + x]) - w * static_cast<double>(Tv[base + x]);
       s += rT * rT + rU * rU;
     } else {
-      const double r = PT[base + x] - w * Tv[base + x];
+      const double r = static_cast<double>(PT[base + x]) - w * static_cast<double>(Tv[base + x]);
       s += r * r;
     }
   }
@@ -146,11 +147,11 @@ __device__ inline double guard(double x) {
   return fabs(x) < 1e-8 ? (x < 0 ? -1e-8 : 1e-8) : x;
 }
 
-template <class TW>
+template <class TI, class TW>
 __global__ void precond_kernel(long nov, int tdhf, const int* __restrict__ sel, const double* __restrict__ om,
-                               const double* __restrict__ d, const double* __restrict__ Tv,
-                               const double* __restrict__ Uv, const double* __restrict__ PT,
-                               const double* __restrict__ MU, TW* __restrict__ W) {
+                               const double* __restrict__ d, const TI* __restrict__ Tv,
+                               const TI* __restrict__ Uv, const TI* __restrict__ PT,
+                               const TI* __restrict__ MU, TW* __restrict__ W) {
   const long x = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
   if (x >= nov) return;
   const int q = blockIdx.y;
@@ -158,12 +159,12 @@ __global__ void precond_kernel(long nov, int tdhf, const int* __restrict__ sel, 
   const double w = om[j];
   const long b = static_cast<long>(j) * nov + x;
   if (tdhf) {
-    const double rT = PT[b] - w * Uv[b];
-    const double rU = MU[b] - w * Tv[b];
+    const double rT = static_cast<double>(PT[b]) - w * static_cast<double>(Uv[b]);
+    const double rU = static_cast<double>(MU[b]) - w * static_cast<double>(Tv[b]);
     W[(2L * q) * nov + x] = static_cast<TW>((rT + rU) / guard(w - d[x]));
     W[(2L * q + 1) * nov + x] = static_cast<TW>((rT - rU) / guard(-w - d[x]));
   } else {
-    const double r = PT[b] - w * Tv[b];
+    const double r = static_cast<double>(PT[b]) - w * static_cast<double>(Tv[b]);
     W[static_cast<long>(q) * nov + x] = static_cast<TW>(r / guard(w - d[x]));
   }
 }
@@ -478,6 +479,12 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   w.PT.ensure(static_cast<size_t>(ps) * K * nov);
   double* Uv = w.Tv.p + static_cast<long>(K) * nov;
   double* MU = w.PT.p + static_cast<long>(K) * nov;
+  // the low-precision phase keeps its Ritz vectors and products in FP32 (the
+  // same storage holds them): they feed only residual norms and FP32 corrections
+  float* Tv32 = reinterpret_cast<float*>(w.Tv.p);
+  float* Uv32 = Tv32 + static_cast<long>(K) * nov;
+  float* PT32 = reinterpret_cast<float*>(w.PT.p);
+  float* MU32 = PT32 + static_cast<long>(K) * nov;
   w.W.ensure(static_cast<size_t>(std::max(ncand_max, opt.guess ? opt.nguess : 0)) * nov);
   w.scratch.ensure(static_cast<size_t>(ps) * q_max * nov);
   w.G.ensure(static_cast<size_t>(ps) * Smax * Smax);
@@ -721,9 +728,9 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       itimer.mark(kDavRitz);
       // [T; U] in one pass over V (t and u are adjacent coefficient columns)
       if (lb) {
-        comb(st, ps * K, nov, S, 1.0, tco, Smax, w.V32.p, nov, 0.0, w.Tv.p, nov);
-        comb(st, K, nov, S, 1.0, tco, Smax, w.SP32.p, ldp, 0.0, w.PT.p, nov);
-        if (tdhf) comb(st, K, nov, S, 1.0, uco, Smax, w.SP32.p + nov, ldp, 0.0, MU, nov);
+        comb(st, ps * K, nov, S, 1.0, tco, Smax, w.V32.p, nov, 0.0, Tv32, nov);
+        comb(st, K, nov, S, 1.0, tco, Smax, w.SP32.p, ldp, 0.0, PT32, nov);
+        if (tdhf) comb(st, K, nov, S, 1.0, uco, Smax, w.SP32.p + nov, ldp, 0.0, MU32, nov);
       } else {
         dgemm(st, false, false, ps * K, static_cast<int>(nov), S, 1.0, tco, Smax, 0, w.V.p, nov, 0, 0.0, w.Tv.p, nov,
               0, 1, nullptr);
@@ -734,8 +741,12 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
                 0, 1, nullptr);
       }
       // 5. residual norms
-      hipLaunchKernelGGL(residual_norm_kernel, dim3(nbres, K), dim3(256), 0, st, nov, tdhf ? 1 : 0, om, w.Tv.p, Uv,
-                         w.PT.p, MU, w.part.p);
+      if (lb)
+        hipLaunchKernelGGL(residual_norm_kernel<float>, dim3(nbres, K), dim3(256), 0, st, nov, tdhf ? 1 : 0, om, Tv32,
+                           Uv32, PT32, MU32, w.part.p);
+      else
+        hipLaunchKernelGGL(residual_norm_kernel<double>, dim3(nbres, K), dim3(256), 0, st, nov, tdhf ? 1 : 0, om,
+                           w.Tv.p, Uv, w.PT.p, MU, w.part.p);
       hipLaunchKernelGGL(reduce_rows_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, nbres, w.part.p, w.rn.p);
       SEQX_LAUNCH_CHECK();
       itimer.mark(kDavCheck);
@@ -838,10 +849,10 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       // FP32 correction rows beside an FP32 basis (W's storage holds twice as many)
       float* W32 = reinterpret_cast<float*>(w.W.p);
       if (lb)
-        hipLaunchKernelGGL(precond_kernel<float>, dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov, tdhf ? 1 : 0,
-                           w.sel.p, om, w.d.p, w.Tv.p, Uv, w.PT.p, MU, W32);
+        hipLaunchKernelGGL((precond_kernel<float, float>), dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov,
+                           tdhf ? 1 : 0, w.sel.p, om, w.d.p, Tv32, Uv32, PT32, MU32, W32);
       else
-        hipLaunchKernelGGL(precond_kernel<double>, dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov,
+        hipLaunchKernelGGL((precond_kernel<double, double>), dim3(ceil_div(nov, 256), nsel), dim3(256), 0, st, nov,
                            tdhf ? 1 : 0, w.sel.p, om, w.d.p, w.Tv.p, Uv, w.PT.p, MU, w.W.p);
       SEQX_LAUNCH_CHECK();
       const int nc = tdhf ? 2 * nsel : nsel;
