@@ -135,6 +135,16 @@ __global__ void residual_norm_kernel(long nov, int tdhf, const double* __restric
   if (threadIdx.x == 0) part[static_cast<long>(j) * gridDim.x + blockIdx.x] = red[0];
 }
 
+// the words the host checks after each iteration, beside the residual norms:
+// lowest eigenvalue of the projected problem, eigh and potrf info
+__global__ void check_words_kernel(const double* __restrict__ w2, const int* __restrict__ info, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    out[0] = w2[0];
+    out[1] = static_cast<double>(info[0]);
+    out[2] = static_cast<double>(info[1]);
+  }
+}
+
 __global__ void reduce_rows_kernel(int K, int nb, const double* __restrict__ part, double* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= K) return;
@@ -499,7 +509,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
   }
   w.ws.ensure(std::max<size_t>(dots_workspace(2 * Smax, std::max(Smax, opt.nlock), nov), 4096));
   w.d.ensure(nov);
-  w.rn.ensure(2 * K);
+  w.rn.ensure(2 * K + 3);  // residual norms, omega, then the check words (lowest eigenvalue, eigh / potrf info)
   const int nbres = static_cast<int>(std::min<long>(256, ceil_div(nov, 256)));
   w.part.ensure(static_cast<size_t>(K) * nbres);
   w.idx.ensure(std::max(ng, 1));
@@ -541,7 +551,7 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
     comb(st, nv, nov, opt.nlock, opt.shift, w.lc.p, opt.nlock, opt.lock_u, nov, 1.0, sp, ldp);
   };
 
-  std::vector<double> h_om(K), h_rn(K);
+  std::vector<double> h_om(K), h_rn(K), h_chk(2 * K + 3);
   std::vector<int> sel;
   hipEvent_t e0, e1;
   IterTimer itimer(st);
@@ -750,13 +760,16 @@ DavResult davidson(DeviceMolecule& m, const DavOptions& opt, DenseSolver& ds, Da
       hipLaunchKernelGGL(reduce_rows_kernel, dim3(ceil_div(K, 64)), dim3(64), 0, st, K, nbres, w.part.p, w.rn.p);
       SEQX_LAUNCH_CHECK();
       itimer.mark(kDavCheck);
-      d2h(h_rn.data(), w.rn.p, K, st);
-      d2h(h_om.data(), om, K, st);
-      double h_w2min = 0.0;  // lowest eigenvalue of the projected problem (TDHF: omega^2)
-      d2h(&h_w2min, w.w2.p, 1, st);
-      int h_info[2] = {0, 0};  // eigh, potrf
-      ds.info_async(h_info);
+      // one copy to the host: residual norms, omega, the lowest eigenvalue of
+      // the projected problem (TDHF: omega^2) and the eigh / potrf info words
+      hipLaunchKernelGGL(check_words_kernel, dim3(1), dim3(64), 0, st, w.w2.p, ds.info_device(), w.rn.p + 2 * K);
+      SEQX_LAUNCH_CHECK();
+      d2h(h_chk.data(), w.rn.p, 2 * K + 3, st);
       SEQX_HIP(hipStreamSynchronize(st));
+      std::copy(h_chk.begin(), h_chk.begin() + K, h_rn.begin());
+      std::copy(h_chk.begin() + K, h_chk.begin() + 2 * K, h_om.begin());
+      const double h_w2min = h_chk[2 * K];
+      const int h_info[2] = {static_cast<int>(h_chk[2 * K + 1]), static_cast<int>(h_chk[2 * K + 2])};
       float ms = 0.f;
       SEQX_HIP(hipEventElapsedTime(&ms, e0, e1));
       res.t_sigma_ms += ms;

@@ -40,6 +40,8 @@ class DenseSolver {
   // enqueue the copy of both info words (eigh, potrf) to host memory on the
   // solver's stream, for a caller that synchronises the stream anyway
   void info_async(int* host2);
+  // the device info words (eigh, potrf), for kernels that gather them
+  const int* info_device() const { return info_.p; }
 
  private:
   rocblas_handle h_ = nullptr;
