@@ -85,9 +85,10 @@ __device__ inline void jacobi_lds(int n, JacobiLds& L, bool q_given = false) {
           c = 1.0 / sqrt(t * t + 1.0);
           s = t * c;
           L.nact = stamp;  // benign race: every writer stores the same value
-        } else {
-          q = p;  // identity rotation of row / column p onto itself (p is in no other pair)
-        }
+        } else if (q >= n) {
+          q = p;  // the spare index of odd n: identity rotation of p onto itself (p is in no other pair)
+        }  // a pair left alone keeps both indices with the identity rotation, so
+           // that every index still belongs to one pair of the round
         L.p[k] = p;
         L.q[k] = q;
         L.c[k] = c;
@@ -95,53 +96,32 @@ __device__ inline void jacobi_lds(int n, JacobiLds& L, bool q_given = false) {
       }
       __syncthreads();
       if (L.nact != stamp) continue;  // uniform: nothing to rotate in this round
-      // The pairs of a round are disjoint, so each wavefront first reads the
-      // pair indices, rotations and operands of all its pairs, then writes:
-      // no read waits on an earlier write, and no access is predicated (a
-      // slot without a pair works on the spare LDS row kJacobiMax - 1, which
-      // exists only when n < kJacobiMax - 1, with the identity rotation).
-      constexpr int KW = (kJacobiMax / 2 + NT / 64 - 1) / (NT / 64);  // pairs per wavefront
-      int pk[KW], qk[KW];
-      double ck[KW], sk[KW];
-#pragma unroll
-      for (int j = 0; j < KW; ++j) {
-        const int k = wv + (NT / 64) * j;
-        const bool has = k < half;
-        pk[j] = has ? L.p[k] : kJacobiMax - 1;
-        qk[j] = has ? L.q[k] : kJacobiMax - 1;
-        ck[j] = has ? L.c[k] : 1.0;
-        sk[j] = has ? L.s[k] : 0.0;
+      // The pairs of a round are disjoint, so A' = J^T A J splits into 2 x 2
+      // blocks (rows of pair k1, columns of pair k2), each formed from its own
+      // four elements, and Q' = Q J into pairs of columns: one pass and one
+      // barrier.  The pairs cover every index once (the spare slot of odd n
+      // as q = p, which reads and writes one element several times with the
+      // same value).
+      for (int it = threadIdx.x; it < half * half; it += NT) {
+        const int k1 = it / half, k2 = it - k1 * half;
+        const int p1 = L.p[k1], q1 = L.q[k1], p2 = L.p[k2], q2 = L.q[k2];
+        const double c1 = L.c[k1], s1 = L.s[k1], c2 = L.c[k2], s2 = L.s[k2];
+        const double app = L.A[p1][p2], apq = L.A[p1][q2], aqp = L.A[q1][p2], aqq = L.A[q1][q2];
+        // rows p1, q1 first (columns p2 and q2), then columns p2, q2
+        const double bpp = c1 * app - s1 * aqp, bqp = s1 * app + c1 * aqp;
+        const double bpq = c1 * apq - s1 * aqq, bqq = s1 * apq + c1 * aqq;
+        L.A[p1][p2] = c2 * bpp - s2 * bpq;
+        L.A[p1][q2] = s2 * bpp + c2 * bpq;
+        L.A[q1][p2] = c2 * bqp - s2 * bqq;
+        L.A[q1][q2] = s2 * bqp + c2 * bqq;
       }
-      if (lane < n) {  // rows p, q: lane = column
-        double ap[KW], aq[KW];
-#pragma unroll
-        for (int j = 0; j < KW; ++j) {
-          ap[j] = L.A[pk[j]][lane];
-          aq[j] = L.A[qk[j]][lane];
-        }
-#pragma unroll
-        for (int j = 0; j < KW; ++j) {
-          L.A[pk[j]][lane] = ck[j] * ap[j] - sk[j] * aq[j];
-          L.A[qk[j]][lane] = sk[j] * ap[j] + ck[j] * aq[j];
-        }
-      }
-      __syncthreads();
-      if (lane < n) {  // columns p, q of A and Q: lane = row
-        double ap[KW], aq[KW], vp[KW], vq[KW];
-#pragma unroll
-        for (int j = 0; j < KW; ++j) {
-          ap[j] = L.A[lane][pk[j]];
-          aq[j] = L.A[lane][qk[j]];
-          vp[j] = L.Q[lane][pk[j]];
-          vq[j] = L.Q[lane][qk[j]];
-        }
-#pragma unroll
-        for (int j = 0; j < KW; ++j) {
-          L.A[lane][pk[j]] = ck[j] * ap[j] - sk[j] * aq[j];
-          L.A[lane][qk[j]] = sk[j] * ap[j] + ck[j] * aq[j];
-          L.Q[lane][pk[j]] = ck[j] * vp[j] - sk[j] * vq[j];
-          L.Q[lane][qk[j]] = sk[j] * vp[j] + ck[j] * vq[j];
-        }
+      for (int it = threadIdx.x; it < n * half; it += NT) {
+        const int row = it / half, k2 = it - row * half;
+        const int p2 = L.p[k2], q2 = L.q[k2];
+        const double c2 = L.c[k2], s2 = L.s[k2];
+        const double vp = L.Q[row][p2], vq = L.Q[row][q2];
+        L.Q[row][p2] = c2 * vp - s2 * vq;
+        L.Q[row][q2] = s2 * vp + c2 * vq;
       }
       __syncthreads();
     }
