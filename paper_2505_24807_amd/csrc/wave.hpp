@@ -39,10 +39,14 @@ __device__ __forceinline__ double lane_value(double x, int src) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
-// the value of lane ^ M (ds_swizzle in bit mode for M < 32, which stays
-// within 32-lane halves; ds_bpermute for M = 32)
+// the value of lane ^ M: DPP moves inside 16-lane rows for M = 1, 2 (quad
+// permutes) and 8 (row rotation by 8), ds_swizzle in bit mode for M = 4, 16
+// (within 32-lane halves), ds_bpermute for M = 32
 template <int M>
 __device__ __forceinline__ double xor_shuffle(double x) {
+  if constexpr (M == 1) return dpp_move<0xb1>(x);   // quad_perm [1,0,3,2]
+  if constexpr (M == 2) return dpp_move<0x4e>(x);   // quad_perm [2,3,0,1]
+  if constexpr (M == 8) return dpp_move<0x128>(x);  // row_ror:8
   const long long b = __double_as_longlong(x);
   int lo = static_cast<int>(b), hi = static_cast<int>(b >> 32);
   if constexpr (M < 32) {
@@ -71,13 +75,14 @@ __device__ __forceinline__ void butterfly_level(double* x) {
 }
 
 // sums of 8 values per lane over the 64 lanes, in a fixed order: returns in
-// lane L the total of x[(L >> 3) & 7] (10 exchanges instead of 8 x 6)
+// lane L the total of x[(L >> 3) & 7] (10 exchanges instead of 8 x 6; the
+// last four are DPP moves, the 8-lane sums pairing lane i with 7 - i first)
 __device__ __forceinline__ double wave_sum8x64(double (&x)[8]) {
   butterfly_level<32, 4>(x);
   butterfly_level<16, 2>(x);
   butterfly_level<8, 1>(x);
   double s = x[0];
-  s += xor_shuffle<4>(s);
+  s += dpp_move<0x141>(s);  // row_half_mirror
   s += xor_shuffle<2>(s);
   s += xor_shuffle<1>(s);
   return s;
