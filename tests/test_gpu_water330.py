@@ -50,3 +50,10 @@ def test_water330_tdhf_matches_oracle(job, precision):
     assert (n, o, v) == (1980, 1320, 660)
     for k in range(10):
         assert abs(np.sum(lib.X[k] ** 2) - np.sum(lib.Y[k] ** 2) - 1.0) < 1e-8
+    st = job.stats()
+    if precision == seqx.BF16X3:
+        # split bfloat16, then FP32 from a later iteration, then FP64
+        assert st.n_sigma_bf16x3 > 0 and 1 <= st.fp32_iteration < st.refine_iteration
+        assert st.n_sigma_bf16x3 + st.n_sigma_fp64 < st.n_sigma
+    elif precision == seqx.FP32:
+        assert st.n_sigma_bf16x3 == 0 and st.fp32_iteration == 0 and st.refine_iteration >= 1
