@@ -566,8 +566,14 @@ __device__ __forceinline__ void split_pair(float x, float y, unsigned& hi, unsig
 constexpr int kBK3 = 32;           // k per panel
 constexpr int kLd3 = kBK3 + 8;     // bf16 per LDS row (k contiguous), padded; rows stay 16-byte aligned
 
+// element pairs per thread of a 32-deep panel W rows (or columns) wide
+template <int W>
+constexpr int kNP3 = W * kBK3 / 2 / 256;
+
+// B planes for tiles BN columns wide (128, or 96 where that pads N less)
+template <int BN>
 struct Lds3 {
-  unsigned short ahi[2][kBM][kLd3], alo[2][kBM][kLd3], bhi[2][kBN][kLd3], blo[2][kBN][kLd3];
+  unsigned short ahi[2][kBM][kLd3], alo[2][kBM][kLd3], bhi[2][BN][kLd3], blo[2][BN][kLd3];
 };
 
 // Which elements a thread loads.  An operand whose rows in memory run along k
@@ -575,24 +581,24 @@ struct Lds3 {
 // row / column; one whose rows run along the tile index (A transposed, B not)
 // as 2 x 2 blocks: pairs 2q and 2q + 1 hold index i, i + 1 at k and k + 1.
 // Either way each LDS word written holds two consecutive k of one row.
-// Element pair j of thread tid: tile index i, panel column k (first element).
-template <bool KM>
+// Element pair j of thread tid in a tile W wide: tile index i, panel column k (first element).
+template <bool KM, int W>
 __device__ __forceinline__ void pair_pos3(int tid, int j, int& i, int& k) {
-  constexpr int HK = kBK3 / 2, HM = kBM / 2;
+  constexpr int HK = kBK3 / 2, HW = W / 2;
   if (!KM) {
     const int c = tid + 256 * j;
     i = c / HK;
     k = (c % HK) * 2;
   } else {
     const int c = tid + 256 * (j >> 1);
-    k = 2 * (c / HM) + (j & 1);
-    i = (c % HM) * 2;
+    k = 2 * (c / HW) + (j & 1);
+    i = (c % HW) * 2;
   }
 }
 
 // Panel loads, clamped at the edges like panel_load_edge: element (i, k) of
 // A (rows i, KA: A[k lda + i] when transposed) and of B (columns i).
-template <bool TA, bool TB>
+template <bool TA, bool TB, int BN>
 __device__ __forceinline__ void panel_load_edge3(const float* __restrict__ A, long lda, const float* __restrict__ B,
                                                  long ldb, int M, int N, int K, int m0, int n0, int k0, int tid,
                                                  f2* ra, f2* rb) {
@@ -607,25 +613,29 @@ __device__ __forceinline__ void panel_load_edge3(const float* __restrict__ A, lo
     return gk < K ? v : 0.0f;
   };
 #pragma unroll
-  for (int j = 0; j < Panel<float>::NP; ++j) {
+  for (int j = 0; j < kNP3<kBM>; ++j) {
     int i, k;
-    pair_pos3<TA>(tid, j, i, k);
+    pair_pos3<TA, kBM>(tid, j, i, k);
     ra[j].x = ld_a(m0 + i, k0 + k);
     ra[j].y = TA ? ld_a(m0 + i + 1, k0 + k) : ld_a(m0 + i, k0 + k + 1);
-    pair_pos3<!TB>(tid, j, i, k);
+  }
+#pragma unroll
+  for (int j = 0; j < kNP3<BN>; ++j) {
+    int i, k;
+    pair_pos3<!TB, BN>(tid, j, i, k);
     rb[j].x = ld_b(n0 + i, k0 + k);
     rb[j].y = TB ? ld_b(n0 + i, k0 + k + 1) : ld_b(n0 + i + 1, k0 + k);
   }
 }
 
-template <bool KM>
+template <bool KM, int W>
 __device__ __forceinline__ void store_plane3(unsigned short (*hi)[kLd3], unsigned short (*lo)[kLd3], int tid,
                                              const f2* r) {
   if (!KM) {
 #pragma unroll
-    for (int j = 0; j < Panel<float>::NP; ++j) {
+    for (int j = 0; j < kNP3<W>; ++j) {
       int i, k;
-      pair_pos3<false>(tid, j, i, k);
+      pair_pos3<false, W>(tid, j, i, k);
       unsigned h, l;
       split_pair(r[j].x, r[j].y, h, l);
       *reinterpret_cast<unsigned*>(&hi[i][k]) = h;
@@ -633,9 +643,9 @@ __device__ __forceinline__ void store_plane3(unsigned short (*hi)[kLd3], unsigne
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < Panel<float>::NP / 2; ++q) {
+    for (int q = 0; q < kNP3<W> / 2; ++q) {
       int i, k;
-      pair_pos3<true>(tid, 2 * q, i, k);
+      pair_pos3<true, W>(tid, 2 * q, i, k);
       unsigned h, l;
       split_pair(r[2 * q].x, r[2 * q + 1].x, h, l);  // index i at k, k + 1
       *reinterpret_cast<unsigned*>(&hi[i][k]) = h;
@@ -647,65 +657,71 @@ __device__ __forceinline__ void store_plane3(unsigned short (*hi)[kLd3], unsigne
   }
 }
 
-template <bool TA, bool TB>
-__device__ __forceinline__ void panel_store3(Lds3& L, int buf, int tid, const f2* ra, const f2* rb) {
-  store_plane3<TA>(L.ahi[buf], L.alo[buf], tid, ra);
-  store_plane3<!TB>(L.bhi[buf], L.blo[buf], tid, rb);
+template <bool TA, bool TB, int BN>
+__device__ __forceinline__ void panel_store3(Lds3<BN>& L, int buf, int tid, const f2* ra, const f2* rb) {
+  store_plane3<TA, kBM>(L.ahi[buf], L.alo[buf], tid, ra);
+  store_plane3<!TB, BN>(L.bhi[buf], L.blo[buf], tid, rb);
 }
 
 // one panel of 32 k: lane l reads k 8 (l / 16) .. + 7 of row l % 16 of each tile
-__device__ __forceinline__ void panel_mfma3(const Lds3& L, int buf, int lane, int wm, int wn, f4 (*acc)[4]) {
+template <int BN>
+__device__ __forceinline__ void panel_mfma3(const Lds3<BN>& L, int buf, int lane, int wm, int wn,
+                                            f4 (*acc)[BN / 32]) {
+  constexpr int TN = BN / 32;
   const int r = lane & 15, k8 = 8 * (lane >> 4);
-  bf8 ah[4], al[4], bh[4], bl[4];
+  bf8 ah[4], al[4], bh[TN], bl[TN];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     ah[i] = *reinterpret_cast<const bf8*>(&L.ahi[buf][wm + i * 16 + r][k8]);
     al[i] = *reinterpret_cast<const bf8*>(&L.alo[buf][wm + i * 16 + r][k8]);
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < TN; ++j) {
     bh[j] = *reinterpret_cast<const bf8*>(&L.bhi[buf][wn + j * 16 + r][k8]);
     bl[j] = *reinterpret_cast<const bf8*>(&L.blo[buf][wn + j * 16 + r][k8]);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < TN; ++j) {
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
     }
 }
 
-template <class To, bool TA, bool TB, bool EPI, int EM>
+template <class To, bool TA, bool TB, bool EPI, int EM, int BN>
 __device__ __forceinline__ void tile128x3(int M, int N, int K, double alpha, const float* __restrict__ A, long lda,
                                           const float* __restrict__ B, long ldb, double beta, To* __restrict__ C,
-                                          long ldc, long b, const SigmaEpilogue& ep, int m0, int n0, Lds3& L) {
+                                          long ldc, long b, const SigmaEpilogue& ep, int m0, int n0, Lds3<BN>& L) {
   typedef f2 P2;
-  constexpr int BK = kBK3;
+  constexpr int BK = kBK3, TN = BN / 32, NPA = kNP3<kBM>, NPB = kNP3<BN>;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  f4 acc[4][4];
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * (BN / 2);
+  f4 acc[4][TN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0, 0, 0, 0};
   // K as a head panel of K % BK columns (zero filled), then full panels; two
   // register sets prefetch two panels ahead (as in the FP32 kernel)
-  P2 ra0[Panel<float>::NP], rb0[Panel<float>::NP], ra1[Panel<float>::NP], rb1[Panel<float>::NP];
+  P2 ra0[NPA], rb0[NPB], ra1[NPA], rb1[NPB];
   const int kr = K % BK;
   const int npan = K / BK + (kr ? 1 : 0);
   const int kshift = kr ? kr - BK : 0;
   const int im = M - 1 - m0, in = N - 1 - n0;
-  unsigned oa[Panel<float>::NP], ob[Panel<float>::NP];
+  unsigned oa[NPA], ob[NPB];
 #pragma unroll
-  for (int j = 0; j < Panel<float>::NP; ++j) {
+  for (int j = 0; j < NPA; ++j) {
     int i, kk;
-    pair_pos3<TA>(tid, j, i, kk);
+    pair_pos3<TA, kBM>(tid, j, i, kk);
     if (EM == 1) i = TA ? min(i, im - 1) : min(i, im);
     oa[j] = static_cast<unsigned>(TA ? kk * lda + i : i * lda + kk) * sizeof(float);
+  }
+#pragma unroll
+  for (int j = 0; j < NPB; ++j) {
     int jj, kb;
-    pair_pos3<!TB>(tid, j, jj, kb);
+    pair_pos3<!TB, BN>(tid, j, jj, kb);
     if (EM == 1) jj = TB ? min(jj, in) : min(jj, in - 1);
     ob[j] = static_cast<unsigned>(TB ? jj * ldb + kb : kb * ldb + jj) * sizeof(float);
   }
@@ -714,35 +730,35 @@ __device__ __forceinline__ void tile128x3(int M, int N, int K, double alpha, con
   auto load_full = [&](int p, P2* ra, P2* rb) {
     const int k0 = p * BK + kshift;
     if (EM < 2)
-      panel_load_fast<float, kBN>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(float), br,
-                             static_cast<unsigned>(TB ? k0 : k0 * ldb) * sizeof(float), oa, ob, ra, rb);
+      panel_load_fast<float, BN>(ar, static_cast<unsigned>(TA ? k0 * lda : k0) * sizeof(float), br,
+                                 static_cast<unsigned>(TB ? k0 : k0 * ldb) * sizeof(float), oa, ob, ra, rb);
     else
-      panel_load_edge3<TA, TB>(A, lda, B, ldb, M, N, K, m0, n0, k0, tid, ra, rb);
+      panel_load_edge3<TA, TB, BN>(A, lda, B, ldb, M, N, K, m0, n0, k0, tid, ra, rb);
   };
-  if (kr) panel_load_edge3<TA, TB>(A, lda, B, ldb, M, N, kr, m0, n0, 0, tid, ra0, rb0);
+  if (kr) panel_load_edge3<TA, TB, BN>(A, lda, B, ldb, M, N, kr, m0, n0, 0, tid, ra0, rb0);
   else load_full(0, ra0, rb0);
   load_full(min(1, npan - 1), ra1, rb1);
-  panel_store3<TA, TB>(L, 0, tid, ra0, rb0);
+  panel_store3<TA, TB, BN>(L, 0, tid, ra0, rb0);
   __syncthreads();
   int kt = 0;
   for (; kt + 1 < npan; kt += 2) {
     load_full(min(kt + 2, npan - 1), ra0, rb0);
     __builtin_amdgcn_sched_barrier(0);
-    panel_mfma3(L, 0, lane, wm, wn, acc);
-    panel_store3<TA, TB>(L, 1, tid, ra1, rb1);
+    panel_mfma3<BN>(L, 0, lane, wm, wn, acc);
+    panel_store3<TA, TB, BN>(L, 1, tid, ra1, rb1);
     __syncthreads();
     load_full(min(kt + 3, npan - 1), ra1, rb1);
     __builtin_amdgcn_sched_barrier(0);
-    panel_mfma3(L, 1, lane, wm, wn, acc);
-    if (kt + 2 < npan) panel_store3<TA, TB>(L, 0, tid, ra0, rb0);
+    panel_mfma3<BN>(L, 1, lane, wm, wn, acc);
+    if (kt + 2 < npan) panel_store3<TA, TB, BN>(L, 0, tid, ra0, rb0);
     __syncthreads();
   }
-  if (kt < npan) panel_mfma3(L, 0, lane, wm, wn, acc);
+  if (kt < npan) panel_mfma3<BN>(L, 0, lane, wm, wn, acc);
   constexpr bool EDGE = EM != 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
@@ -751,27 +767,27 @@ __device__ __forceinline__ void tile128x3(int M, int N, int K, double alpha, con
       }
 }
 
-template <class To, bool TA, bool TB, bool EPI>
+template <class To, bool TA, bool TB, bool EPI, int BN>
 __global__ void __launch_bounds__(256) gemm128x3_kernel(int M, int N, int K, double alpha,
                                                         const float* __restrict__ A, long lda, long sA,
                                                         const float* __restrict__ B, long ldb, long sB, double beta,
                                                         To* __restrict__ C, long ldc, long sC, SigmaEpilogue ep) {
-  __shared__ Lds3 L;
+  __shared__ Lds3<BN> L;
   const long b = blockIdx.z;
   const int nbx = gridDim.x, nb = gridDim.x * gridDim.y, nfull = nb - nb % 8;
   int bid = blockIdx.y * nbx + blockIdx.x;
   if (bid < nfull) bid = (bid % 8) * (nfull / 8) + bid / 8;
-  const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * kBN;
+  const int m0 = (bid / nbx) * kBM, n0 = (bid % nbx) * BN;
   const bool keven = (K & 1) == 0;
-  if (m0 + kBM <= M && n0 + kBN <= N && keven)
-    tile128x3<To, TA, TB, EPI, 0>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
-                                  n0, L);
+  if (m0 + kBM <= M && n0 + BN <= N && keven)
+    tile128x3<To, TA, TB, EPI, 0, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
+                                      m0, n0, L);
   else if (keven && (!TA || (M & 1) == 0) && (TB || (N & 1) == 0))
-    tile128x3<To, TA, TB, EPI, 1>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
-                                  n0, L);
+    tile128x3<To, TA, TB, EPI, 1, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
+                                      m0, n0, L);
   else
-    tile128x3<To, TA, TB, EPI, 2>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep, m0,
-                                  n0, L);
+    tile128x3<To, TA, TB, EPI, 2, BN>(M, N, K, alpha, A + b * sA, lda, B + b * sB, ldb, beta, C + b * sC, ldc, b, ep,
+                                      m0, n0, L);
 }
 
 template <class To>
@@ -789,20 +805,28 @@ void gemm_x3(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha
   }
   SigmaEpilogue ep;
   if (epi) ep = *epi;
-  dim3 grid(ceil_div(N, kBN), ceil_div(M, kBM), batch);
-#define SEQX_X3(TA_, TB_)                                                                                        \
-  do {                                                                                                          \
-    if (epi)                                                                                                    \
-      hipLaunchKernelGGL((gemm128x3_kernel<To, TA_, TB_, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, \
-                         sA, B, ldb, sB, beta, C, ldc, sC, ep);                                                 \
-    else                                                                                                        \
-      hipLaunchKernelGGL((gemm128x3_kernel<To, TA_, TB_, false>), grid, dim3(256), 0, st, M, N, K, alpha, A,    \
-                         lda, sA, B, ldb, sB, beta, C, ldc, sC, ep);                                            \
+  // 96-wide tiles where they pad N less (v = 660: 672 columns instead of 768)
+  const bool w96 = tile_width(N) == 96;
+  dim3 grid(ceil_div(N, w96 ? 96 : kBN), ceil_div(M, kBM), batch);
+#define SEQX_X3(TA_, TB_, BN_)                                                                                     \
+  do {                                                                                                            \
+    if (epi)                                                                                                      \
+      hipLaunchKernelGGL((gemm128x3_kernel<To, TA_, TB_, true, BN_>), grid, dim3(256), 0, st, M, N, K, alpha, A,   \
+                         lda, sA, B, ldb, sB, beta, C, ldc, sC, ep);                                              \
+    else                                                                                                          \
+      hipLaunchKernelGGL((gemm128x3_kernel<To, TA_, TB_, false, BN_>), grid, dim3(256), 0, st, M, N, K, alpha, A,  \
+                         lda, sA, B, ldb, sB, beta, C, ldc, sC, ep);                                              \
   } while (0)
-  if (!ta && !tb) SEQX_X3(false, false);
-  else if (!ta && tb) SEQX_X3(false, true);
-  else if (ta && !tb) SEQX_X3(true, false);
-  else SEQX_X3(true, true);
+#define SEQX_X3_BN(BN_)                   \
+  do {                                    \
+    if (!ta && !tb) SEQX_X3(false, false, BN_); \
+    else if (!ta && tb) SEQX_X3(false, true, BN_); \
+    else if (ta && !tb) SEQX_X3(true, false, BN_); \
+    else SEQX_X3(true, true, BN_);        \
+  } while (0)
+  if (w96) SEQX_X3_BN(96);
+  else SEQX_X3_BN(kBN);
+#undef SEQX_X3_BN
 #undef SEQX_X3
   SEQX_LAUNCH_CHECK();
 }
